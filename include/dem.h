@@ -1,0 +1,269 @@
+/*
+ * dem.h -- C ABI of the MI355X (gfx950) multiresolution contact-detection
+ * library (libdem.so).
+ *
+ * The operations follow Noble & Weinzierl, "A multiresolution Discrete
+ * Element Method for triangulated objects with implicit time stepping"
+ * (arXiv 2105.12415):
+ *
+ *   - particles are closed triangulated surfaces, each surrounded by an
+ *     epsilon environment (Section 2, Definition "contact point");
+ *   - two triangles are in contact iff their epsilon environments overlap,
+ *     i.e. iff their distance d <= eps_i + eps_j; the contact point lies on
+ *     the shortest path between the triangles with normal n(c) pointing to a
+ *     triangle (Section 2, minimisation problem for x(c));
+ *   - findContacts over a pair of particles (Algorithm 2) is answered either
+ *     over all fine triangle pairs (DEM_MODE_FLAT) or by descending a
+ *     surrogate tree that prunes the children of surrogate pairs whose
+ *     epsilon environments do not overlap (Algorithm 5, Section 5.1);
+ *   - every triangle pair is evaluated with the batched, fixed-iteration,
+ *     penalty-regularised closest-point iteration (Section 3, iterative
+ *     functional and its modified Newton update; Algorithm 4), and pairs
+ *     the iteration cannot settle ("not terminated") fall back to the exact
+ *     comparison-based distance (Section 3, direct distance calculation);
+ *   - surrogate trees are built offline (Section 4, surrogate tree
+ *     definition; Appendix B, Algorithm 7) with the smallest epsilon that
+ *     keeps each surrogate conservative (Section 4, Definition
+ *     "conservative").
+ *
+ * Conventions for every call:
+ *   - All pointers documented "device" are caller-owned device memory
+ *     (e.g. torch tensors); the library allocates no device memory and keeps
+ *     no state between calls.  Host pointers are read during the call only.
+ *   - Calls that take a stream enqueue work on it and return without
+ *     synchronising; they contain no host-device copies or allocations, so
+ *     they can be captured into a HIP graph.  Errors the host can see
+ *     (bad arguments, undersized workspace, launch failures) are returned
+ *     as dem_status; conditions only the device can see are OR-ed into
+ *     *dev_status (DEM_DEV_* bits) for the caller to read after the stream
+ *     has completed.
+ *   - Coordinates are float (DEM_F32) or double (DEM_F64) as selected by
+ *     dem_scene.precision; all floating-point device buffers of a call use
+ *     that type unless stated otherwise.
+ */
+#ifndef DEM_H_
+#define DEM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DEM_OK = 0,
+  DEM_ERR_ARG = -1,               /* invalid argument (null pointer, size, layout) */
+  DEM_ERR_CAPACITY = -2,          /* workspace smaller than dem_workspace_bytes() */
+  DEM_ERR_HIP = -3,               /* a HIP runtime call or kernel launch failed */
+  DEM_ERR_NOT_CONSERVATIVE = -4,  /* hierarchy input violates the surrogate-tree rules */
+  DEM_ERR_OOM = -5                /* host allocation failed (dem_build_hierarchy) */
+} dem_status;
+
+typedef enum { DEM_F32 = 0, DEM_F64 = 1 } dem_precision;
+typedef enum { DEM_MODE_FLAT = 0, DEM_MODE_HIER = 1 } dem_mode;
+
+/* Bits OR-ed into *dev_status by the device. */
+#define DEM_DEV_CONTACT_OVERFLOW 0x1u /* more contacts than dem_contacts.capacity */
+#define DEM_DEV_QUEUE_OVERFLOW 0x2u   /* a level work queue exceeded queue_capacity */
+#define DEM_DEV_NEAR_OVERFLOW 0x4u    /* near-pair list exceeded near_capacity */
+#define DEM_DEV_NONFINITE 0x8u        /* a non-finite coordinate or distance was met */
+
+#define DEM_MAX_LEVELS 32
+
+typedef void* dem_stream_t; /* a hipStream_t (0 = the null stream) */
+
+/* ------------------------------------------------------------------ hierarchy */
+
+typedef struct {
+  /* Upper bound on |coordinate| the mesh will take in the world frame.  Sets
+   * an absolute slack of coord_scale * 2^-19 on every stored surrogate
+   * epsilon, which covers the FP32 rounding of vertices that are rigidly
+   * moved after the build.  0 = use the largest |coordinate| of verts. */
+  double coord_scale;
+  /* Relative slack added to surrogate epsilons (>= 0; default 1e-6). */
+  double rel_slack;
+} dem_build_opts;
+
+typedef struct {
+  int32_t n_tris;        /* triangles of all levels */
+  int32_t n_levels;
+  int32_t* tri_verts;    /* [n_tris][3] vertex ids (as given) */
+  int32_t* child_begin;  /* [n_tris] id of the first child (0 if none) */
+  int32_t* child_count;  /* [n_tris] number of children; 0 marks a fine triangle */
+  int32_t* level_begin;  /* [n_levels + 1] first triangle id of each level */
+  double* eps;           /* [n_tris] epsilon in FP64: eps0 for fine triangles,
+                            eps0 + max deviation of the fine descendants for surrogates */
+  float* eps_f32;        /* [n_tris] eps with slack, rounded up to float */
+  double* eps_f64;       /* [n_tris] eps with slack (double) */
+  int32_t root_begin, root_count; /* level 0 = the coarsest model (tree root) */
+  int32_t fine_begin, fine_count; /* last level = the particle triangulation */
+  double max_dev;        /* largest surrogate deviation (eps - eps0) */
+} dem_hierarchy;
+
+/*
+ * dem_build_hierarchy -- offline, host, FP64 (Section 4, surrogate tree
+ * definition; Appendix B, Algorithm 7 "assign the smallest epsilon such that
+ * the surrogate is conservative").
+ *
+ * verts     [n_verts][3] host, FP64: vertex positions of one particle (any
+ *           frame; distances are invariant under the rigid motions applied
+ *           later).
+ * tris      [n_tris][3] host: vertex ids of all triangles, levels
+ *           concatenated from the coarsest (level 0, the root model) to the
+ *           finest (the particle triangulation).
+ * parent    [n_tris] host: for a triangle of level l >= 1 the id (into
+ *           tris) of its parent in level l-1; ignored for level 0.  Children
+ *           of one parent must be contiguous and levels sorted by parent.
+ * level_sizes [n_levels] host: triangles per level (sum = n_tris).
+ * eps0      epsilon of the fine triangles (uniform per particle, Section 2).
+ * opts      may be NULL (defaults).
+ * out       filled with library-allocated host arrays; release with
+ *           dem_hierarchy_free.  Every triangle of levels < n_levels-1 must
+ *           have children and the last level must have none.
+ *
+ * Each surrogate gets eps = eps0 + max over the vertices of its fine
+ * descendants of their distance to the surrogate triangle: the distance to
+ * a triangle is convex, so the maximum over a fine triangle is at a vertex,
+ * and that eps is the smallest for which the surrogate's environment holds
+ * every fine descendant's eps0 environment (Definition "conservative").
+ * Returns DEM_ERR_ARG / DEM_ERR_NOT_CONSERVATIVE on malformed input.
+ */
+dem_status dem_build_hierarchy(const double* verts, int32_t n_verts, const int32_t* tris,
+                               const int32_t* parent, const int32_t* level_sizes, int32_t n_levels,
+                               double eps0, const dem_build_opts* opts, dem_hierarchy* out);
+void dem_hierarchy_free(dem_hierarchy* h);
+
+/* ------------------------------------------------------------------ scene */
+
+/* A scene: all particles, all levels, in one global numbering (device). */
+typedef struct {
+  int32_t precision;      /* dem_precision of verts and tri_eps */
+  int32_t n_verts;
+  int32_t n_tris;         /* all levels of all particles */
+  int32_t n_particles;
+  int32_t n_levels_max;   /* largest number of levels of any particle (<= DEM_MAX_LEVELS) */
+  const void* verts;      /* [3][n_verts] SoA world coordinates */
+  const int32_t* tri_verts;   /* [3][n_tris] SoA global vertex ids */
+  const int32_t* child_begin; /* [n_tris] global id of the first child */
+  const int32_t* child_count; /* [n_tris] 0 marks a fine triangle */
+  const int32_t* tri_particle;/* [n_tris] owning particle */
+  const void* tri_eps;        /* [n_tris] epsilon (surrogate eps with slack) */
+  const int32_t* root_begin;  /* [n_particles] coarsest-level triangles */
+  const int32_t* root_count;
+  const int32_t* fine_begin;  /* [n_particles] fine (particle) triangles */
+  const int32_t* fine_count;
+} dem_scene;
+
+/* ------------------------------------------------------------------ parameters */
+
+typedef struct {
+  int32_t mode;           /* DEM_MODE_FLAT (Algorithm 2) or DEM_MODE_HIER (Algorithm 5) */
+  int32_t n_iter;         /* fixed Newton iteration count N_iterative (paper: 4) */
+  float omega;            /* damping of the diagonal-Newton step (1 = undamped) */
+  float alpha_reg_rel;    /* alpha_regulariser of a triangle = alpha_reg_rel * (|e1|^2 + |e2|^2) / 2 */
+  float alpha_it_ratio;   /* alpha_iterative / alpha_regulariser */
+  int32_t init_centroid;  /* 0: start the iteration at (a,b) = 0 as the paper does; 1: at the centroids */
+  int32_t dense_distance; /* 1: threshold = +inf, every fine pair is reported with its exact distance */
+  int32_t certify;        /* 1: accept a near pair's distance from the iterate when the lower
+                             bound certifies it; 0: every near pair takes the exact fallback */
+  double energy_k;        /* k of E = k sum max(0, delta - d)^2 (used when dev_energy != NULL) */
+  int32_t block;          /* threads per block of the descent / near kernels (64..1024, multiple of 64) */
+  int32_t grid;           /* blocks of the persistent kernels (0 = 8 per compute unit) */
+  int32_t batch_items;    /* work items a block claims at once (1..block) */
+  int32_t flat_tile_i;    /* flat mode: i-triangles per tile (multiple of 64, <= 1024) */
+  int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..256) */
+  int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges */
+  int64_t queue_capacity; /* items per level queue */
+  int64_t near_capacity;  /* fine pairs the lower bound could not prune */
+} dem_params;
+
+/* Fill p with the defaults (N_it = 4, HIER mode, certify on). */
+void dem_default_params(dem_params* p);
+
+/* ------------------------------------------------------------------ outputs */
+
+/* Contacts (device SoA, caller-owned).  Contact c joins global triangles
+ * ti[c] (particle pi[c]) and tj[c] (particle pj[c]) at exact distance d[c];
+ * x = contact point, n = normal n(c) = p_i - x where p_i, p_j are the closest
+ * points and x lies on the segment between them at the centre of the overlap
+ * of the two epsilon environments (Section 2: centre of the shortest path
+ * for equal eps, shifted by (eps_i - eps_j)/2 otherwise); for d = 0, x = p_i
+ * and n = 0.  Order is unspecified. */
+typedef struct {
+  int64_t capacity;
+  int32_t* pi;
+  int32_t* pj;
+  int32_t* ti;
+  int32_t* tj;
+  void* d;          /* [capacity] */
+  void* x;          /* [3][capacity] */
+  void* n;          /* [3][capacity] */
+  uint32_t* count;  /* device scalar: contacts found (may exceed capacity) */
+} dem_contacts;
+
+/* Per-call counters (device memory, cleared by dem_find_contacts). */
+typedef struct {
+  unsigned long long evals[DEM_MAX_LEVELS];     /* triangle-pair evaluations at each depth */
+  unsigned long long survivors[DEM_MAX_LEVELS]; /* surrogate pairs not pruned at each depth */
+  unsigned long long near;      /* fine pairs the lower bound did not prune */
+  unsigned long long certified; /* near pairs whose distance the iterate's bound certified */
+  unsigned long long fallback;  /* near pairs sent to the comparison-based distance */
+  unsigned long long contacts;  /* contacts found */
+  unsigned long long items[DEM_MAX_LEVELS];     /* work items consumed at each depth */
+} dem_stats;
+
+/* Bytes of device workspace dem_find_contacts needs for this scene and
+ * parameters (soup, level queues, near list, counters).  0 on bad input. */
+size_t dem_workspace_bytes(const dem_scene* scene, int32_t n_pairs, const dem_params* p);
+
+/*
+ * dem_find_contacts -- all contacts between the candidate particle pairs
+ * (Algorithm 2 in DEM_MODE_FLAT, Algorithm 5 in DEM_MODE_HIER; both give
+ * the same set, Lemma 1).
+ *
+ * scene      device arrays as described in dem_scene (host struct).
+ * pairs      device [2][n_pairs]: particle ids (pairs[0][k], pairs[1][k]).
+ * p          parameters (host); NULL = defaults.
+ * out        contact buffers (host struct of device pointers).
+ * workspace  device, >= dem_workspace_bytes(scene, n_pairs, p) bytes.
+ * dev_stats  device dem_stats or NULL.
+ * dev_status device uint32: cleared, then DEM_DEV_* bits.
+ * dev_energy device double or NULL: receives k * sum max(0, delta - d)^2.
+ * stream     hipStream_t to enqueue on.
+ */
+dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
+                             const dem_params* p, const dem_contacts* out, void* workspace,
+                             size_t workspace_bytes, dem_stats* dev_stats, uint32_t* dev_status,
+                             double* dev_energy, dem_stream_t stream);
+
+/*
+ * dem_contact_backward -- adjoint of the penalty contact energy
+ * E = k * sum over contacts of max(0, delta - d)^2 (delta = eps_i + eps_j).
+ *
+ * The closest points are recomputed for each contact (nothing is stored by
+ * the forward call); with u = (p_j - p_i) / d and barycentric weights w_i,
+ * w_j of the closest points, dE/dv = +2k (delta - d) w_i u for the vertices
+ * of t_i and -2k (delta - d) w_j u for those of t_j (envelope theorem: d
+ * is a minimum over the two triangles).  Intersecting pairs (d = 0) add
+ * energy but no gradient.
+ *
+ * contacts   the output of dem_find_contacts (device count is read on device).
+ * grad_E     device double scalar multiplying the gradient, or NULL for 1.
+ * grad_verts device [3][n_verts], ACCUMULATED into (caller zeroes it).
+ * energy_out device double or NULL: set to E.
+ * dev_status device uint32: DEM_DEV_* bits are OR-ed in (not cleared).
+ */
+dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* contacts, double k,
+                                const double* grad_E, void* grad_verts, double* energy_out,
+                                uint32_t* dev_status, dem_stream_t stream);
+
+const char* dem_status_string(dem_status s);
+
+/* Library version string ("dem <major>.<minor> gfx950"). */
+const char* dem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEM_H_ */

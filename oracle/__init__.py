@@ -52,6 +52,7 @@ def lib():
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         L.oracle_tri_tri.argtypes = [dp, dp, dp]
+        L.oracle_set_ambiguity_tol.argtypes = [C.c_double]
         L.oracle_tri_tri_batch.argtypes = [dp, C.c_int64, dp, C.c_int]
         L.oracle_point_triangle.argtypes = [dp, dp, dp]
         L.oracle_segment_segment.argtypes = [dp, dp, dp]
@@ -74,6 +75,13 @@ def _d(a):
 def _i(a):
     a = np.ascontiguousarray(a, dtype=np.int32)
     return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def set_ambiguity_tol(rel: float = 1e-9) -> None:
+    """Candidates within rel * (largest edge) of the minimum, with different
+    closest points, mark a pair 'ambiguous' (closest points not unique at
+    that resolution).  Process-wide; default 1e-9."""
+    lib().oracle_set_ambiguity_tol(float(rel))
 
 
 def default_threads() -> int:

@@ -229,6 +229,12 @@ typedef struct {
   int ambiguous;   /* another candidate within tolerance has different points */
 } tt_result;
 
+/* Relative distance tolerance under which two of the fifteen candidates
+ * count as tied when flagging non-unique closest points (see tri_tri). */
+static double g_ambiguity_rel = 1e-9;
+
+void oracle_set_ambiguity_tol(double rel) { g_ambiguity_rel = rel; }
+
 static void tri_tri(const double* A, const double* B, tt_result* res) {
   const double* a[3] = {A, A + 3, A + 6};
   const double* b[3] = {B, B + 3, B + 6};
@@ -310,7 +316,7 @@ static void tri_tri(const double* A, const double* B, tt_result* res) {
   }
   for (int k = 0; k < 15; ++k) {
     if (k == best) continue;
-    if (cand_d[k] - cand_d[best] <= 1e-9 * scale) {
+    if (cand_d[k] - cand_d[best] <= g_ambiguity_rel * scale) {
       double dp = dist3(cand_p1[k], cand_p1[best]) + dist3(cand_p2[k], cand_p2[best]);
       if (dp > 1e-6 * scale) res->ambiguous = 1;
     }

@@ -1,0 +1,123 @@
+"""ctypes view of include/dem.h and the loader of libdem.so.
+
+Argument marshalling only: every computation of the path runs in the HIP
+kernels behind these symbols.  Importing this module fails loudly when the
+library has not been built; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdem.so")
+
+DEM_OK, DEM_ERR_ARG, DEM_ERR_CAPACITY, DEM_ERR_HIP, DEM_ERR_NOT_CONSERVATIVE, DEM_ERR_OOM = 0, -1, -2, -3, -4, -5
+DEM_F32, DEM_F64 = 0, 1
+DEM_MODE_FLAT, DEM_MODE_HIER = 0, 1
+DEM_DEV_CONTACT_OVERFLOW = 0x1
+DEM_DEV_QUEUE_OVERFLOW = 0x2
+DEM_DEV_NEAR_OVERFLOW = 0x4
+DEM_DEV_NONFINITE = 0x8
+DEM_MAX_LEVELS = 32
+
+# Every exported symbol declared in include/dem.h.
+EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "dem_workspace_bytes",
+           "dem_find_contacts", "dem_contact_backward", "dem_status_string", "dem_version")
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("coord_scale", C.c_double), ("rel_slack", C.c_double)]
+
+
+class Hierarchy(C.Structure):
+    _fields_ = [("n_tris", C.c_int32), ("n_levels", C.c_int32),
+                ("tri_verts", C.POINTER(C.c_int32)), ("child_begin", C.POINTER(C.c_int32)),
+                ("child_count", C.POINTER(C.c_int32)), ("level_begin", C.POINTER(C.c_int32)),
+                ("eps", C.POINTER(C.c_double)), ("eps_f32", C.POINTER(C.c_float)),
+                ("eps_f64", C.POINTER(C.c_double)),
+                ("root_begin", C.c_int32), ("root_count", C.c_int32),
+                ("fine_begin", C.c_int32), ("fine_count", C.c_int32), ("max_dev", C.c_double)]
+
+
+class Scene(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("n_verts", C.c_int32), ("n_tris", C.c_int32),
+                ("n_particles", C.c_int32), ("n_levels_max", C.c_int32),
+                ("verts", C.c_void_p), ("tri_verts", C.c_void_p), ("child_begin", C.c_void_p),
+                ("child_count", C.c_void_p), ("tri_particle", C.c_void_p), ("tri_eps", C.c_void_p),
+                ("root_begin", C.c_void_p), ("root_count", C.c_void_p),
+                ("fine_begin", C.c_void_p), ("fine_count", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_iter", C.c_int32), ("omega", C.c_float),
+                ("alpha_reg_rel", C.c_float), ("alpha_it_ratio", C.c_float),
+                ("init_centroid", C.c_int32), ("dense_distance", C.c_int32), ("certify", C.c_int32),
+                ("energy_k", C.c_double), ("block", C.c_int32), ("grid", C.c_int32),
+                ("batch_items", C.c_int32), ("flat_tile_i", C.c_int32), ("flat_tile_j", C.c_int32),
+                ("seed_chunk", C.c_int32), ("queue_capacity", C.c_int64), ("near_capacity", C.c_int64)]
+
+
+class Contacts(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("pi", C.c_void_p), ("pj", C.c_void_p), ("ti", C.c_void_p),
+                ("tj", C.c_void_p), ("d", C.c_void_p), ("x", C.c_void_p), ("n", C.c_void_p),
+                ("count", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("evals", C.c_uint64 * DEM_MAX_LEVELS), ("survivors", C.c_uint64 * DEM_MAX_LEVELS),
+                ("near", C.c_uint64), ("certified", C.c_uint64), ("fallback", C.c_uint64),
+                ("contacts", C.c_uint64), ("items", C.c_uint64 * DEM_MAX_LEVELS)]
+
+
+STATS_WORDS = C.sizeof(Stats) // 8
+
+_lib = None
+
+
+class DemError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libdem.so (built by paper_2105_12415_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DemError(f"{LIB_PATH} is missing: build it with `python -m paper_2105_12415_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.dem_build_hierarchy.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                                          C.c_double, C.POINTER(BuildOpts), C.POINTER(Hierarchy)]
+        L.dem_build_hierarchy.restype = C.c_int
+        L.dem_hierarchy_free.argtypes = [C.POINTER(Hierarchy)]
+        L.dem_hierarchy_free.restype = None
+        L.dem_default_params.argtypes = [C.POINTER(Params)]
+        L.dem_default_params.restype = None
+        L.dem_workspace_bytes.argtypes = [C.POINTER(Scene), C.c_int32, C.POINTER(Params)]
+        L.dem_workspace_bytes.restype = C.c_size_t
+        L.dem_find_contacts.argtypes = [C.POINTER(Scene), vp, C.c_int32, C.POINTER(Params),
+                                        C.POINTER(Contacts), vp, C.c_size_t, vp, vp, vp, vp]
+        L.dem_find_contacts.restype = C.c_int
+        L.dem_contact_backward.argtypes = [C.POINTER(Scene), C.POINTER(Contacts), C.c_double, vp, vp,
+                                           vp, vp, vp]
+        L.dem_contact_backward.restype = C.c_int
+        L.dem_status_string.argtypes = [C.c_int]
+        L.dem_status_string.restype = C.c_char_p
+        L.dem_version.argtypes = []
+        L.dem_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != DEM_OK:
+        msg = lib().dem_status_string(status).decode()
+        raise DemError(f"{what} failed: {msg} ({status})")
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().dem_default_params(C.byref(p))
+    return p

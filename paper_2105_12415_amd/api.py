@@ -1,0 +1,342 @@
+"""Python binding of libdem: scene packing, the three C-ABI calls, autograd.
+
+Everything that touches contact geometry runs in libdem's HIP kernels; this
+module only packs host arrays into the library's layout, allocates device
+buffers with torch, and passes pointers and the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import DemError, check, lib
+
+
+# ------------------------------------------------------------------ hierarchy
+def build_hierarchy(verts: np.ndarray, tris: np.ndarray, parent: np.ndarray, level_sizes,
+                    eps0: float, coord_scale: float = 0.0, rel_slack: float = 1e-6) -> dict:
+    """dem_build_hierarchy on one particle; returns numpy copies of the blob."""
+    V = np.ascontiguousarray(verts, np.float64).reshape(-1, 3)
+    T = np.ascontiguousarray(tris, np.int32).reshape(-1, 3)
+    P = np.ascontiguousarray(parent, np.int32).reshape(-1)
+    S = np.ascontiguousarray(level_sizes, np.int32).reshape(-1)
+    opts = _abi.BuildOpts(float(coord_scale), float(rel_slack))
+    h = _abi.Hierarchy()
+    st = lib().dem_build_hierarchy(V.ctypes.data_as(C.POINTER(C.c_double)), len(V),
+                                   T.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   P.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   S.ctypes.data_as(C.POINTER(C.c_int32)), len(S), float(eps0),
+                                   C.byref(opts), C.byref(h))
+    check(st, "dem_build_hierarchy")
+    try:
+        n = h.n_tris
+        out = {
+            "tri_verts": np.ctypeslib.as_array(h.tri_verts, (n, 3)).copy(),
+            "child_begin": np.ctypeslib.as_array(h.child_begin, (n,)).copy(),
+            "child_count": np.ctypeslib.as_array(h.child_count, (n,)).copy(),
+            "level_begin": np.ctypeslib.as_array(h.level_begin, (h.n_levels + 1,)).copy(),
+            "eps": np.ctypeslib.as_array(h.eps, (n,)).copy(),
+            "eps_f32": np.ctypeslib.as_array(h.eps_f32, (n,)).copy(),
+            "eps_f64": np.ctypeslib.as_array(h.eps_f64, (n,)).copy(),
+            "root_begin": h.root_begin, "root_count": h.root_count,
+            "fine_begin": h.fine_begin, "fine_count": h.fine_count, "max_dev": h.max_dev,
+        }
+    finally:
+        lib().dem_hierarchy_free(C.byref(h))
+    return out
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ scene
+class DeviceScene:
+    """A scene packed into dem_scene's global numbering, resident on the GPU.
+
+    Triangles are numbered particle by particle, coarsest level first; the
+    fine triangles of particle p are [fine_begin[p], fine_begin[p]+fine_count[p]).
+    ``verts`` is the (3, V) world-coordinate tensor the kernels read; replace
+    its contents (same tensor) to move the particles.
+    """
+
+    def __init__(self, scene, device="cuda", coord_scale: Optional[float] = None,
+                 hier_levels: bool = True):
+        self.scene = scene
+        self.device = torch.device(device)
+        self.precision = _abi.DEM_F64 if scene.dtype == "f64" else _abi.DEM_F32
+        self.dtype = torch.float64 if scene.dtype == "f64" else torch.float32
+        worlds = [scene.world(p) for p in range(len(scene.particles))]
+        if coord_scale is None:
+            coord_scale = 1.25 * max(float(np.abs(w).max()) for w in worlds) + 1.0
+        tv, cb, cc, tp, ep, rb, rc, fb, fc, vb = [], [], [], [], [], [], [], [], [], []
+        nv = nt = 0
+        n_levels_max = 1
+        self.max_dev = 0.0
+        for p, part in enumerate(scene.particles):
+            levels = part.levels if hier_levels else [part.levels[-1]]
+            sizes = [len(l) for l in levels]
+            offs = np.cumsum([0] + sizes)
+            tris = np.concatenate(levels).astype(np.int32)
+            parent = np.full(len(tris), -1, np.int32)
+            if hier_levels:
+                for l in range(1, len(levels)):
+                    parent[offs[l]:offs[l + 1]] = part.parents[l] + offs[l - 1]
+            h = build_hierarchy(worlds[p], tris, parent, sizes, part.eps0, coord_scale)
+            self.max_dev = max(self.max_dev, h["max_dev"])
+            n = len(tris)
+            tv.append(h["tri_verts"] + nv)
+            cb.append(np.where(h["child_count"] > 0, h["child_begin"] + nt, 0))
+            cc.append(h["child_count"])
+            tp.append(np.full(n, p, np.int32))
+            ep.append(h["eps_f64"] if self.precision == _abi.DEM_F64 else h["eps_f32"])
+            rb.append(nt + h["root_begin"]); rc.append(h["root_count"])
+            fb.append(nt + h["fine_begin"]); fc.append(h["fine_count"])
+            vb.append(nv)
+            n_levels_max = max(n_levels_max, len(levels))
+            nv += len(worlds[p])
+            nt += n
+        d = self.device
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32), device=d)
+        self.n_verts, self.n_tris, self.n_particles = nv, nt, len(scene.particles)
+        self.n_levels_max = n_levels_max
+        self.vert_begin = np.array(vb, np.int64)
+        self.verts_host = np.concatenate(worlds)  # (V,3) f64 (precision-rounded)
+        self.verts = torch.as_tensor(self.verts_host.T.copy(), dtype=self.dtype, device=d).contiguous()
+        self.tri_verts_host = np.concatenate(tv)
+        self.tri_verts = i32(self.tri_verts_host.T.copy())
+        self.child_begin = i32(np.concatenate(cb))
+        self.child_count = i32(np.concatenate(cc))
+        self.tri_particle = i32(np.concatenate(tp))
+        self.tri_eps = torch.as_tensor(np.concatenate(ep), dtype=self.dtype, device=d)
+        self.root_begin, self.root_count = i32(rb), i32(rc)
+        self.fine_begin_host = np.array(fb, np.int64)
+        self.fine_count_host = np.array(fc, np.int64)
+        self.root_count_host = np.array(rc, np.int64)
+        self.fine_begin, self.fine_count = i32(fb), i32(fc)
+        self.pairs_host = np.asarray(scene.pairs, np.int32).reshape(-1, 2)
+        if len(self.pairs_host) and (self.pairs_host.min() < 0 or self.pairs_host.max() >= len(scene.particles)
+                                     or np.any(self.pairs_host[:, 0] == self.pairs_host[:, 1])):
+            raise DemError("candidate pairs must join two different existing particles")
+        self.pairs = i32(self.pairs_host.T.copy())  # (2, P)
+        self.coord_scale = coord_scale
+        self._refresh()
+
+    def _refresh(self):
+        s = _abi.Scene()
+        s.precision = self.precision
+        s.n_verts, s.n_tris, s.n_particles = self.n_verts, self.n_tris, self.n_particles
+        s.n_levels_max = self.n_levels_max
+        s.verts = self.verts.data_ptr()
+        s.tri_verts = self.tri_verts.data_ptr()
+        s.child_begin = self.child_begin.data_ptr()
+        s.child_count = self.child_count.data_ptr()
+        s.tri_particle = self.tri_particle.data_ptr()
+        s.tri_eps = self.tri_eps.data_ptr()
+        s.root_begin, s.root_count = self.root_begin.data_ptr(), self.root_count.data_ptr()
+        s.fine_begin, s.fine_count = self.fine_begin.data_ptr(), self.fine_count.data_ptr()
+        self.c = s
+
+    def set_verts(self, verts: torch.Tensor):
+        """Point the scene at another (3, V) tensor of the scene's dtype."""
+        assert verts.shape == (3, self.n_verts) and verts.dtype == self.dtype and verts.is_contiguous()
+        self.verts = verts
+        self._refresh()
+
+    @property
+    def n_pairs(self) -> int:
+        return len(self.pairs_host)
+
+    def n_fine_pairs(self) -> int:
+        F = self.fine_count_host
+        return int(np.sum(F[self.pairs_host[:, 0]] * F[self.pairs_host[:, 1]]))
+
+
+# ------------------------------------------------------------------ calls
+def make_params(mode: str = "hier", **kw) -> _abi.Params:
+    p = _abi.default_params()
+    p.mode = _abi.DEM_MODE_HIER if mode == "hier" else _abi.DEM_MODE_FLAT
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+@dataclass
+class ContactBuffers:
+    capacity: int
+    pi: torch.Tensor
+    pj: torch.Tensor
+    ti: torch.Tensor
+    tj: torch.Tensor
+    d: torch.Tensor
+    x: torch.Tensor
+    n: torch.Tensor
+    count: torch.Tensor
+
+    @staticmethod
+    def alloc(capacity: int, dtype, device) -> "ContactBuffers":
+        cap = max(1, int(capacity))
+        z = lambda *s, dt=torch.int32: torch.zeros(*s, dtype=dt, device=device)
+        return ContactBuffers(cap, z(cap), z(cap), z(cap), z(cap), z(cap, dt=dtype), z(3, cap, dt=dtype),
+                              z(3, cap, dt=dtype), z(1))
+
+    def c(self) -> _abi.Contacts:
+        s = _abi.Contacts()
+        s.capacity = self.capacity
+        s.pi, s.pj, s.ti, s.tj = (t.data_ptr() for t in (self.pi, self.pj, self.ti, self.tj))
+        s.d, s.x, s.n = self.d.data_ptr(), self.x.data_ptr(), self.n.data_ptr()
+        s.count = self.count.data_ptr()
+        return s
+
+
+class ContactEngine:
+    """Preallocated buffers + the C-ABI calls for one scene.
+
+    ``forward()`` enqueues dem_find_contacts (contacts and energy),
+    ``backward()`` dem_contact_backward.  Neither synchronises, so a step can
+    be captured in a CUDA/HIP graph; ``check()`` synchronises and raises on
+    device-reported overflow.
+    """
+
+    def __init__(self, ds: DeviceScene, params: Optional[_abi.Params] = None,
+                 contact_capacity: Optional[int] = None, energy_k: float = 1e4):
+        self.ds = ds
+        self.p = params if params is not None else make_params("hier")
+        self.p.energy_k = float(energy_k)
+        dev = ds.device
+        if contact_capacity is None:
+            contact_capacity = ds.n_fine_pairs() if self.p.dense_distance else max(1 << 16, 64 * ds.n_pairs)
+        if self.p.dense_distance:
+            self.p.near_capacity = max(int(self.p.near_capacity), ds.n_fine_pairs())
+        if self.p.mode == _abi.DEM_MODE_FLAT:
+            ti, tj = self.p.flat_tile_i, self.p.flat_tile_j
+            F = ds.fine_count_host
+            a, b = F[ds.pairs_host[:, 0]], F[ds.pairs_host[:, 1]]
+            tiles = int(np.sum(((a + ti - 1) // ti) * ((b + tj - 1) // tj)))
+            self.p.queue_capacity = max(int(self.p.queue_capacity), tiles)
+        self.contacts = ContactBuffers.alloc(contact_capacity, ds.dtype, dev)
+        self.stats = torch.zeros(_abi.STATS_WORDS, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.energy = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.energy_bwd = torch.zeros(1, dtype=torch.float64, device=dev)
+        self._alloc_ws()
+
+    def _alloc_ws(self):
+        nbytes = lib().dem_workspace_bytes(C.byref(self.ds.c), self.ds.n_pairs, C.byref(self.p))
+        if nbytes == 0:
+            raise DemError("dem_workspace_bytes rejected the scene or parameters")
+        self.ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.ds.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = self.ws.data_ptr() + off
+        self.ws_bytes = int(nbytes)
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.ds.device).cuda_stream)
+
+    def forward(self, with_energy: bool = True):
+        cs = self.contacts.c()
+        st = lib().dem_find_contacts(C.byref(self.ds.c), _ptr(self.ds.pairs), self.ds.n_pairs,
+                                     C.byref(self.p), C.byref(cs), C.c_void_p(self.ws_ptr),
+                                     self.ws_bytes, _ptr(self.stats), _ptr(self.status),
+                                     _ptr(self.energy) if with_energy else None, self._stream())
+        check(st, "dem_find_contacts")
+
+    def backward(self, grad_verts: torch.Tensor, grad_E: Optional[torch.Tensor] = None,
+                 energy: bool = False):
+        assert grad_verts.shape == (3, self.ds.n_verts) and grad_verts.dtype == self.ds.dtype
+        cs = self.contacts.c()
+        st = lib().dem_contact_backward(C.byref(self.ds.c), C.byref(cs), float(self.p.energy_k),
+                                        _ptr(grad_E), _ptr(grad_verts),
+                                        _ptr(self.energy_bwd) if energy else None, _ptr(self.status),
+                                        self._stream())
+        check(st, "dem_contact_backward")
+
+    # ---------------------------------------------------------- host-side reads
+    def counters(self) -> dict:
+        w = self.ws[(self.ws_ptr - self.ws.data_ptr()):][: 4 * 68].view(torch.int32).cpu().numpy()
+        w = w.astype(np.int64) & 0xFFFFFFFF
+        return {"head": w[0:33], "tail": w[33:66], "near": int(w[66])}
+
+    def check(self) -> int:
+        torch.cuda.synchronize(self.ds.device)
+        return int(self.status.item()) & 0xFFFFFFFF
+
+    def count(self) -> int:
+        return int(self.contacts.count.item()) & 0xFFFFFFFF
+
+    def run(self, with_energy: bool = True, max_retries: int = 6):
+        """forward() + synchronise; grows capacities and reruns on overflow."""
+        for _ in range(max_retries):
+            self.forward(with_energy)
+            status = self.check()
+            if status & _abi.DEM_DEV_NONFINITE:
+                raise DemError("non-finite coordinates or distances")
+            if not status & (_abi.DEM_DEV_CONTACT_OVERFLOW | _abi.DEM_DEV_QUEUE_OVERFLOW |
+                             _abi.DEM_DEV_NEAR_OVERFLOW):
+                return status
+            ctr = self.counters()
+            if status & _abi.DEM_DEV_CONTACT_OVERFLOW:
+                self.contacts = ContactBuffers.alloc(int(self.count() * 1.25) + 1024, self.ds.dtype,
+                                                     self.ds.device)
+            grow = False
+            if status & _abi.DEM_DEV_QUEUE_OVERFLOW:
+                self.p.queue_capacity = max(2 * self.p.queue_capacity, int(1.25 * ctr["tail"].max()) + 1024)
+                grow = True
+            if status & _abi.DEM_DEV_NEAR_OVERFLOW:
+                self.p.near_capacity = max(2 * self.p.near_capacity, int(1.25 * ctr["near"]) + 1024)
+                grow = True
+            if grow:
+                self.ws = None
+                self._alloc_ws()
+        raise DemError("capacities kept overflowing")
+
+    def stats_dict(self) -> dict:
+        s = self.stats.cpu().numpy().view(np.uint64)
+        L = _abi.DEM_MAX_LEVELS
+        return {"evals": s[0:L].astype(np.int64), "survivors": s[L:2 * L].astype(np.int64),
+                "near": int(s[2 * L]), "certified": int(s[2 * L + 1]), "fallback": int(s[2 * L + 2]),
+                "contacts": int(s[2 * L + 3]), "items": s[2 * L + 4:3 * L + 4].astype(np.int64)}
+
+    def result(self) -> dict:
+        """Host copy of the contacts (after run())."""
+        n = min(self.count(), self.contacts.capacity)
+        c = self.contacts
+        return {"pi": c.pi[:n].cpu().numpy(), "pj": c.pj[:n].cpu().numpy(),
+                "ti": c.ti[:n].cpu().numpy(), "tj": c.tj[:n].cpu().numpy(),
+                "d": c.d[:n].double().cpu().numpy(), "x": c.x[:, :n].double().cpu().numpy().T,
+                "n": c.n[:, :n].double().cpu().numpy().T, "energy": float(self.energy.item())}
+
+
+class DemContactEnergy(torch.autograd.Function):
+    """E(verts) = k * sum over contacts of max(0, eps_i + eps_j - d)^2.
+
+    forward: dem_find_contacts (contacts + energy); backward: the adjoint
+    kernel dem_contact_backward, which recomputes the closest points.
+    """
+
+    @staticmethod
+    def forward(ctx, verts: torch.Tensor, engine: ContactEngine):
+        if verts.data_ptr() != engine.ds.verts.data_ptr():
+            engine.ds.set_verts(verts.detach().contiguous())
+        engine.forward(with_energy=True)
+        ctx.engine = engine
+        return engine.energy[0].to(verts.dtype).clone()
+
+    @staticmethod
+    def backward(ctx, grad_E: torch.Tensor):
+        eng = ctx.engine
+        g = torch.zeros(3, eng.ds.n_verts, dtype=eng.ds.dtype, device=eng.ds.device)
+        gE = grad_E.detach().to(torch.float64).reshape(1).contiguous()
+        eng.backward(g, gE)
+        return g, None
+
+
+def contact_energy(verts: torch.Tensor, engine: ContactEngine) -> torch.Tensor:
+    return DemContactEnergy.apply(verts, engine)

@@ -1,0 +1,755 @@
+// HIP kernels (gfx950) and the C ABI of the contact-detection path.
+//
+// Step of one dem_find_contacts call (all on the caller's stream):
+//   k_reset    clear the device counters (a kernel, not a memset, so the
+//              call can be captured in a graph and replayed)
+//   k_flatten  world vertices -> triangle soup (Section 3, triangle soup
+//              implementation note: per-triangle coordinates with no
+//              indirection), plus the regularised Newton diagonal
+//   k_seed     one work item per (root-range x root-range) chunk of each
+//              candidate particle pair (HIER) or per fine tile (FLAT)
+//   k_level    HIER: one launch per tree depth; every item is a product of
+//              two child ranges; each child pair runs the fixed-count
+//              iteration + lower bound; surviving surrogate pairs become the
+//              next depth's items, fine pairs that are not pruned go to the
+//              near list (Algorithm 5, pairwise form)
+//   k_flat     FLAT: LDS-staged tiles over all fine pairs (Algorithm 2)
+//   k_near     exact comparison-based distance for the near list, contact
+//              emission and the penalty energy (Algorithm 4, fallback part)
+// dem_contact_backward launches k_backward: recompute closest points per
+// contact and scatter the energy gradient with atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+
+#include "dem.h"
+#include "dem_geom.hpp"
+
+using namespace dem;
+
+namespace {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ layout
+// Soup record: 12 values + 4 ints.  float: 64 B (one half cache line),
+// double: 112 B.
+template <typename T>
+struct alignas(16) SoupRec {
+  T g[12];         // v0.xyz eps | e1.xyz ia | e2.xyz ib
+  int32_t topo[4]; // child_begin, child_count, particle, unused
+};
+
+struct Counters {
+  uint32_t head[DEM_MAX_LEVELS + 1];
+  uint32_t tail[DEM_MAX_LEVELS + 1];
+  uint32_t near_tail;
+  uint32_t near_head;
+  uint32_t pad[30];
+};
+
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct WsLayout {
+  size_t ctr, soup, qa, qb, near_, total;
+};
+
+WsLayout ws_layout(int precision, int64_t n_tris, int64_t qcap, int64_t ncap) {
+  WsLayout L;
+  size_t rec = precision == DEM_F64 ? sizeof(SoupRec<double>) : sizeof(SoupRec<float>);
+  size_t o = 0;
+  L.ctr = o; o = align_up(o + sizeof(Counters), 256);
+  L.soup = o; o = align_up(o + rec * (size_t)n_tris, 256);
+  L.qa = o; o = align_up(o + 16 * (size_t)qcap, 256);
+  L.qb = o; o = align_up(o + 16 * (size_t)qcap, 256);
+  L.near_ = o; o = align_up(o + 8 * (size_t)ncap, 256);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+__device__ __forceinline__ Tri<T> load_tri(const SoupRec<T>* __restrict__ s, int t, int& cb, int& cc,
+                                           int& part) {
+  const SoupRec<T>& r = s[t];
+  Tri<T> x;
+  if constexpr (sizeof(T) == 4) {
+    const float4* p = reinterpret_cast<const float4*>(&r);
+    float4 a = p[0], b = p[1], c = p[2];
+    int4 d = reinterpret_cast<const int4*>(&r)[3];
+    x.v0 = {a.x, a.y, a.z}; x.eps = a.w;
+    x.e1 = {b.x, b.y, b.z}; x.ia = b.w;
+    x.e2 = {c.x, c.y, c.z}; x.ib = c.w;
+    cb = d.x; cc = d.y; part = d.z;
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(&r);
+    double2 a0 = p[0], a1 = p[1], b0 = p[2], b1 = p[3], c0 = p[4], c1 = p[5];
+    int4 d = *reinterpret_cast<const int4*>(&r.topo[0]);
+    x.v0 = {a0.x, a0.y, a1.x}; x.eps = a1.y;
+    x.e1 = {b0.x, b0.y, b1.x}; x.ia = b1.y;
+    x.e2 = {c0.x, c0.y, c1.x}; x.ib = c1.y;
+    cb = d.x; cc = d.y; part = d.z;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Wave-aggregated append: one atomic per wave; returns this lane's slot.
+// Must be called by every lane that may append (pred false for the rest).
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* tail, uint32_t& slot_ok) {
+  unsigned long long m = __ballot(pred);
+  slot_ok = 0;
+  if (m == 0ull) return 0;
+  int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(tail, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  unsigned long long lt = (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
+  slot_ok = pred ? 1u : 0u;
+  return base + (uint32_t)__popcll(m & lt);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ void add_stat(unsigned long long* p, unsigned long long v) {
+  if (p) atomicAdd(p, v);
+}
+
+// ------------------------------------------------------------------ kernels
+__global__ void k_reset(Counters* ctr, dem_stats* stats, uint32_t* status, uint32_t* count,
+                        double* energy) {
+  int t = threadIdx.x;
+  uint32_t* c = reinterpret_cast<uint32_t*>(ctr);
+  for (int i = t; i < (int)(sizeof(Counters) / 4); i += blockDim.x) c[i] = 0;
+  if (stats) {
+    unsigned long long* s = reinterpret_cast<unsigned long long*>(stats);
+    for (int i = t; i < (int)(sizeof(dem_stats) / 8); i += blockDim.x) s[i] = 0;
+  }
+  if (t == 0) {
+    *status = 0;
+    *count = 0;
+    if (energy) *energy = 0.0;
+  }
+}
+
+__global__ void k_zero_scalar(double* e) {
+  if (threadIdx.x == 0) *e = 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, int n_verts,
+                                                 const int32_t* __restrict__ tv, int n_tris,
+                                                 const int32_t* __restrict__ cbeg,
+                                                 const int32_t* __restrict__ ccnt,
+                                                 const int32_t* __restrict__ tpart,
+                                                 const T* __restrict__ teps, T areg_rel,
+                                                 SoupRec<T>* __restrict__ soup, uint32_t* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tris) return;
+  const T* X = verts;
+  const T* Y = verts + n_verts;
+  const T* Z = verts + 2 * (size_t)n_verts;
+  int i0 = tv[t], i1 = tv[n_tris + t], i2 = tv[2 * (size_t)n_tris + t];
+  V3<T> v0 = {X[i0], Y[i0], Z[i0]};
+  V3<T> v1 = {X[i1], Y[i1], Z[i1]};
+  V3<T> v2 = {X[i2], Y[i2], Z[i2]};
+  V3<T> e1 = v1 - v0, e2 = v2 - v0;
+  T n1 = dot(e1, e1), n2 = dot(e2, e2);
+  T areg = areg_rel * T(0.5) * (n1 + n2);
+  T ia = T(1) / (n1 + areg), ib = T(1) / (n2 + areg);
+  SoupRec<T> r;
+  r.g[0] = v0.x; r.g[1] = v0.y; r.g[2] = v0.z; r.g[3] = teps[t];
+  r.g[4] = e1.x; r.g[5] = e1.y; r.g[6] = e1.z; r.g[7] = ia;
+  r.g[8] = e2.x; r.g[9] = e2.y; r.g[10] = e2.z; r.g[11] = ib;
+  r.topo[0] = cbeg[t]; r.topo[1] = ccnt[t]; r.topo[2] = tpart[t]; r.topo[3] = 0;
+  soup[t] = r;
+  T chk = v0.x + v0.y + v0.z + v1.x + v1.y + v1.z + v2.x + v2.y + v2.z;
+  if (!isfinite(chk)) atomicOr(status, DEM_DEV_NONFINITE);
+}
+
+// One block per candidate pair: items covering range_i x range_j in chunks.
+__global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
+                       const int32_t* __restrict__ rbeg, const int32_t* __restrict__ rcnt, int ci,
+                       int cj, int4* __restrict__ q, uint32_t* tail, int64_t cap,
+                       uint32_t* status) {
+  int pr = blockIdx.x;
+  if (pr >= n_pairs) return;
+  int pi = pairs[pr], pj = pairs[n_pairs + pr];
+  int bi = rbeg[pi], ni = rcnt[pi], bj = rbeg[pj], nj = rcnt[pj];
+  int nci = (ni + ci - 1) / ci, ncj = (nj + cj - 1) / cj;
+  int n = nci * ncj;
+  __shared__ uint32_t base;
+  if (threadIdx.x == 0) base = n > 0 ? atomicAdd(tail, (uint32_t)n) : 0u;
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    int ii = k / ncj, jj = k - ii * ncj;
+    int4 it;
+    it.x = bi + ii * ci;
+    it.y = min(ci, ni - ii * ci);
+    it.z = bj + jj * cj;
+    it.w = min(cj, nj - jj * cj);
+    uint64_t slot = (uint64_t)base + (uint64_t)k;
+    if (slot < (uint64_t)cap)
+      q[slot] = it;
+    else
+      atomicOr(status, DEM_DEV_QUEUE_OVERFLOW);
+  }
+}
+
+// Block-wide exclusive scan of v (blockDim <= 1024) into offs[0..n].
+__device__ __forceinline__ void block_scan(int v, int* offs, int* wsum, int n) {
+  int lane = lane_id();
+  int wid = threadIdx.x / kWave;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    int nw = (blockDim.x + kWave - 1) / kWave;
+    for (int w = 0; w < nw; ++w) {
+      int s = wsum[w];
+      wsum[w] = acc;
+      acc += s;
+    }
+    offs[n] = acc;  // total lives after the last item (read only after sync)
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < n) offs[threadIdx.x] = x - v + wsum[wid];
+  __syncthreads();
+}
+
+struct LevelArgs {
+  const int4* qin;
+  const uint32_t* tail_in;
+  uint32_t* head_in;
+  int4* qout;
+  uint32_t* tail_out;
+  int64_t qcap;
+  int2* near_;
+  uint32_t* near_tail;
+  int64_t ncap;
+  dem_stats* stats;
+  uint32_t* status;
+  int depth;
+  int dense;
+  int batch;
+  IterParams ip;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
+  __shared__ int4 items[256];
+  __shared__ int offs[257];
+  __shared__ int wsum[16];
+  __shared__ uint32_t sh_base;
+  const uint32_t count = min((uint64_t)*a.tail_in, (uint64_t)a.qcap);
+  unsigned long long my_evals = 0, my_surv = 0, my_near = 0;
+  for (;;) {
+    if (threadIdx.x == 0) sh_base = atomicAdd(a.head_in, (uint32_t)a.batch);
+    __syncthreads();
+    uint32_t b = sh_base;
+    if (b >= count) break;
+    int n = (int)min((uint32_t)a.batch, count - b);
+    int np = 0;
+    if ((int)threadIdx.x < n) {
+      int4 it = a.qin[b + threadIdx.x];
+      items[threadIdx.x] = it;
+      np = it.y * it.w;
+    }
+    block_scan(np, offs, wsum, n);
+    const int total = offs[n];
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      // item owning flat index e: last k with offs[k] <= e
+      int lo = 0, hi = n - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      int4 it = items[lo];
+      int l = e - offs[lo];
+      int jn = it.w;
+      int qd = (int)((float)l * (1.0f / (float)jn));
+      int rr = l - qd * jn;
+      if (rr < 0) { qd -= 1; rr += jn; }
+      if (rr >= jn) { qd += 1; rr -= jn; }
+      int ci = it.x + qd, cj = it.z + rr;
+      int cbi, cci, pi_, cbj, ccj, pj_;
+      Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
+      Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_);
+      V3<T> D0 = A.v0 - B.v0;
+      T th[4], up;
+      T L = iterate_and_bound(A, B, D0, a.ip, th, &up);
+      T delta = A.eps + B.eps;
+      bool fine = (cci == 0) && (ccj == 0);
+      bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
+      ++my_evals;
+      // surrogate survivors -> next depth (only the non-fine side unfolds)
+      uint32_t ok;
+      bool push_item = keep && !fine;
+      uint32_t slot = wave_append(push_item, a.tail_out, ok);
+      if (ok) {
+        int4 nx;
+        nx.x = cci ? cbi : ci; nx.y = cci ? cci : 1;
+        nx.z = ccj ? cbj : cj; nx.w = ccj ? ccj : 1;
+        if (slot < (uint64_t)a.qcap) a.qout[slot] = nx;
+        else atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+        ++my_surv;
+      }
+      bool push_near = keep && fine;
+      slot = wave_append(push_near, a.near_tail, ok);
+      if (ok) {
+        if (slot < (uint64_t)a.ncap) a.near_[slot] = make_int2(ci, cj);
+        else atomicOr(a.status, DEM_DEV_NEAR_OVERFLOW);
+        ++my_near;
+      }
+    }
+    __syncthreads();
+  }
+  if (a.stats) {
+    // one atomic per wave
+    unsigned long long s0 = my_evals, s1 = my_surv, s2 = my_near;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o);
+      s1 += __shfl_xor(s1, o);
+      s2 += __shfl_xor(s2, o);
+    }
+    if (lane_id() == 0) {
+      if (s0) atomicAdd(&a.stats->evals[a.depth], s0);
+      if (s1) atomicAdd(&a.stats->survivors[a.depth], s1);
+      if (s2) atomicAdd(&a.stats->near, s2);
+    }
+  }
+}
+
+// FLAT: tile = (i range <= blockDim) x (j range <= TJ) of fine triangles.
+template <typename T, int TJ>
+__global__ void __launch_bounds__(256) k_flat(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
+  __shared__ SoupRec<T> tj_s[TJ];
+  __shared__ uint32_t sh_base;
+  const uint32_t count = min((uint64_t)*a.tail_in, (uint64_t)a.qcap);
+  unsigned long long my_evals = 0, my_near = 0;
+  for (;;) {
+    if (threadIdx.x == 0) sh_base = atomicAdd(a.head_in, 1u);
+    __syncthreads();
+    uint32_t b = sh_base;
+    if (b >= count) break;
+    int4 it = a.qin[b];
+    // stage the j-triangles in LDS
+    for (int k = threadIdx.x; k < it.w; k += blockDim.x) tj_s[k] = soup[it.z + k];
+    __syncthreads();
+    for (int r = threadIdx.x; r < it.y; r += blockDim.x) {
+      int ci = it.x + r;
+      int cbi, cci, pi_;
+      Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
+      for (int k = 0; k < it.w; ++k) {
+        int cbj, ccj, pj_;
+        Tri<T> B = load_tri(tj_s, k, cbj, ccj, pj_);
+        V3<T> D0 = A.v0 - B.v0;
+        T th[4], up;
+        T L = iterate_and_bound(A, B, D0, a.ip, th, &up);
+        T delta = A.eps + B.eps;
+        bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
+        ++my_evals;
+        uint32_t ok;
+        uint32_t slot = wave_append(keep, a.near_tail, ok);
+        if (ok) {
+          if (slot < (uint64_t)a.ncap) a.near_[slot] = make_int2(ci, it.z + k);
+          else atomicOr(a.status, DEM_DEV_NEAR_OVERFLOW);
+          ++my_near;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (a.stats) {
+    unsigned long long s0 = my_evals, s2 = my_near;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o);
+      s2 += __shfl_xor(s2, o);
+    }
+    if (lane_id() == 0) {
+      if (s0) atomicAdd(&a.stats->evals[0], s0);
+      if (s2) atomicAdd(&a.stats->near, s2);
+    }
+  }
+}
+
+struct NearArgs {
+  const int2* near_;
+  const uint32_t* near_tail;
+  int64_t ncap;
+  int32_t* pi;
+  int32_t* pj;
+  int32_t* ti;
+  int32_t* tj;
+  void* d;
+  void* x;
+  void* n;
+  uint32_t* count;
+  int64_t ccap;
+  int dense;
+  double k;
+  double* energy;
+  dem_stats* stats;
+  uint32_t* status;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
+  const uint32_t cnt = min((uint64_t)*a.near_tail, (uint64_t)a.ncap);
+  T* dd = static_cast<T*>(a.d);
+  T* xx = static_cast<T*>(a.x);
+  T* nn = static_cast<T*>(a.n);
+  double e_acc = 0.0;
+  unsigned long long my_fb = 0, my_c = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  // uniform trip count per wave so the wave-level appends see every lane
+  const uint32_t start = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t wave0 = start - (threadIdx.x % kWave);
+  for (uint32_t base = wave0; base < cnt; base += stride) {
+    uint32_t e = base + (threadIdx.x % kWave);
+    bool act = e < cnt;
+    bool emit = false;
+    T d = T(0);
+    V3<T> xc = {0, 0, 0}, nc = {0, 0, 0};
+    int ci = 0, cj = 0, pi_ = 0, pj_ = 0;
+    if (act) {
+      int2 pr = a.near_[e];
+      ci = pr.x; cj = pr.y;
+      int cbi, cci, cbj, ccj;
+      Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
+      Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_);
+      V3<T> D0 = A.v0 - B.v0;
+      Closest<T> c;
+      exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, c);
+      ++my_fb;
+      d = sqrt(c.d2);
+      T delta = a.dense ? T(INFINITY) : A.eps + B.eps;
+      emit = d <= delta;
+      if (!isfinite(d)) atomicOr(a.status, DEM_DEV_NONFINITE);
+      if (emit) {
+        // contact point at the centre of the overlap of the two environments
+        V3<T> w = c.q - c.p;
+        T lam = d > T(0) ? (d + A.eps - B.eps) / (T(2) * d) : T(0);
+        V3<T> xl = fma3(lam, w, c.p);
+        nc = c.p - xl;
+        xc = xl + A.v0;
+        if (!a.dense) {
+          double pen = (double)delta - (double)d;
+          e_acc += a.k * pen * pen;
+        }
+      }
+    }
+    uint32_t ok;
+    uint32_t slot = wave_append(emit, a.count, ok);
+    if (ok) {
+      ++my_c;
+      if (slot < (uint64_t)a.ccap) {
+        a.pi[slot] = pi_; a.pj[slot] = pj_; a.ti[slot] = ci; a.tj[slot] = cj;
+        dd[slot] = d;
+        xx[slot] = xc.x; xx[a.ccap + slot] = xc.y; xx[2 * a.ccap + slot] = xc.z;
+        nn[slot] = nc.x; nn[a.ccap + slot] = nc.y; nn[2 * a.ccap + slot] = nc.z;
+      } else {
+        atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
+      }
+    }
+  }
+  if (a.energy) {
+    double s = wave_sum(e_acc);
+    if (lane_id() == 0 && s != 0.0) atomicAdd(a.energy, s);
+  }
+  if (a.stats) {
+    unsigned long long s0 = my_fb, s1 = my_c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o);
+      s1 += __shfl_xor(s1, o);
+    }
+    if (lane_id() == 0) {
+      if (s0) atomicAdd(&a.stats->fallback, s0);
+      if (s1) atomicAdd(&a.stats->contacts, s1);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void atomic_add_t(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_backward(const T* __restrict__ verts, int n_verts,
+                                                  const int32_t* __restrict__ tv, int n_tris,
+                                                  const T* __restrict__ teps,
+                                                  const int32_t* __restrict__ cti,
+                                                  const int32_t* __restrict__ ctj,
+                                                  const uint32_t* __restrict__ ccount, int64_t ccap,
+                                                  double k, const double* __restrict__ grad_E,
+                                                  T* __restrict__ grad, double* energy,
+                                                  uint32_t* status) {
+  const uint32_t cnt = min((uint64_t)*ccount, (uint64_t)ccap);
+  const double gE = grad_E ? *grad_E : 1.0;
+  const T* X = verts;
+  const T* Y = verts + n_verts;
+  const T* Z = verts + 2 * (size_t)n_verts;
+  double e_acc = 0.0;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
+    int ti = cti[c], tj = ctj[c];
+    int ia[3] = {tv[ti], tv[n_tris + ti], tv[2 * (size_t)n_tris + ti]};
+    int ib[3] = {tv[tj], tv[n_tris + tj], tv[2 * (size_t)n_tris + tj]};
+    V3<T> A0 = {X[ia[0]], Y[ia[0]], Z[ia[0]]};
+    V3<T> A1 = {X[ia[1]], Y[ia[1]], Z[ia[1]]};
+    V3<T> A2 = {X[ia[2]], Y[ia[2]], Z[ia[2]]};
+    V3<T> B0 = {X[ib[0]], Y[ib[0]], Z[ib[0]]};
+    V3<T> B1 = {X[ib[1]], Y[ib[1]], Z[ib[1]]};
+    V3<T> B2 = {X[ib[2]], Y[ib[2]], Z[ib[2]]};
+    V3<T> D0 = A0 - B0;
+    Closest<T> cl;
+    exact_tri_tri(V3<T>{0, 0, 0}, A1 - A0, A2 - A0, -D0, B1 - B0, B2 - B0, cl);
+    T d = sqrt(cl.d2);
+    T delta = teps[ti] + teps[tj];
+    double pen = (double)delta - (double)d;
+    if (!(pen >= 0.0)) continue;
+    e_acc += k * pen * pen;
+    if (!(d > T(0)) || grad == nullptr) continue;
+    T g = T(2.0 * k * pen * gE);
+    V3<T> u = (T(1) / d) * (cl.q - cl.p);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      T gi = g * cl.wp[v], gj = -g * cl.wq[v];
+      if (gi != T(0)) {
+        atomic_add_t(grad + ia[v], gi * u.x);
+        atomic_add_t(grad + n_verts + ia[v], gi * u.y);
+        atomic_add_t(grad + 2 * (size_t)n_verts + ia[v], gi * u.z);
+      }
+      if (gj != T(0)) {
+        atomic_add_t(grad + ib[v], gj * u.x);
+        atomic_add_t(grad + n_verts + ib[v], gj * u.y);
+        atomic_add_t(grad + 2 * (size_t)n_verts + ib[v], gj * u.z);
+      }
+    }
+  }
+  if (energy) {
+    double s = wave_sum(e_acc);
+    if (lane_id() == 0 && s != 0.0) atomicAdd(energy, s);
+  }
+}
+
+// ------------------------------------------------------------------ host
+IterParams make_iter(const dem_params& p) {
+  IterParams ip;
+  ip.n_iter = p.n_iter;
+  ip.omega = p.omega;
+  double rho = p.alpha_it_ratio;
+  ip.kappa1 = (float)(rho / (rho + 1.0));
+  ip.kappa2 = (float)(rho / (2.0 * rho + 1.0));
+  ip.init_centroid = p.init_centroid;
+  return ip;
+}
+
+bool scene_ok(const dem_scene* s) {
+  if (!s) return false;
+  if (s->precision != DEM_F32 && s->precision != DEM_F64) return false;
+  if (s->n_verts <= 0 || s->n_tris <= 0 || s->n_particles <= 0) return false;
+  if (s->n_levels_max < 1 || s->n_levels_max > DEM_MAX_LEVELS) return false;
+  if (!s->verts || !s->tri_verts || !s->child_begin || !s->child_count || !s->tri_particle ||
+      !s->tri_eps || !s->root_begin || !s->root_count || !s->fine_begin || !s->fine_count)
+    return false;
+  return true;
+}
+
+bool params_ok(const dem_params& p) {
+  if (p.mode != DEM_MODE_FLAT && p.mode != DEM_MODE_HIER) return false;
+  if (p.n_iter < 0 || p.n_iter > 64) return false;
+  if (!(p.omega > 0.0f) || !(p.alpha_reg_rel >= 0.0f) || !(p.alpha_it_ratio > 0.0f)) return false;
+  if (p.block < 64 || p.block > 256 || p.block % 64) return false;
+  if (p.batch_items < 1 || p.batch_items > p.block) return false;
+  if (p.flat_tile_i < 64 || p.flat_tile_i > 1024 || p.flat_tile_i % 64) return false;
+  if (p.flat_tile_j < 1 || p.flat_tile_j > 64) return false;
+  if (p.seed_chunk < 1 || p.seed_chunk > 16) return false;
+  if (p.queue_capacity < 1 || p.queue_capacity > (int64_t)0xFFFFFFFF) return false;
+  if (p.near_capacity < 1 || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
+  if (p.grid < 0) return false;
+  return true;
+}
+
+template <typename T>
+dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const dem_params& p,
+                    const dem_contacts* out, void* ws, const WsLayout& L, dem_stats* stats,
+                    uint32_t* status, double* energy, hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  Counters* ctr = reinterpret_cast<Counters*>(base + L.ctr);
+  SoupRec<T>* soup = reinterpret_cast<SoupRec<T>*>(base + L.soup);
+  int4* q[2] = {reinterpret_cast<int4*>(base + L.qa), reinterpret_cast<int4*>(base + L.qb)};
+  int2* nearl = reinterpret_cast<int2*>(base + L.near_);
+  const int grid = p.grid > 0 ? p.grid : 2048;
+
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctr, stats, status, out->count, energy);
+  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + 255) / 256), dim3(256), 0, st,
+                     static_cast<const T*>(s->verts), s->n_verts, s->tri_verts, s->n_tris,
+                     s->child_begin, s->child_count, s->tri_particle,
+                     static_cast<const T*>(s->tri_eps), T(p.alpha_reg_rel), soup, status);
+  LevelArgs la;
+  la.qcap = p.queue_capacity;
+  la.near_ = nearl;
+  la.near_tail = &ctr->near_tail;
+  la.ncap = p.near_capacity;
+  la.stats = stats;
+  la.status = status;
+  la.dense = p.dense_distance;
+  la.batch = p.batch_items;
+  la.ip = make_iter(p);
+  if (n_pairs > 0) {
+    if (p.mode == DEM_MODE_HIER) {
+      hipLaunchKernelGGL(k_seed, dim3(n_pairs), dim3(256), 0, st, pairs, n_pairs, s->root_begin,
+                         s->root_count, p.seed_chunk, p.seed_chunk, q[0], &ctr->tail[0],
+                         p.queue_capacity, status);
+      for (int lev = 0; lev < s->n_levels_max; ++lev) {
+        la.qin = q[lev & 1];
+        la.tail_in = &ctr->tail[lev];
+        la.head_in = &ctr->head[lev];
+        la.qout = q[(lev + 1) & 1];
+        la.tail_out = &ctr->tail[lev + 1];
+        la.depth = lev;
+        hipLaunchKernelGGL(k_level<T>, dim3(grid), dim3(p.block), 0, st, soup, la);
+      }
+    } else {
+      hipLaunchKernelGGL(k_seed, dim3(n_pairs), dim3(256), 0, st, pairs, n_pairs, s->fine_begin,
+                         s->fine_count, p.flat_tile_i, p.flat_tile_j, q[0], &ctr->tail[0],
+                         p.queue_capacity, status);
+      la.qin = q[0];
+      la.tail_in = &ctr->tail[0];
+      la.head_in = &ctr->head[0];
+      la.qout = q[1];
+      la.tail_out = &ctr->tail[1];
+      la.depth = 0;
+      hipLaunchKernelGGL((k_flat<T, 64>), dim3(grid), dim3(p.flat_tile_i > 256 ? 256 : p.flat_tile_i),
+                         0, st, soup, la);
+    }
+  }
+  NearArgs na;
+  na.near_ = nearl;
+  na.near_tail = &ctr->near_tail;
+  na.ncap = p.near_capacity;
+  na.pi = out->pi; na.pj = out->pj; na.ti = out->ti; na.tj = out->tj;
+  na.d = out->d; na.x = out->x; na.n = out->n;
+  na.count = out->count;
+  na.ccap = out->capacity;
+  na.dense = p.dense_distance;
+  na.k = p.energy_k;
+  na.energy = energy;
+  na.stats = stats;
+  na.status = status;
+  hipLaunchKernelGGL(k_near<T>, dim3(grid), dim3(p.block), 0, st, soup, na);
+  return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dem_default_params(dem_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->mode = DEM_MODE_HIER;
+  p->n_iter = 4;
+  p->omega = 1.0f;
+  p->alpha_reg_rel = 1e-4f;
+  p->alpha_it_ratio = 1e3f;
+  p->init_centroid = 0;
+  p->dense_distance = 0;
+  p->certify = 0;
+  p->energy_k = 1e4;
+  p->block = 256;
+  p->grid = 0;
+  p->batch_items = 64;
+  p->flat_tile_i = 256;
+  p->flat_tile_j = 64;
+  p->seed_chunk = 16;
+  p->queue_capacity = 1 << 22;
+  p->near_capacity = 1 << 22;
+}
+
+size_t dem_workspace_bytes(const dem_scene* scene, int32_t n_pairs, const dem_params* pp) {
+  dem_params p;
+  if (pp) p = *pp; else dem_default_params(&p);
+  if (!scene_ok(scene) || !params_ok(p) || n_pairs < 0) return 0;
+  return ws_layout(scene->precision, scene->n_tris, p.queue_capacity, p.near_capacity).total;
+}
+
+dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
+                             const dem_params* pp, const dem_contacts* out, void* workspace,
+                             size_t workspace_bytes, dem_stats* dev_stats, uint32_t* dev_status,
+                             double* dev_energy, dem_stream_t stream) {
+  dem_params p;
+  if (pp) p = *pp; else dem_default_params(&p);
+  if (!scene_ok(scene) || !params_ok(p)) return DEM_ERR_ARG;
+  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return DEM_ERR_ARG;
+  if (!out || !out->count || out->capacity < 0 || out->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
+  if (out->capacity > 0 && (!out->pi || !out->pj || !out->ti || !out->tj || !out->d || !out->x || !out->n))
+    return DEM_ERR_ARG;
+  if (!workspace || !dev_status) return DEM_ERR_ARG;
+  WsLayout L = ws_layout(scene->precision, scene->n_tris, p.queue_capacity, p.near_capacity);
+  if (workspace_bytes < L.total) return DEM_ERR_CAPACITY;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (scene->precision == DEM_F64)
+    return run_find<double>(scene, pairs, n_pairs, p, out, workspace, L, dev_stats, dev_status,
+                            dev_energy, st);
+  return run_find<float>(scene, pairs, n_pairs, p, out, workspace, L, dev_stats, dev_status,
+                         dev_energy, st);
+}
+
+dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* c, double k,
+                                const double* grad_E, void* grad_verts, double* energy_out,
+                                uint32_t* dev_status, dem_stream_t stream) {
+  if (!scene_ok(scene) || !c || !c->count || !c->ti || !c->tj || !dev_status) return DEM_ERR_ARG;
+  if (!grad_verts && !energy_out) return DEM_ERR_ARG;
+  if (!(k >= 0.0)) return DEM_ERR_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (energy_out) hipLaunchKernelGGL(k_zero_scalar, dim3(1), dim3(64), 0, st, energy_out);
+  const int grid = 1024;
+  if (scene->precision == DEM_F64) {
+    hipLaunchKernelGGL(k_backward<double>, dim3(grid), dim3(256), 0, st,
+                         static_cast<const double*>(scene->verts), scene->n_verts, scene->tri_verts,
+                         scene->n_tris, static_cast<const double*>(scene->tri_eps), c->ti, c->tj,
+                         c->count, c->capacity, k, grad_E, static_cast<double*>(grad_verts),
+                         energy_out, dev_status);
+  } else {
+    hipLaunchKernelGGL(k_backward<float>, dim3(grid), dim3(256), 0, st,
+                         static_cast<const float*>(scene->verts), scene->n_verts, scene->tri_verts,
+                         scene->n_tris, static_cast<const float*>(scene->tri_eps), c->ti, c->tj,
+                         c->count, c->capacity, k, grad_E, static_cast<float*>(grad_verts),
+                         energy_out, dev_status);
+  }
+  return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
+const char* dem_status_string(dem_status s) {
+  switch (s) {
+    case DEM_OK: return "ok";
+    case DEM_ERR_ARG: return "invalid argument";
+    case DEM_ERR_CAPACITY: return "workspace too small";
+    case DEM_ERR_HIP: return "HIP error";
+    case DEM_ERR_NOT_CONSERVATIVE: return "hierarchy violates the surrogate-tree rules";
+    case DEM_ERR_OOM: return "host allocation failed";
+  }
+  return "unknown status";
+}
+
+const char* dem_version(void) { return "dem 0.1 gfx950"; }
+
+}  // extern "C"

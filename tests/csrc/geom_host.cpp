@@ -1,0 +1,64 @@
+// Test harness: host build of the product's triangle geometry
+// (paper_2105_12415_amd/csrc/dem_geom.hpp) so CPU tests can compare it with
+// the FP64 oracle before any kernel runs.  Not part of the library.
+#include "dem_geom.hpp"
+
+using namespace dem;
+
+template <typename T>
+static void exact_one(const double* P, double* out) {
+  V3<T> a0{(T)P[0], (T)P[1], (T)P[2]}, a1{(T)P[3], (T)P[4], (T)P[5]}, a2{(T)P[6], (T)P[7], (T)P[8]};
+  V3<T> b0{(T)P[9], (T)P[10], (T)P[11]}, b1{(T)P[12], (T)P[13], (T)P[14]}, b2{(T)P[15], (T)P[16], (T)P[17]};
+  V3<T> D0 = a0 - b0;
+  Closest<T> c;
+  exact_tri_tri(V3<T>{0, 0, 0}, a1 - a0, a2 - a0, -D0, b1 - b0, b2 - b0, c);
+  out[0] = (double)sq_(c.d2);
+  out[1] = c.p.x + (double)a0.x; out[2] = c.p.y + (double)a0.y; out[3] = c.p.z + (double)a0.z;
+  out[4] = c.q.x + (double)a0.x; out[5] = c.q.y + (double)a0.y; out[6] = c.q.z + (double)a0.z;
+  for (int k = 0; k < 3; ++k) { out[7 + k] = c.wp[k]; out[10 + k] = c.wq[k]; }
+  out[13] = c.feature;
+}
+
+template <typename T>
+static void bound_one(const double* P, const float* prm, double* out) {
+  V3<T> a0{(T)P[0], (T)P[1], (T)P[2]}, a1{(T)P[3], (T)P[4], (T)P[5]}, a2{(T)P[6], (T)P[7], (T)P[8]};
+  V3<T> b0{(T)P[9], (T)P[10], (T)P[11]}, b1{(T)P[12], (T)P[13], (T)P[14]}, b2{(T)P[15], (T)P[16], (T)P[17]};
+  Tri<T> A, B;
+  A.v0 = a0; A.e1 = a1 - a0; A.e2 = a2 - a0; A.eps = 0;
+  B.v0 = b0; B.e1 = b1 - b0; B.e2 = b2 - b0; B.eps = 0;
+  T areg = (T)prm[2];
+  T n1 = dot(A.e1, A.e1), n2 = dot(A.e2, A.e2);
+  T r = areg * T(0.5) * (n1 + n2);
+  A.ia = T(1) / (n1 + r); A.ib = T(1) / (n2 + r);
+  n1 = dot(B.e1, B.e1); n2 = dot(B.e2, B.e2);
+  r = areg * T(0.5) * (n1 + n2);
+  B.ia = T(1) / (n1 + r); B.ib = T(1) / (n2 + r);
+  IterParams ip;
+  ip.n_iter = (int)prm[0];
+  ip.omega = prm[1];
+  double rho = prm[3];
+  ip.kappa1 = (float)(rho / (rho + 1.0));
+  ip.kappa2 = (float)(rho / (2.0 * rho + 1.0));
+  ip.init_centroid = (int)prm[4];
+  V3<T> D0 = A.v0 - B.v0;
+  T th[4], up;
+  T L = iterate_and_bound(A, B, D0, ip, th, &up);
+  out[0] = L;
+  out[1] = bound_slack(A, B, D0, T(0));
+  out[2] = up;
+  for (int k = 0; k < 4; ++k) out[3 + k] = th[k];
+}
+
+extern "C" void geom_exact(const double* pairs, long n, int use_double, double* out) {
+  for (long i = 0; i < n; ++i) {
+    if (use_double) exact_one<double>(pairs + 18 * i, out + 14 * i);
+    else exact_one<float>(pairs + 18 * i, out + 14 * i);
+  }
+}
+
+extern "C" void geom_bound(const double* pairs, long n, int use_double, const float* prm, double* out) {
+  for (long i = 0; i < n; ++i) {
+    if (use_double) bound_one<double>(pairs + 18 * i, prm, out + 7 * i);
+    else bound_one<float>(pairs + 18 * i, prm, out + 7 * i);
+  }
+}

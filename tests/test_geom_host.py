@@ -1,0 +1,49 @@
+"""CPU checks of the product's triangle geometry (dem_geom.hpp compiled for
+the host) against the FP64 oracle: exact distances and the conservativeness
+of the iteration's lower bound, in FP64 and FP32."""
+import numpy as np
+import pytest
+
+import host_geom
+import oracle
+import scenegen as sg
+
+
+def _h(P):
+    e = lambda X: np.linalg.norm(X - np.roll(X, 1, 1), axis=2).max(1)
+    return np.maximum(e(P[:, 0]), e(P[:, 1]))
+
+
+def _cases():
+    P = sg.random_triangle_pairs(60000, seed=21)
+    rng = np.random.default_rng(22)
+    A = rng.uniform(-1, 1, (20000, 3, 3))
+    B = A + rng.normal(0, 1e-3, A.shape) + rng.normal(0, 0.05, (20000, 1, 3))  # near parallel
+    C = sg.random_triangle_pairs(20000, seed=23, scale=0.05, spread=0.2) + 20.0  # far from origin
+    return np.concatenate([P, np.stack([A, B], 1), C.astype(np.float32).astype(np.float64)])
+
+
+@pytest.mark.parametrize("double,r,a", [(True, 1e-12, 1e-13), (False, 1e-5, 1e-6)])
+def test_exact_distance_matches_oracle(double, r, a):
+    P = _cases()
+    ref = oracle.tri_tri_batch(P)
+    got = host_geom.exact(P, double)
+    err = np.abs(got["d"] - ref["d"]) - (r * ref["d"] + a * _h(P))
+    assert np.all(err <= 0), np.max(err)
+    # returned points realise the returned distance and sit on their triangles
+    assert np.allclose(np.linalg.norm(got["p2"] - got["p1"], axis=1), got["d"],
+                       atol=(1e-12 if double else 1e-5) * (1 + _h(P)))
+    assert np.all(got["w1"] >= -1e-6) and np.allclose(got["w1"].sum(1), 1, atol=1e-5)
+
+
+@pytest.mark.parametrize("double", [True, False])
+@pytest.mark.parametrize("n_iter,omega,centroid", [(4, 1.0, 0), (4, 0.5, 1), (0, 1.0, 0), (8, 0.7, 0)])
+def test_lower_bound_never_exceeds_distance(double, n_iter, omega, centroid):
+    """The pruning test L > delta + slack is safe: L - slack <= d always."""
+    P = _cases()
+    ref = oracle.tri_tri_batch(P)
+    b = host_geom.bound(P, double, n_iter=n_iter, omega=omega, centroid=centroid)
+    assert np.all(b["L"] - b["slack"] <= ref["d"])
+    # the bound is informative for well separated pairs
+    far = ref["d"] > _h(P)
+    assert np.mean(b["L"][far] > 0.5 * ref["d"][far]) > 0.9
