@@ -1,0 +1,299 @@
+#!/usr/bin/env python3
+"""Benchmark of the multiresolution contact-detection path on one MI355X.
+
+Default workload (``--config 5``): the 1000-sphere lattice (subdivision 3-5,
+radii log-uniform in [0.5, 2], gaps U(0, 0.1); FP32), forward + backward of
+the penalty contact energy k * sum max(0, delta - d)^2, k = 1e4, with a
+seeded rigid perturbation of every particle per step; K steps are captured
+in one HIP graph and replayed.  Configs 1-4 (forward only) are selectable.
+
+One JSON line is printed: tri-pair evaluations per second of the
+hierarchical step (``value``), its ms per step, the plain all-pairs (flat)
+step on the same scene for comparison, the roofline of the dominant kernel
+(measured with HIP events recorded by the library around each launch), and
+the FP64 CPU oracle's rate on a bounded sample of candidate pairs.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tri-pair evals/s and contact fwd+bwd ms/step: hierarchical batched vs plain all-pairs"
+PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (unpacked FP32)
+PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def flops_per_eval(n_iter: int) -> int:
+    """Algorithmic FP32 operations of one iterate-and-bound evaluation
+    (FMA = 2), counted from the formulas: 84 per Newton iteration (residual
+    24, gradient 20, diagonal step 12, two penalty half-steps 28) plus 160
+    for the set-up, projection to the triangles, direction, the two support
+    functions and the rounding slack."""
+    return 84 * n_iter + 160
+
+
+FLATTEN_BYTES_PER_TRI = 12 + 16 + 64  # indices, per-triangle static data, soup record
+FLATTEN_BYTES_PER_VERT = 12
+
+
+def workload(cfg: int):
+    import scenegen as sg
+    if cfg == 1:
+        return sg.config1(), "two bumped unit spheres, subdivision 3 (1280 tris each), FP64, single level"
+    if cfg == 2:
+        return sg.config2(), "two bumped unit spheres, subdivision 5 (20480 tris each), levels s=3/4/5, FP32"
+    if cfg in (3, 5):
+        return sg.config3(), ("1000 bumped spheres on a 10x10x10 lattice, subdivision 3-5, radii logU[0.5,2], "
+                              "gaps U(0,0.1), full icosphere cascades, FP32")
+    if cfg == 4:
+        return sg.config4(), ("bumped sphere R=20 subdivision 7 (327680 tris) + 2000 R=0.5 subdivision-3 spheres "
+                              "on its surface, FP32")
+    raise SystemExit(f"unknown config {cfg}")
+
+
+class Step:
+    """One step: a seeded rigid perturbation of every particle (passed to the
+    library as per-particle poses, applied while flattening), then the
+    contact path (forward, and backward for the fwd+bwd workload)."""
+
+    def __init__(self, ds, eng, backward: bool, n_steps: int, torch):
+        import scenegen as sg
+        self.ds, self.eng, self.backward = ds, eng, backward
+        P = ds.n_particles
+        centres = np.array([p.centre for p in ds.scene.particles])
+        Rs, ts = sg.rigid_perturbations(P, max(n_steps, 1))
+        # world = c + R (v - c) + t = R v + (c + t - R c)
+        shift = centres + ts - np.einsum("kpij,pj->kpi", Rs, centres)
+        poses = np.concatenate([Rs.reshape(len(Rs), P, 9), shift], axis=2)
+        self.poses = torch.as_tensor(poses, device=ds.device, dtype=ds.dtype).contiguous()
+        self.grad = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device=ds.device)
+
+    def pose(self, k: int):
+        self.ds.set_pose(self.poses[k % len(self.poses)])
+
+    def __call__(self, k: int):
+        self.pose(k)
+        self.eng.forward(with_energy=True)
+        if self.backward:
+            self.grad.zero_()
+            self.eng.backward(self.grad)
+
+
+def time_graph(torch, step: Step, K: int, warmup: int):
+    """Capture K steps in one graph; returns (ms/step by events, by wall clock)."""
+    for w in range(warmup):
+        step(w)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(0)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for k in range(K):
+            step(k)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / K
+    return e0.elapsed_time(e1) / K, wall, g
+
+
+def kernel_times(torch, step: Step, K: int):
+    """Per-launch durations (ms) of dem_find_contacts' kernels, averaged over
+    K eager steps, from HIP events the library records between launches on
+    the step's stream; plus the backward call bracketed the same way."""
+    from paper_2105_12415_amd import _abi
+    eng = step.eng
+    n_ev = 8 + _abi.DEM_MAX_LEVELS
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
+    for e in evs:
+        e.record()  # materialise the underlying hipEvent
+    torch.cuda.synchronize()
+    handles = (C.c_void_p * n_ev)(*[C.c_void_p(e.cuda_event) for e in evs])
+    eng.p.events = C.cast(handles, C.POINTER(C.c_void_p))
+    eng.p.n_events = n_ev
+    n_launch = 3 + (eng.ds.n_levels_max if eng.p.mode == _abi.DEM_MODE_HIER else 1) + 1
+    acc = np.zeros(n_launch)
+    bwd = 0.0
+    evals = np.zeros(_abi.DEM_MAX_LEVELS)
+    stats_acc = None
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    try:
+        for k in range(K):
+            step.pose(k)
+            eng.forward(with_energy=True)
+            if step.backward:
+                step.grad.zero_()
+                b0.record()
+                eng.backward(step.grad)
+                b1.record()
+            torch.cuda.synchronize()
+            for i in range(n_launch):
+                acc[i] += evs[i].elapsed_time(evs[i + 1])
+            if step.backward:
+                bwd += b0.elapsed_time(b1)
+            st = eng.stats_dict()
+            if stats_acc is None:
+                stats_acc = {k2: (np.array(v, dtype=np.float64) if isinstance(v, np.ndarray) else float(v))
+                             for k2, v in st.items()}
+            else:
+                for k2, v in st.items():
+                    stats_acc[k2] = stats_acc[k2] + (np.array(v, dtype=np.float64) if isinstance(v, np.ndarray) else v)
+    finally:
+        eng.p.events = None
+        eng.p.n_events = 0
+    for k2 in stats_acc:
+        stats_acc[k2] = stats_acc[k2] / K
+    return acc / K, bwd / K, stats_acc
+
+
+def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capacity):
+    p = api.make_params(mode, **params_kw)
+    eng = api.ContactEngine(ds, p, contact_capacity=contact_capacity, energy_k=1e4)
+    step = Step(ds, eng, backward, K, torch)
+    # size the buffers on the first (eager) step: overflow triggers a regrow
+    step.pose(0)
+    eng.run()
+    status = eng.check()
+    if status:
+        raise RuntimeError(f"device status {status:#x}")
+    ms_graph, ms_wall, graph = time_graph(torch, step, K, warmup)
+    status = eng.check()
+    if status:
+        raise RuntimeError(f"device status {status:#x} after graph replay")
+    kt, bwd_ms, st = kernel_times(torch, step, K)
+    del graph
+    return eng, step, ms_graph, ms_wall, kt, bwd_ms, st
+
+
+def cpu_baseline(scene, n_sample: int, backward: bool):
+    import oracle
+    fs = oracle.fine_scene(scene)
+    rng = np.random.default_rng(12345)
+    n = min(n_sample, len(scene.pairs))
+    idx = np.sort(rng.choice(len(scene.pairs), n, replace=False))
+    P = np.asarray(scene.pairs)[idx]
+    F = fs.tri_count.astype(np.int64)
+    pairs_fine = int(np.sum(F[P[:, 0]] * F[P[:, 1]]))
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    c = oracle.find_contacts(fs, pairs=P, n_threads=threads)
+    if backward:
+        oracle.energy_grad(fs, c, 1e4, pairs=P)
+    dt = time.perf_counter() - t0
+    return {"value": pairs_fine / dt, "unit": "tri-pair evals/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{n} of {len(scene.pairs)} candidate particle pairs (seeded), {pairs_fine} fine "
+                       f"triangle pairs decided exactly in FP64 (flat all-pairs with exact bounding-sphere "
+                       f"rejection{', plus energy gradient' if backward else ''}) in {dt:.2f} s"),
+            "seconds": dt, "contacts": int(len(c["d"]))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--flat-steps", type=int, default=1)
+    ap.add_argument("--no-flat", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=60)
+    ap.add_argument("--contact-capacity", type=int, default=1 << 23)
+    ap.add_argument("--param", action="append", default=[], help="dem_params override, e.g. omega=0.5")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2105_12415_amd import api
+
+    params_kw = {}
+    for kv in args.param:
+        k, v = kv.split("=")
+        params_kw[k] = float(v) if "." in v or "e" in v else int(v)
+
+    scene, desc = workload(args.config)
+    backward = args.config == 5
+    ds = api.DeviceScene(scene, device="cuda:0")
+    K = args.steps
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    log(f"[bench] config {args.config}: {desc}; {ds.n_particles} particles, {ds.n_tris} triangles, "
+        f"{ds.n_pairs} candidate pairs, {ds.n_fine_pairs()} fine pairs")
+
+    eng, step, ms, ms_wall, kt, bwd_ms, st = run_mode(torch, api, ds, "hier", backward, K, args.warmup,
+                                                     params_kw, args.contact_capacity)
+    evals = float(np.sum(st["evals"]))
+    log(f"[bench] hier: {ms:.3f} ms/step (wall {ms_wall:.3f}), {evals:.4g} evals/step, "
+        f"{st['contacts']:.0f} contacts, near {st['near']:.0f}")
+    L = ds.n_levels_max
+    level_ms = float(np.sum(kt[3:3 + L]))
+    n_iter = eng.p.n_iter
+    fl = flops_per_eval(n_iter) * evals
+    dtype = "f64" if scene.dtype == "f64" else "f32"
+    peak = PEAK_FP64_VALU_TFLOPS if dtype == "f64" else PEAK_FP32_VALU_TFLOPS
+    achieved = fl / (level_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": f"k_level<{'double' if dtype == 'f64' else 'float'}>",
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "launches_per_step": L, "avg_launch_ms": level_ms / L,
+            "flops_per_eval": flops_per_eval(n_iter), "evals_per_step": evals,
+            "peak_published_packed_fp32": 157.3}
+    flat_bytes = FLATTEN_BYTES_PER_TRI * ds.n_tris + FLATTEN_BYTES_PER_VERT * ds.n_verts
+    kernels = {"reset_ms": kt[0], "flatten_ms": kt[1], "seed_ms": kt[2], "levels_ms": level_ms,
+               "levels_ms_each": [round(x, 4) for x in kt[3:3 + L]], "near_ms": kt[3 + L],
+               "backward_ms": bwd_ms if backward else None,
+               "flatten_GBs": flat_bytes / (kt[1] * 1e-3) / 1e9}
+    out = {"metric": METRIC, "value": evals / (ms * 1e-3), "unit": "tri-pair evals/s", "n_gpus": 1,
+           "steps": K, "warmup": args.warmup, "ms_per_step": ms, "ms_per_step_wall": ms_wall,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic",
+           "config": {"workload": f"config {args.config}: {desc}" + ("; forward + backward (k=1e4), "
+                      f"per-step rigid perturbation, {K} steps captured in one HIP graph" if backward else
+                      f"; forward contacts, {K} steps captured in one HIP graph"),
+                      "particles": ds.n_particles, "triangles_all_levels": ds.n_tris,
+                      "candidate_pairs": ds.n_pairs, "fine_pairs": ds.n_fine_pairs(), "n_iter": n_iter},
+           "roofline": roof, "kernels": kernels,
+           "stats": {"evals_per_level": [int(x) for x in st["evals"][:L]],
+                     "survivors_per_level": [int(x) for x in st["survivors"][:L]],
+                     "near": st["near"], "fallback": st["fallback"], "contacts": st["contacts"]}}
+    if not args.no_flat:
+        del eng, step
+        torch.cuda.empty_cache()
+        fe, fstep, fms, fwall, fkt, fbwd, fst = run_mode(torch, api, ds, "flat", backward, args.flat_steps,
+                                                       0, params_kw, args.contact_capacity)
+        fevals = float(np.sum(fst["evals"]))
+        out["flat"] = {"ms_per_step": fms, "ms_per_step_wall": fwall, "evals_per_step": fevals,
+                       "evals_per_s": fevals / (fms * 1e-3), "contacts": fst["contacts"],
+                       "flat_kernel_ms": float(fkt[3]), "near_ms": float(fkt[4]),
+                       "flat_kernel_TFLOPs": flops_per_eval(n_iter) * fevals / (fkt[3] * 1e-3) / 1e12}
+        out["speedup_vs_flat"] = fms / ms
+        log(f"[bench] flat: {fms:.2f} ms/step, {fevals:.4g} evals/step")
+        del fe, fstep
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_pairs, backward)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,13 @@ typedef struct {
   const int32_t* root_count;
   const int32_t* fine_begin;  /* [n_particles] fine (particle) triangles */
   const int32_t* fine_count;
+  /* Optional [n_particles][12] rigid motion per particle (row-major R, then
+   * c): the kernels use world = R v + c for the vertices v of verts, applied
+   * while flattening each step's triangle soup (Section 3, triangle soup:
+   * every coordinate undergoes the update's affine transformation).  NULL:
+   * verts already are world coordinates.  Gradients are always with respect
+   * to world positions. */
+  const void* pose;
 } dem_scene;
 
 /* ------------------------------------------------------------------ parameters */
@@ -176,6 +183,15 @@ typedef struct {
   int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges */
   int64_t queue_capacity; /* items per level queue */
   int64_t near_capacity;  /* fine pairs the lower bound could not prune */
+  /* Optional timing: an array of n_events hipEvent_t (host handles, created
+   * by the caller).  events[0] is recorded before the first kernel launch of
+   * dem_find_contacts and events[k] right after its k-th launch, in launch
+   * order: reset, flatten, seed, then one launch per tree depth (HIER) or
+   * the flat tile kernel (FLAT), then the near-pair kernel.  Launches beyond
+   * n_events - 1 are not bracketed.  NULL / 0 disables (use that when the
+   * call is captured into a graph). */
+  void* const* events;
+  int32_t n_events;
 } dem_params;
 
 /* Fill p with the defaults (N_it = 4, HIER mode, certify on). */
@@ -241,21 +257,29 @@ dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32
  * dem_contact_backward -- adjoint of the penalty contact energy
  * E = k * sum over contacts of max(0, delta - d)^2 (delta = eps_i + eps_j).
  *
- * The closest points are recomputed for each contact (nothing is stored by
- * the forward call); with u = (p_j - p_i) / d and barycentric weights w_i,
- * w_j of the closest points, dE/dv = +2k (delta - d) w_i u for the vertices
- * of t_i and -2k (delta - d) w_j u for those of t_j (envelope theorem: d
- * is a minimum over the two triangles).  Intersecting pairs (d = 0) add
- * energy but no gradient.
+ * The closest points are recomputed for each contact (nothing but the
+ * contact's triangle pair is kept from the forward call); with
+ * u = (p_j - p_i) / d and barycentric weights w_i, w_j of the closest
+ * points, dE/dv = +2k (delta - d) w_i u for the vertices of t_i and
+ * -2k (delta - d) w_j u for those of t_j (envelope theorem: d is a minimum
+ * over the two triangles).  Intersecting pairs (d = 0) add energy but no
+ * gradient.
  *
  * contacts   the output of dem_find_contacts (device count is read on device).
  * grad_E     device double scalar multiplying the gradient, or NULL for 1.
- * grad_verts device [3][n_verts], ACCUMULATED into (caller zeroes it).
+ * grad_verts device [3][n_verts] with respect to world positions,
+ *            ACCUMULATED into (caller zeroes it); NULL for energy only.
  * energy_out device double or NULL: set to E.
+ * workspace  the workspace of the dem_find_contacts call that produced
+ *            `contacts`, unchanged since, with the scene's verts and pose
+ *            unchanged: the triangle soup flattened there is reused.
+ *            Needs workspace_bytes >= the soup's end (any size
+ *            dem_workspace_bytes returned for this scene suffices).
  * dev_status device uint32: DEM_DEV_* bits are OR-ed in (not cleared).
  */
 dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* contacts, double k,
                                 const double* grad_E, void* grad_verts, double* energy_out,
+                                const void* workspace, size_t workspace_bytes,
                                 uint32_t* dev_status, dem_stream_t stream);
 
 const char* dem_status_string(dem_status s);

@@ -46,7 +46,7 @@ class Scene(C.Structure):
                 ("verts", C.c_void_p), ("tri_verts", C.c_void_p), ("child_begin", C.c_void_p),
                 ("child_count", C.c_void_p), ("tri_particle", C.c_void_p), ("tri_eps", C.c_void_p),
                 ("root_begin", C.c_void_p), ("root_count", C.c_void_p),
-                ("fine_begin", C.c_void_p), ("fine_count", C.c_void_p)]
+                ("fine_begin", C.c_void_p), ("fine_count", C.c_void_p), ("pose", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -55,7 +55,8 @@ class Params(C.Structure):
                 ("init_centroid", C.c_int32), ("dense_distance", C.c_int32), ("certify", C.c_int32),
                 ("energy_k", C.c_double), ("block", C.c_int32), ("grid", C.c_int32),
                 ("batch_items", C.c_int32), ("flat_tile_i", C.c_int32), ("flat_tile_j", C.c_int32),
-                ("seed_chunk", C.c_int32), ("queue_capacity", C.c_int64), ("near_capacity", C.c_int64)]
+                ("seed_chunk", C.c_int32), ("queue_capacity", C.c_int64), ("near_capacity", C.c_int64),
+                ("events", C.POINTER(C.c_void_p)), ("n_events", C.c_int32)]
 
 
 class Contacts(C.Structure):
@@ -101,7 +102,7 @@ def lib():
                                         C.POINTER(Contacts), vp, C.c_size_t, vp, vp, vp, vp]
         L.dem_find_contacts.restype = C.c_int
         L.dem_contact_backward.argtypes = [C.POINTER(Scene), C.POINTER(Contacts), C.c_double, vp, vp,
-                                           vp, vp, vp]
+                                           vp, vp, C.c_size_t, vp, vp]
         L.dem_contact_backward.restype = C.c_int
         L.dem_status_string.argtypes = [C.c_int]
         L.dem_status_string.restype = C.c_char_p

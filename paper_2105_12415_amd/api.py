@@ -125,6 +125,7 @@ class DeviceScene:
             raise DemError("candidate pairs must join two different existing particles")
         self.pairs = i32(self.pairs_host.T.copy())  # (2, P)
         self.coord_scale = coord_scale
+        self.pose = None
         self._refresh()
 
     def _refresh(self):
@@ -140,12 +141,21 @@ class DeviceScene:
         s.tri_eps = self.tri_eps.data_ptr()
         s.root_begin, s.root_count = self.root_begin.data_ptr(), self.root_count.data_ptr()
         s.fine_begin, s.fine_count = self.fine_begin.data_ptr(), self.fine_count.data_ptr()
+        s.pose = None if self.pose is None else self.pose.data_ptr()
         self.c = s
 
     def set_verts(self, verts: torch.Tensor):
         """Point the scene at another (3, V) tensor of the scene's dtype."""
         assert verts.shape == (3, self.n_verts) and verts.dtype == self.dtype and verts.is_contiguous()
         self.verts = verts
+        self._refresh()
+
+    def set_pose(self, pose: Optional[torch.Tensor]):
+        """Per-particle rigid motion (n_particles, 12) = row-major R then c,
+        applied in the flatten kernel (world = R v + c); None disables."""
+        if pose is not None:
+            assert pose.shape == (self.n_particles, 12) and pose.dtype == self.dtype and pose.is_contiguous()
+        self.pose = pose
         self._refresh()
 
     @property
@@ -254,7 +264,8 @@ class ContactEngine:
         cs = self.contacts.c()
         st = lib().dem_contact_backward(C.byref(self.ds.c), C.byref(cs), float(self.p.energy_k),
                                         _ptr(grad_E), _ptr(grad_verts),
-                                        _ptr(self.energy_bwd) if energy else None, _ptr(self.status),
+                                        _ptr(self.energy_bwd) if energy else None,
+                                        C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.status),
                                         self._stream())
         check(st, "dem_contact_backward")
 

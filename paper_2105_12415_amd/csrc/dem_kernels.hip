@@ -148,7 +148,8 @@ __global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, in
                                                  const int32_t* __restrict__ cbeg,
                                                  const int32_t* __restrict__ ccnt,
                                                  const int32_t* __restrict__ tpart,
-                                                 const T* __restrict__ teps, T areg_rel,
+                                                 const T* __restrict__ teps,
+                                                 const T* __restrict__ pose, T areg_rel,
                                                  SoupRec<T>* __restrict__ soup, uint32_t* status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tris) return;
@@ -160,6 +161,16 @@ __global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, in
   V3<T> v1 = {X[i1], Y[i1], Z[i1]};
   V3<T> v2 = {X[i2], Y[i2], Z[i2]};
   V3<T> e1 = v1 - v0, e2 = v2 - v0;
+  const int part = tpart[t];
+  if (pose) {
+    // rigid motion of the particle applied while flattening: world = R v + c
+    const T* P = pose + 12 * (size_t)part;
+    V3<T> r0 = {P[0], P[1], P[2]}, r1 = {P[3], P[4], P[5]}, r2 = {P[6], P[7], P[8]};
+    V3<T> c = {P[9], P[10], P[11]};
+    v0 = V3<T>{dot(r0, v0), dot(r1, v0), dot(r2, v0)} + c;
+    e1 = V3<T>{dot(r0, e1), dot(r1, e1), dot(r2, e1)};
+    e2 = V3<T>{dot(r0, e2), dot(r1, e2), dot(r2, e2)};
+  }
   T n1 = dot(e1, e1), n2 = dot(e2, e2);
   T areg = areg_rel * T(0.5) * (n1 + n2);
   T ia = T(1) / (n1 + areg), ib = T(1) / (n2 + areg);
@@ -167,9 +178,9 @@ __global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, in
   r.g[0] = v0.x; r.g[1] = v0.y; r.g[2] = v0.z; r.g[3] = teps[t];
   r.g[4] = e1.x; r.g[5] = e1.y; r.g[6] = e1.z; r.g[7] = ia;
   r.g[8] = e2.x; r.g[9] = e2.y; r.g[10] = e2.z; r.g[11] = ib;
-  r.topo[0] = cbeg[t]; r.topo[1] = ccnt[t]; r.topo[2] = tpart[t]; r.topo[3] = 0;
+  r.topo[0] = cbeg[t]; r.topo[1] = ccnt[t]; r.topo[2] = part; r.topo[3] = 0;
   soup[t] = r;
-  T chk = v0.x + v0.y + v0.z + v1.x + v1.y + v1.z + v2.x + v2.y + v2.z;
+  T chk = v0.x + v0.y + v0.z + e1.x + e1.y + e1.z + e2.x + e2.y + e2.z;
   if (!isfinite(chk)) atomicOr(status, DEM_DEV_NONFINITE);
 }
 
@@ -247,19 +258,63 @@ struct LevelArgs {
   IterParams ip;
 };
 
+// Block-local append buffer in LDS: lanes reserve slots with one LDS atomic
+// per wave; the block flushes the buffer to the global queue with a single
+// global atomic (same-address global atomics serialise in L2, so one per
+// wave per evaluation round would dominate the descent).
+template <typename R, int CAP>
+struct LdsQueue {
+  R buf[CAP];
+  uint32_t n;
+  uint32_t gbase;
+};
+
+template <typename R>
+__device__ __forceinline__ void lds_append(bool pred, R rec, R* buf, uint32_t* n) {
+  unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(n, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  unsigned long long lt = (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
+  if (pred) buf[base + (uint32_t)__popcll(m & lt)] = rec;
+}
+
+// Copy an LDS queue to global memory at a reserved range (whole block).
+template <typename R, int CAP>
+__device__ __forceinline__ void lds_flush(LdsQueue<R, CAP>& q, uint32_t* tail, R* out, int64_t cap,
+                                          uint32_t* status, uint32_t flag) {
+  if (threadIdx.x == 0) q.gbase = q.n ? atomicAdd(tail, q.n) : 0u;
+  __syncthreads();
+  const uint32_t n = q.n, g = q.gbase;
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+    uint64_t slot = (uint64_t)g + k;
+    if (slot < (uint64_t)cap) out[slot] = q.buf[k];
+    else atomicOr(status, flag);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) q.n = 0;
+  __syncthreads();
+}
+
+constexpr int kStageItems = 512;
+constexpr int kStageNear = 512;
+constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between checks
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
   __shared__ int4 items[256];
   __shared__ int offs[257];
   __shared__ int wsum[16];
-  __shared__ uint32_t sh_base;
+  __shared__ LdsQueue<int4, kStageItems> qi;
+  __shared__ LdsQueue<int2, kStageNear> qn;
   const uint32_t count = min((uint64_t)*a.tail_in, (uint64_t)a.qcap);
+  const uint32_t bdim = blockDim.x;
   unsigned long long my_evals = 0, my_surv = 0, my_near = 0;
-  for (;;) {
-    if (threadIdx.x == 0) sh_base = atomicAdd(a.head_in, (uint32_t)a.batch);
-    __syncthreads();
-    uint32_t b = sh_base;
-    if (b >= count) break;
+  if (threadIdx.x == 0) { qi.n = 0; qn.n = 0; }
+  // static grid-stride over batches of items (items carry similar work)
+  for (uint32_t b = blockIdx.x * (uint32_t)a.batch; b < count; b += gridDim.x * (uint32_t)a.batch) {
     int n = (int)min((uint32_t)a.batch, count - b);
     int np = 0;
     if ((int)threadIdx.x < n) {
@@ -269,53 +324,60 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
     }
     block_scan(np, offs, wsum, n);
     const int total = offs[n];
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      // item owning flat index e: last k with offs[k] <= e
-      int lo = 0, hi = n - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (offs[mid] <= e) lo = mid; else hi = mid - 1;
-      }
-      int4 it = items[lo];
-      int l = e - offs[lo];
-      int jn = it.w;
-      int qd = (int)((float)l * (1.0f / (float)jn));
-      int rr = l - qd * jn;
-      if (rr < 0) { qd -= 1; rr += jn; }
-      if (rr >= jn) { qd += 1; rr -= jn; }
-      int ci = it.x + qd, cj = it.z + rr;
-      int cbi, cci, pi_, cbj, ccj, pj_;
-      Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
-      Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_);
-      V3<T> D0 = A.v0 - B.v0;
-      T th[4], up;
-      T L = iterate_and_bound(A, B, D0, a.ip, th, &up);
-      T delta = A.eps + B.eps;
-      bool fine = (cci == 0) && (ccj == 0);
-      bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
-      ++my_evals;
-      // surrogate survivors -> next depth (only the non-fine side unfolds)
-      uint32_t ok;
-      bool push_item = keep && !fine;
-      uint32_t slot = wave_append(push_item, a.tail_out, ok);
-      if (ok) {
-        int4 nx;
+    for (int base = 0; base < total; base += bdim) {
+      const int e = base + (int)threadIdx.x;
+      bool push_item = false, push_near = false;
+      int4 nx = make_int4(0, 0, 0, 0);
+      int ci = 0, cj = 0;
+      if (e < total) {
+        // item owning flat index e: last k with offs[k] <= e
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (offs[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        int4 it = items[lo];
+        int l = e - offs[lo];
+        int jn = it.w;
+        int qd = (int)((float)l * (1.0f / (float)jn));
+        int rr = l - qd * jn;
+        if (rr < 0) { qd -= 1; rr += jn; }
+        if (rr >= jn) { qd += 1; rr -= jn; }
+        ci = it.x + qd;
+        cj = it.z + rr;
+        int cbi, cci, pi_, cbj, ccj, pj_;
+        Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
+        Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_);
+        V3<T> D0 = A.v0 - B.v0;
+        T th[4], up;
+        T L = iterate_and_bound(A, B, D0, a.ip, th, &up);
+        T delta = A.eps + B.eps;
+        bool fine = (cci == 0) && (ccj == 0);
+        bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
+        ++my_evals;
+        // surrogate survivors unfold into the next depth's item (only the
+        // non-fine side unfolds); fine survivors go to the near list
+        push_item = keep && !fine;
+        push_near = keep && fine;
         nx.x = cci ? cbi : ci; nx.y = cci ? cci : 1;
         nx.z = ccj ? cbj : cj; nx.w = ccj ? ccj : 1;
-        if (slot < (uint64_t)a.qcap) a.qout[slot] = nx;
-        else atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
-        ++my_surv;
+        my_surv += push_item;
+        my_near += push_near;
       }
-      bool push_near = keep && fine;
-      slot = wave_append(push_near, a.near_tail, ok);
-      if (ok) {
-        if (slot < (uint64_t)a.ncap) a.near_[slot] = make_int2(ci, cj);
-        else atomicOr(a.status, DEM_DEV_NEAR_OVERFLOW);
-        ++my_near;
-      }
+      lds_append(push_item, nx, qi.buf, &qi.n);
+      lds_append(push_near, make_int2(ci, cj), qn.buf, &qn.n);
+      __syncthreads();
+      // flush when another round could overflow the stage (uniform test)
+      if (qi.n + bdim > (uint32_t)kStageItems)
+        lds_flush(qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
+      if (qn.n + bdim > (uint32_t)kStageNear)
+        lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
     }
     __syncthreads();
   }
+  __syncthreads();
+  lds_flush(qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
+  lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
   if (a.stats) {
     // one atomic per wave
     unsigned long long s0 = my_evals, s1 = my_surv, s2 = my_near;
@@ -337,20 +399,21 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
 template <typename T, int TJ>
 __global__ void __launch_bounds__(256) k_flat(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
   __shared__ SoupRec<T> tj_s[TJ];
-  __shared__ uint32_t sh_base;
+  __shared__ LdsQueue<int2, kStageFlat> qn;
   const uint32_t count = min((uint64_t)*a.tail_in, (uint64_t)a.qcap);
+  const uint32_t bdim = blockDim.x;
   unsigned long long my_evals = 0, my_near = 0;
-  for (;;) {
-    if (threadIdx.x == 0) sh_base = atomicAdd(a.head_in, 1u);
-    __syncthreads();
-    uint32_t b = sh_base;
-    if (b >= count) break;
+  if (threadIdx.x == 0) qn.n = 0;
+  __syncthreads();
+  for (uint32_t b = blockIdx.x; b < count; b += gridDim.x) {
     int4 it = a.qin[b];
     // stage the j-triangles in LDS
-    for (int k = threadIdx.x; k < it.w; k += blockDim.x) tj_s[k] = soup[it.z + k];
+    for (int k = threadIdx.x; k < it.w; k += bdim) tj_s[k] = soup[it.z + k];
     __syncthreads();
-    for (int r = threadIdx.x; r < it.y; r += blockDim.x) {
-      int ci = it.x + r;
+    for (int r0 = 0; r0 < it.y; r0 += bdim) {
+      const int r = r0 + (int)threadIdx.x;
+      const bool act = r < it.y;
+      const int ci = it.x + (act ? r : 0);
       int cbi, cci, pi_;
       Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
       for (int k = 0; k < it.w; ++k) {
@@ -360,19 +423,21 @@ __global__ void __launch_bounds__(256) k_flat(const SoupRec<T>* __restrict__ sou
         T th[4], up;
         T L = iterate_and_bound(A, B, D0, a.ip, th, &up);
         T delta = A.eps + B.eps;
-        bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
-        ++my_evals;
-        uint32_t ok;
-        uint32_t slot = wave_append(keep, a.near_tail, ok);
-        if (ok) {
-          if (slot < (uint64_t)a.ncap) a.near_[slot] = make_int2(ci, it.z + k);
-          else atomicOr(a.status, DEM_DEV_NEAR_OVERFLOW);
-          ++my_near;
+        bool keep = act && (a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta)));
+        my_evals += act;
+        my_near += keep;
+        lds_append(keep, make_int2(ci, it.z + k), qn.buf, &qn.n);
+        if (k % 4 == 3 || k == it.w - 1) {
+          // at most 4 * bdim appends since the last check
+          __syncthreads();
+          if (qn.n + 4 * bdim > (uint32_t)kStageFlat)
+            lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
         }
       }
     }
     __syncthreads();
   }
+  lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
   if (a.stats) {
     unsigned long long s0 = my_evals, s2 = my_near;
 #pragma unroll
@@ -408,68 +473,97 @@ struct NearArgs {
 };
 
 template <typename T>
+struct ContactRec {
+  int32_t pi, pj, ti, tj;
+  T d, x[3], n[3];
+};
+
+constexpr int kStageContacts = 512;
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
+  __shared__ LdsQueue<ContactRec<T>, kStageContacts> qc;
   const uint32_t cnt = min((uint64_t)*a.near_tail, (uint64_t)a.ncap);
   T* dd = static_cast<T*>(a.d);
   T* xx = static_cast<T*>(a.x);
   T* nn = static_cast<T*>(a.n);
+  const uint32_t bdim = blockDim.x;
   double e_acc = 0.0;
   unsigned long long my_fb = 0, my_c = 0;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  // uniform trip count per wave so the wave-level appends see every lane
-  const uint32_t start = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t wave0 = start - (threadIdx.x % kWave);
-  for (uint32_t base = wave0; base < cnt; base += stride) {
-    uint32_t e = base + (threadIdx.x % kWave);
-    bool act = e < cnt;
+  if (threadIdx.x == 0) qc.n = 0;
+  __syncthreads();
+  for (uint32_t base = blockIdx.x * bdim; base < cnt; base += gridDim.x * bdim) {
+    const uint32_t e = base + threadIdx.x;
     bool emit = false;
-    T d = T(0);
-    V3<T> xc = {0, 0, 0}, nc = {0, 0, 0};
-    int ci = 0, cj = 0, pi_ = 0, pj_ = 0;
-    if (act) {
+    ContactRec<T> rec;
+    if (e < cnt) {
       int2 pr = a.near_[e];
-      ci = pr.x; cj = pr.y;
-      int cbi, cci, cbj, ccj;
-      Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
-      Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_);
+      int cbi, cci, cbj, ccj, pi_, pj_;
+      Tri<T> A = load_tri(soup, pr.x, cbi, cci, pi_);
+      Tri<T> B = load_tri(soup, pr.y, cbj, ccj, pj_);
       V3<T> D0 = A.v0 - B.v0;
       Closest<T> c;
       exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, c);
       ++my_fb;
-      d = sqrt(c.d2);
+      T d = sq_(c.d2);
       T delta = a.dense ? T(INFINITY) : A.eps + B.eps;
       emit = d <= delta;
       if (!isfinite(d)) atomicOr(a.status, DEM_DEV_NONFINITE);
-      if (emit) {
-        // contact point at the centre of the overlap of the two environments
-        V3<T> w = c.q - c.p;
-        T lam = d > T(0) ? (d + A.eps - B.eps) / (T(2) * d) : T(0);
-        V3<T> xl = fma3(lam, w, c.p);
-        nc = c.p - xl;
-        xc = xl + A.v0;
-        if (!a.dense) {
-          double pen = (double)delta - (double)d;
-          e_acc += a.k * pen * pen;
+      // contact point at the centre of the overlap of the two environments
+      V3<T> w = c.q - c.p;
+      T lam = d > T(0) ? (d + A.eps - B.eps) / (T(2) * d) : T(0);
+      V3<T> xl = fma3(lam, w, c.p);
+      V3<T> nc = c.p - xl;
+      V3<T> xc = xl + A.v0;
+      rec.pi = pi_; rec.pj = pj_; rec.ti = pr.x; rec.tj = pr.y; rec.d = d;
+      rec.x[0] = xc.x; rec.x[1] = xc.y; rec.x[2] = xc.z;
+      rec.n[0] = nc.x; rec.n[1] = nc.y; rec.n[2] = nc.z;
+      if (emit && !a.dense) {
+        double pen = (double)delta - (double)d;
+        e_acc += a.k * pen * pen;
+      }
+      my_c += emit;
+    }
+    lds_append(emit, rec, qc.buf, &qc.n);
+    __syncthreads();
+    if (qc.n + bdim > (uint32_t)kStageContacts) {
+      if (threadIdx.x == 0) qc.gbase = atomicAdd(a.count, qc.n);
+      __syncthreads();
+      for (uint32_t k = threadIdx.x; k < qc.n; k += bdim) {
+        uint64_t slot = (uint64_t)qc.gbase + k;
+        const ContactRec<T>& r = qc.buf[k];
+        if (slot < (uint64_t)a.ccap) {
+          a.pi[slot] = r.pi; a.pj[slot] = r.pj; a.ti[slot] = r.ti; a.tj[slot] = r.tj;
+          dd[slot] = r.d;
+          xx[slot] = r.x[0]; xx[a.ccap + slot] = r.x[1]; xx[2 * a.ccap + slot] = r.x[2];
+          nn[slot] = r.n[0]; nn[a.ccap + slot] = r.n[1]; nn[2 * a.ccap + slot] = r.n[2];
+        } else {
+          atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
         }
       }
+      __syncthreads();
+      if (threadIdx.x == 0) qc.n = 0;
+      __syncthreads();
     }
-    uint32_t ok;
-    uint32_t slot = wave_append(emit, a.count, ok);
-    if (ok) {
-      ++my_c;
-      if (slot < (uint64_t)a.ccap) {
-        a.pi[slot] = pi_; a.pj[slot] = pj_; a.ti[slot] = ci; a.tj[slot] = cj;
-        dd[slot] = d;
-        xx[slot] = xc.x; xx[a.ccap + slot] = xc.y; xx[2 * a.ccap + slot] = xc.z;
-        nn[slot] = nc.x; nn[a.ccap + slot] = nc.y; nn[2 * a.ccap + slot] = nc.z;
-      } else {
-        atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
-      }
+  }
+  // final flush
+  if (threadIdx.x == 0) qc.gbase = qc.n ? atomicAdd(a.count, qc.n) : 0u;
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < qc.n; k += bdim) {
+    uint64_t slot = (uint64_t)qc.gbase + k;
+    const ContactRec<T>& r = qc.buf[k];
+    if (slot < (uint64_t)a.ccap) {
+      a.pi[slot] = r.pi; a.pj[slot] = r.pj; a.ti[slot] = r.ti; a.tj[slot] = r.tj;
+      dd[slot] = r.d;
+      xx[slot] = r.x[0]; xx[a.ccap + slot] = r.x[1]; xx[2 * a.ccap + slot] = r.x[2];
+      nn[slot] = r.n[0]; nn[a.ccap + slot] = r.n[1]; nn[2 * a.ccap + slot] = r.n[2];
+    } else {
+      atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
     }
   }
   if (a.energy) {
-    double s = wave_sum(e_acc);
-    if (lane_id() == 0 && s != 0.0) atomicAdd(a.energy, s);
+    double sum = wave_sum(e_acc);
+    if (lane_id() == 0 && sum != 0.0) atomicAdd(a.energy, sum);
   }
   if (a.stats) {
     unsigned long long s0 = my_fb, s1 = my_c;
@@ -490,61 +584,103 @@ __device__ __forceinline__ void atomic_add_t(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
+// Gradient accumulation in LDS: contributions of a chunk of contacts are
+// summed per vertex in an open-addressing hash table before one global
+// atomic per (vertex, component) leaves the block.  Contacts arrive grouped
+// by the surrogate pair they descend from, so a chunk touches few distinct
+// vertices; scattered device-scope float atomics are the costly part.
+constexpr int kHashSlots = 2048;     // power of two
+constexpr int kHashBits = 11;
+constexpr int kBwdPerThread = 4;     // contacts per thread per chunk
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_backward(const T* __restrict__ verts, int n_verts,
+struct GradHash {
+  int key[kHashSlots];
+  T val[3][kHashSlots];
+};
+
+template <typename T>
+__device__ __forceinline__ void hash_add(GradHash<T>& H, int vid, T gx, T gy, T gz, T* grad,
+                                         int n_verts) {
+  uint32_t h = ((uint32_t)vid * 2654435761u) >> (32 - kHashBits);
+#pragma unroll 1
+  for (int probe = 0; probe < 32; ++probe) {
+    int cur = atomicCAS(&H.key[h], -1, vid);
+    if (cur == -1 || cur == vid) {
+      atomicAdd(&H.val[0][h], gx);
+      atomicAdd(&H.val[1][h], gy);
+      atomicAdd(&H.val[2][h], gz);
+      return;
+    }
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  unsafeAtomicAdd(grad + vid, gx);  // crowded table: straight to memory
+  unsafeAtomicAdd(grad + n_verts + vid, gy);
+  unsafeAtomicAdd(grad + 2 * (size_t)n_verts + vid, gz);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__ soup,
                                                   const int32_t* __restrict__ tv, int n_tris,
-                                                  const T* __restrict__ teps,
-                                                  const int32_t* __restrict__ cti,
+                                                  int n_verts, const int32_t* __restrict__ cti,
                                                   const int32_t* __restrict__ ctj,
                                                   const uint32_t* __restrict__ ccount, int64_t ccap,
                                                   double k, const double* __restrict__ grad_E,
                                                   T* __restrict__ grad, double* energy,
                                                   uint32_t* status) {
+  __shared__ GradHash<T> H;
   const uint32_t cnt = min((uint64_t)*ccount, (uint64_t)ccap);
   const double gE = grad_E ? *grad_E : 1.0;
-  const T* X = verts;
-  const T* Y = verts + n_verts;
-  const T* Z = verts + 2 * (size_t)n_verts;
+  const uint32_t bdim = blockDim.x;
+  const uint32_t chunk = bdim * kBwdPerThread;
+  for (int s2 = threadIdx.x; s2 < kHashSlots; s2 += bdim) {
+    H.key[s2] = -1;
+    H.val[0][s2] = H.val[1][s2] = H.val[2][s2] = T(0);
+  }
+  __syncthreads();
   double e_acc = 0.0;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
-    int ti = cti[c], tj = ctj[c];
-    int ia[3] = {tv[ti], tv[n_tris + ti], tv[2 * (size_t)n_tris + ti]};
-    int ib[3] = {tv[tj], tv[n_tris + tj], tv[2 * (size_t)n_tris + tj]};
-    V3<T> A0 = {X[ia[0]], Y[ia[0]], Z[ia[0]]};
-    V3<T> A1 = {X[ia[1]], Y[ia[1]], Z[ia[1]]};
-    V3<T> A2 = {X[ia[2]], Y[ia[2]], Z[ia[2]]};
-    V3<T> B0 = {X[ib[0]], Y[ib[0]], Z[ib[0]]};
-    V3<T> B1 = {X[ib[1]], Y[ib[1]], Z[ib[1]]};
-    V3<T> B2 = {X[ib[2]], Y[ib[2]], Z[ib[2]]};
-    V3<T> D0 = A0 - B0;
-    Closest<T> cl;
-    exact_tri_tri(V3<T>{0, 0, 0}, A1 - A0, A2 - A0, -D0, B1 - B0, B2 - B0, cl);
-    T d = sqrt(cl.d2);
-    T delta = teps[ti] + teps[tj];
-    double pen = (double)delta - (double)d;
-    if (!(pen >= 0.0)) continue;
-    e_acc += k * pen * pen;
-    if (!(d > T(0)) || grad == nullptr) continue;
-    T g = T(2.0 * k * pen * gE);
-    V3<T> u = (T(1) / d) * (cl.q - cl.p);
+  for (uint32_t c0 = blockIdx.x * chunk; c0 < cnt; c0 += gridDim.x * chunk) {
+    for (int j = 0; j < kBwdPerThread; ++j) {
+      const uint32_t c = c0 + j * bdim + threadIdx.x;
+      if (c >= cnt) continue;
+      const int ti = cti[c], tj = ctj[c];
+      int cbi, cci, pi_, cbj, ccj, pj_;
+      Tri<T> A = load_tri(soup, ti, cbi, cci, pi_);
+      Tri<T> B = load_tri(soup, tj, cbj, ccj, pj_);
+      V3<T> D0 = A.v0 - B.v0;
+      Closest<T> cl;
+      exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, cl);
+      T d = sq_(cl.d2);
+      T delta = A.eps + B.eps;
+      double pen = (double)delta - (double)d;
+      if (!(pen >= 0.0)) continue;
+      e_acc += k * pen * pen;
+      if (!(d > T(0)) || grad == nullptr) continue;
+      T g = T(2.0 * k * pen * gE);
+      V3<T> u = (T(1) / d) * (cl.q - cl.p);
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      T gi = g * cl.wp[v], gj = -g * cl.wq[v];
-      if (gi != T(0)) {
-        atomic_add_t(grad + ia[v], gi * u.x);
-        atomic_add_t(grad + n_verts + ia[v], gi * u.y);
-        atomic_add_t(grad + 2 * (size_t)n_verts + ia[v], gi * u.z);
-      }
-      if (gj != T(0)) {
-        atomic_add_t(grad + ib[v], gj * u.x);
-        atomic_add_t(grad + n_verts + ib[v], gj * u.y);
-        atomic_add_t(grad + 2 * (size_t)n_verts + ib[v], gj * u.z);
+      for (int v = 0; v < 3; ++v) {
+        T gi = g * cl.wp[v], gj = -g * cl.wq[v];
+        if (gi != T(0)) hash_add(H, tv[(size_t)v * n_tris + ti], gi * u.x, gi * u.y, gi * u.z, grad, n_verts);
+        if (gj != T(0)) hash_add(H, tv[(size_t)v * n_tris + tj], gj * u.x, gj * u.y, gj * u.z, grad, n_verts);
       }
     }
+    __syncthreads();
+    for (int s2 = threadIdx.x; s2 < kHashSlots; s2 += bdim) {
+      int vid = H.key[s2];
+      if (vid >= 0) {
+        unsafeAtomicAdd(grad + vid, H.val[0][s2]);
+        unsafeAtomicAdd(grad + n_verts + vid, H.val[1][s2]);
+        unsafeAtomicAdd(grad + 2 * (size_t)n_verts + vid, H.val[2][s2]);
+        H.key[s2] = -1;
+        H.val[0][s2] = H.val[1][s2] = H.val[2][s2] = T(0);
+      }
+    }
+    __syncthreads();
   }
   if (energy) {
-    double s = wave_sum(e_acc);
-    if (lane_id() == 0 && s != 0.0) atomicAdd(energy, s);
+    double sum = wave_sum(e_acc);
+    if (lane_id() == 0 && sum != 0.0) atomicAdd(energy, sum);
   }
 }
 
@@ -583,6 +719,7 @@ bool params_ok(const dem_params& p) {
   if (p.queue_capacity < 1 || p.queue_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.near_capacity < 1 || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.grid < 0) return false;
+  if (p.n_events < 0 || (p.n_events > 0 && !p.events)) return false;
   return true;
 }
 
@@ -596,12 +733,21 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   int4* q[2] = {reinterpret_cast<int4*>(base + L.qa), reinterpret_cast<int4*>(base + L.qb)};
   int2* nearl = reinterpret_cast<int2*>(base + L.near_);
   const int grid = p.grid > 0 ? p.grid : 2048;
-
+  int n_launch = 0;
+  auto mark = [&]() {
+    if (p.events && n_launch < p.n_events)
+      hipEventRecord(reinterpret_cast<hipEvent_t>(p.events[n_launch]), st);
+    ++n_launch;
+  };
+  mark();
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctr, stats, status, out->count, energy);
+  mark();
   hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + 255) / 256), dim3(256), 0, st,
                      static_cast<const T*>(s->verts), s->n_verts, s->tri_verts, s->n_tris,
                      s->child_begin, s->child_count, s->tri_particle,
-                     static_cast<const T*>(s->tri_eps), T(p.alpha_reg_rel), soup, status);
+                     static_cast<const T*>(s->tri_eps), static_cast<const T*>(s->pose),
+                     T(p.alpha_reg_rel), soup, status);
+  mark();
   LevelArgs la;
   la.qcap = p.queue_capacity;
   la.near_ = nearl;
@@ -617,6 +763,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
       hipLaunchKernelGGL(k_seed, dim3(n_pairs), dim3(256), 0, st, pairs, n_pairs, s->root_begin,
                          s->root_count, p.seed_chunk, p.seed_chunk, q[0], &ctr->tail[0],
                          p.queue_capacity, status);
+      mark();
       for (int lev = 0; lev < s->n_levels_max; ++lev) {
         la.qin = q[lev & 1];
         la.tail_in = &ctr->tail[lev];
@@ -625,11 +772,13 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         la.tail_out = &ctr->tail[lev + 1];
         la.depth = lev;
         hipLaunchKernelGGL(k_level<T>, dim3(grid), dim3(p.block), 0, st, soup, la);
+        mark();
       }
     } else {
       hipLaunchKernelGGL(k_seed, dim3(n_pairs), dim3(256), 0, st, pairs, n_pairs, s->fine_begin,
                          s->fine_count, p.flat_tile_i, p.flat_tile_j, q[0], &ctr->tail[0],
                          p.queue_capacity, status);
+      mark();
       la.qin = q[0];
       la.tail_in = &ctr->tail[0];
       la.head_in = &ctr->head[0];
@@ -638,6 +787,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
       la.depth = 0;
       hipLaunchKernelGGL((k_flat<T, 64>), dim3(grid), dim3(p.flat_tile_i > 256 ? 256 : p.flat_tile_i),
                          0, st, soup, la);
+      mark();
     }
   }
   NearArgs na;
@@ -654,6 +804,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   na.stats = stats;
   na.status = status;
   hipLaunchKernelGGL(k_near<T>, dim3(grid), dim3(p.block), 0, st, soup, na);
+  mark();
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
 
@@ -715,25 +866,29 @@ dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32
 
 dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* c, double k,
                                 const double* grad_E, void* grad_verts, double* energy_out,
-                                uint32_t* dev_status, dem_stream_t stream) {
+                                const void* workspace, size_t workspace_bytes, uint32_t* dev_status,
+                                dem_stream_t stream) {
   if (!scene_ok(scene) || !c || !c->count || !c->ti || !c->tj || !dev_status) return DEM_ERR_ARG;
   if (!grad_verts && !energy_out) return DEM_ERR_ARG;
-  if (!(k >= 0.0)) return DEM_ERR_ARG;
+  if (!(k >= 0.0) || !workspace) return DEM_ERR_ARG;
+  if (c->capacity < 0 || c->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
+  WsLayout L = ws_layout(scene->precision, scene->n_tris, 1, 1);
+  if (workspace_bytes < L.qa) return DEM_ERR_CAPACITY;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const char* base = static_cast<const char*>(workspace);
   if (energy_out) hipLaunchKernelGGL(k_zero_scalar, dim3(1), dim3(64), 0, st, energy_out);
   const int grid = 1024;
   if (scene->precision == DEM_F64) {
     hipLaunchKernelGGL(k_backward<double>, dim3(grid), dim3(256), 0, st,
-                         static_cast<const double*>(scene->verts), scene->n_verts, scene->tri_verts,
-                         scene->n_tris, static_cast<const double*>(scene->tri_eps), c->ti, c->tj,
-                         c->count, c->capacity, k, grad_E, static_cast<double*>(grad_verts),
-                         energy_out, dev_status);
+                       reinterpret_cast<const SoupRec<double>*>(base + L.soup), scene->tri_verts,
+                       scene->n_tris, scene->n_verts, c->ti, c->tj, c->count, c->capacity, k, grad_E,
+                       static_cast<double*>(grad_verts), energy_out, dev_status);
   } else {
     hipLaunchKernelGGL(k_backward<float>, dim3(grid), dim3(256), 0, st,
-                         static_cast<const float*>(scene->verts), scene->n_verts, scene->tri_verts,
-                         scene->n_tris, static_cast<const float*>(scene->tri_eps), c->ti, c->tj,
-                         c->count, c->capacity, k, grad_E, static_cast<float*>(grad_verts),
-                         energy_out, dev_status);
+                       reinterpret_cast<const SoupRec<float>*>(base + L.soup), scene->tri_verts,
+                       scene->n_tris, scene->n_verts, c->ti, c->tj, c->count, c->capacity, k, grad_E,
+                       static_cast<float*>(grad_verts), energy_out, dev_status);
   }
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }

@@ -51,6 +51,7 @@ def _fake_scene(precision=_abi.DEM_F32):
     for f in ("verts", "tri_verts", "child_begin", "child_count", "tri_particle", "tri_eps",
               "root_begin", "root_count", "fine_begin", "fine_count"):
         setattr(s, f, 4096)  # never dereferenced by host-side validation
+    s.pose = None
     return s
 
 
@@ -79,7 +80,7 @@ def test_workspace_bytes_and_validation():
                              C.c_void_p(4096), 16, None, C.c_void_p(4096), None, None)
     assert st == _abi.DEM_ERR_CAPACITY
     st = L.dem_contact_backward(C.byref(s), C.byref(out), -1.0, None, C.c_void_p(4096), None,
-                                C.c_void_p(4096), None)
+                                C.c_void_p(4096), 1 << 20, C.c_void_p(4096), None)
     assert st == _abi.DEM_ERR_ARG
 
 

@@ -258,3 +258,66 @@ def test_graph_replay_matches_eager():
         assert abs(float(eng.energy.item()) - e_ref) <= 1e-9 * e_ref
         assert torch.allclose(grad, g_ref, rtol=1e-5, atol=1e-6 * float(g_ref.abs().max()))
         del junk
+
+
+# ------------------------------------------------------------------ poses
+def _rot90z():
+    return np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+
+
+def test_pose_exact_rotation_matches_oracle():
+    """A 90-degree rotation applied in the flatten kernel is exact in FP32:
+    contacts must match the oracle on the rotated coordinates."""
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=48, name="pose90")
+    ds = api.DeviceScene(scene, device="cuda:0")
+    R = _rot90z()
+    pose = np.concatenate([np.tile(R.reshape(1, 9), (ds.n_particles, 1)), np.zeros((ds.n_particles, 3))], 1)
+    ds.set_pose(torch.as_tensor(pose, dtype=ds.dtype, device="cuda:0").contiguous())
+    eng = api.ContactEngine(ds, api.make_params("hier"))
+    assert eng.run() == 0
+    res = eng.result()
+    rotated = [scene.world(p) @ R.T for p in range(len(scene.particles))]
+    fs = oracle.fine_scene(scene, verts_override=rotated)
+    ref = oracle.find_contacts(fs)
+    n, _, _ = compare_sets(scene, ds, res, ref, TOL["f32"], fs=fs)
+    assert n > 500
+
+
+def test_pose_small_rigid_motion_within_rounding():
+    """Random small rigid motions (as in the fwd+bwd benchmark) applied in
+    the flatten kernel, against the oracle on the exact FP64 rigid images;
+    the bar adds the FP32 rounding of the transform (8 ulp of the largest
+    coordinate) to the distance tolerance and the threshold band."""
+    scene = sg.lattice_scene(3, config_id=49, s_choices=(2, 3))
+    ds = api.DeviceScene(scene, device="cuda:0")
+    P = ds.n_particles
+    Rs, ts = sg.rigid_perturbations(P, 4, config_id=49)
+    k = 3
+    centres = np.array([p.centre for p in scene.particles])
+    shift = centres + ts[k] - np.einsum("pij,pj->pi", Rs[k], centres)
+    pose = np.concatenate([Rs[k].reshape(P, 9), shift], 1)
+    ds.set_pose(torch.as_tensor(pose, dtype=ds.dtype, device="cuda:0").contiguous())
+    eng = api.ContactEngine(ds, api.make_params("hier"))
+    assert eng.run() == 0
+    res = eng.result()
+    moved = [(scene.world(p) - centres[p]) @ Rs[k][p].T + centres[p] + ts[k][p] for p in range(P)]
+    fs = oracle.fine_scene(scene, verts_override=moved)
+    ref = oracle.find_contacts(fs)
+    cmax = max(np.abs(m).max() for m in moved)
+    extra = 8 * 2.0 ** -24 * cmax
+    tol = dict(TOL["f32"])
+    tol["a"] = TOL["f32"]["a"]
+    tol["band"] = TOL["f32"]["band"] + 2 * extra
+    # distances: add the transform rounding as an absolute term
+    g = keyed(ds, res)
+    o = oracle_keyed(scene, ref)
+    common = sorted(set(g) & set(o))
+    dg = np.array([res["d"][g[c]] for c in common])
+    dr = np.array([ref["d"][o[c]] for c in common])
+    h = np.array([longest_edge(*pair_geom(fs, *c)) for c in common])
+    assert np.all(np.abs(dg - dr) <= 1e-5 * dr + 1e-6 * h + 2 * extra)
+    for key in set(o) - set(g):
+        assert abs(ref["d"][o[key]] - 0.1) <= tol["band"]
+    for key in set(g) - set(o):
+        assert abs(oracle.tri_tri(*pair_geom(fs, *key))["d"] - 0.1) <= tol["band"]
+    assert len(common) > 100
