@@ -28,18 +28,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "tri-pair evals/s and contact fwd+bwd ms/step: hierarchical batched vs plain all-pairs"
-PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (unpacked FP32)
-PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_FP32_VALU_TFLOPS = 157.3  # 256 CU x 128 FP32 FMA lanes/clk x 2 flop x 2.4 GHz
+PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 64 FP64 FMA lanes/clk x 2 flop x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
 
 def flops_per_eval(n_iter: int) -> int:
-    """Algorithmic FP32 operations of one iterate-and-bound evaluation
-    (FMA = 2), counted from the formulas: 84 per Newton iteration (residual
-    24, gradient 20, diagonal step 12, two penalty half-steps 28) plus 160
-    for the set-up, projection to the triangles, direction, the two support
-    functions and the rounding slack."""
-    return 84 * n_iter + 160
+    """Algorithmic floating-point operations of one iterate-and-bound
+    evaluation, counted from its formulas (FMA = 2; add, mul, min, max,
+    compare, reciprocal, rsqrt = 1; sign changes and selects = 0): 80 per
+    Newton iteration (residual 24, gradient 20, diagonal step 8, two penalty
+    half-steps 28; the first step starts at (a, b) = 0 where the residual is
+    the vertex difference itself, 24 fewer) plus 93 for the pair set-up, the
+    projection of both iterates onto their triangles, the search direction,
+    the two support functions, the rounding slack and the threshold test."""
+    if n_iter == 0:
+        return 93
+    return 80 * n_iter - 24 + 93
 
 
 FLATTEN_BYTES_PER_TRI = 12 + 16 + 64  # indices, per-triangle static data, soup record
@@ -219,7 +224,19 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=60)
     ap.add_argument("--contact-capacity", type=int, default=1 << 23)
     ap.add_argument("--param", action="append", default=[], help="dem_params override, e.g. omega=0.5")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calib_copy_mib:
+        import torch
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": 4 * n, "copies": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))

@@ -68,8 +68,10 @@ typedef enum { DEM_MODE_FLAT = 0, DEM_MODE_HIER = 1 } dem_mode;
 #define DEM_DEV_QUEUE_OVERFLOW 0x2u   /* a level work queue exceeded queue_capacity */
 #define DEM_DEV_NEAR_OVERFLOW 0x4u    /* near-pair list exceeded near_capacity */
 #define DEM_DEV_NONFINITE 0x8u        /* a non-finite coordinate or distance was met */
+#define DEM_DEV_BAD_TREE 0x10u        /* a child count outside 0..DEM_MAX_CHILDREN */
 
 #define DEM_MAX_LEVELS 32
+#define DEM_MAX_CHILDREN 16           /* children per surrogate (N_surrogate <= 16) */
 
 typedef void* dem_stream_t; /* a hipStream_t (0 = the null stream) */
 
@@ -120,7 +122,8 @@ typedef struct {
  * opts      may be NULL (defaults).
  * out       filled with library-allocated host arrays; release with
  *           dem_hierarchy_free.  Every triangle of levels < n_levels-1 must
- *           have children and the last level must have none.
+ *           have between 1 and DEM_MAX_CHILDREN children and the last level
+ *           must have none.
  *
  * Each surrogate gets eps = eps0 + max over the vertices of its fine
  * descendants of their distance to the surrogate triangle: the distance to
@@ -166,7 +169,7 @@ typedef struct {
 
 typedef struct {
   int32_t mode;           /* DEM_MODE_FLAT (Algorithm 2) or DEM_MODE_HIER (Algorithm 5) */
-  int32_t n_iter;         /* fixed Newton iteration count N_iterative (paper: 4) */
+  int32_t n_iter;         /* fixed Newton iteration count N_iterative, 0..8 (paper: 4) */
   float omega;            /* damping of the diagonal-Newton step (1 = undamped) */
   float alpha_reg_rel;    /* alpha_regulariser of a triangle = alpha_reg_rel * (|e1|^2 + |e2|^2) / 2 */
   float alpha_it_ratio;   /* alpha_iterative / alpha_regulariser */

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdem.so")
+# DEM_LIBRARY selects another build of the same ABI (e.g. a tuning variant).
+LIB_PATH = os.environ.get("DEM_LIBRARY") or os.path.join(HERE, "libdem.so")
 
 DEM_OK, DEM_ERR_ARG, DEM_ERR_CAPACITY, DEM_ERR_HIP, DEM_ERR_NOT_CONSERVATIVE, DEM_ERR_OOM = 0, -1, -2, -3, -4, -5
 DEM_F32, DEM_F64 = 0, 1
@@ -19,7 +20,9 @@ DEM_DEV_CONTACT_OVERFLOW = 0x1
 DEM_DEV_QUEUE_OVERFLOW = 0x2
 DEM_DEV_NEAR_OVERFLOW = 0x4
 DEM_DEV_NONFINITE = 0x8
+DEM_DEV_BAD_TREE = 0x10
 DEM_MAX_LEVELS = 32
+DEM_MAX_CHILDREN = 16
 
 # Every exported symbol declared in include/dem.h.
 EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "dem_workspace_bytes",

@@ -289,6 +289,8 @@ class ContactEngine:
             status = self.check()
             if status & _abi.DEM_DEV_NONFINITE:
                 raise DemError("non-finite coordinates or distances")
+            if status & _abi.DEM_DEV_BAD_TREE:
+                raise DemError("malformed surrogate tree (child counts)")
             if not status & (_abi.DEM_DEV_CONTACT_OVERFLOW | _abi.DEM_DEV_QUEUE_OVERFLOW |
                              _abi.DEM_DEV_NEAR_OVERFLOW):
                 return status

@@ -26,12 +26,15 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, lib_path: str = LIB, extra_flags=(), sources=None) -> str:
+    """Compile SOURCES (or ``sources``: paths) into ``lib_path``."""
     objs = []
     common = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(CSRC, "_obj_" + os.path.splitext(src)[0] + ".o")
+    common += list(extra_flags)
+    out_dir = os.path.dirname(os.path.abspath(lib_path))
+    for src in (sources or [os.path.join(CSRC, s) for s in SOURCES]):
+        path = src
+        obj = os.path.join(out_dir, "_obj_" + os.path.splitext(os.path.basename(src))[0] + ".o")
         cmd = [hipcc(), "-c", "-x", "hip", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-munsafe-fp-atomics"] + common + ["-o", obj, path]
@@ -39,15 +42,15 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib_path)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib_path
 
 
 if __name__ == "__main__":

@@ -94,13 +94,35 @@ struct Eps<double> {
   static constexpr double u = 1.1102230246251565e-16;  // 2^-53
 };
 
+// Hardware reciprocal / reciprocal square root for FP32 on the device (1 ulp),
+// used only where an approximate value is harmless: normalising the search
+// direction (the bound's slack absorbs a 1-ulp length error) and projecting
+// iterates into the triangle (only the direction depends on it).
+DEM_HD float rcp_fast(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+DEM_HD double rcp_fast(double x) { return 1.0 / x; }
+DEM_HD float rsq_fast(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(x);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
+DEM_HD double rsq_fast(double x) { return 1.0 / sqrt(x); }
+
 // A triangle in "soup" form: first vertex, two edge vectors, epsilon,
 // diagonal of the regularised Hessian block (inverted) for its two
-// barycentric parameters.
+// barycentric parameters, and a size bound (max|e1| + max|e2| over
+// components) for the rounding slack.
 template <typename T>
 struct Tri {
   V3<T> v0, e1, e2;
-  T eps, ia, ib;
+  T eps, ia, ib, size;
 };
 
 // ------------------------------------------------------------------ iteration
@@ -129,72 +151,73 @@ DEM_HD void penalty_half_step(T& a, T& b, T k1, T k2) {
   b += kb * (cb - cs);
 }
 
-// Feasible point of the triangle closest in parameter space to (a, b):
-// clamp to a, b >= 0 and rescale onto a + b <= 1.
+// Point of the triangle for parameters (a, b) pulled into a, b >= 0 and
+// rescaled onto a + b <= 1 (it only fixes the search direction).
 template <typename T>
 DEM_HD void to_simplex(T& a, T& b) {
   a = mx_(a, T(0));
   b = mx_(b, T(0));
-  T s = a + b;
-  T inv = T(1) / mx_(s, T(1));
+  T inv = rcp_fast(mx_(a + b, T(1)));
   a *= inv;
   b *= inv;
 }
 
-// Fixed-count modified Newton iteration on J (Section 3) for triangles A, B
-// in pair-local coordinates (A.v0 at the origin, B's first vertex at -D0),
-// then the lower bound along the direction between the two feasible
-// iterate points.  Returns the bound; th = (a1, b1, a2, b2) feasible.
-template <typename T>
-DEM_HD T iterate_and_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip,
-                           T th[4], T* dist_up) {
+// N modified-Newton iterations on J (Section 3: diagonal Newton step on the
+// distance term, then a half-step on the constraint penalties; N fixed as
+// in Algorithm 4) for triangles A, B in pair-local coordinates (A.v0 at the
+// origin, B's first vertex at -D0), then the lower bound on the distance
+// along the unit direction u between the two iterate points:
+//     d(A, B) >= min_k u.b_k - max_k u.a_k.
+// Returns the bound (-inf if the two points coincide: nothing is pruned).
+template <typename T, int N>
+DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip) {
+  const T om = T(ip.omega), k1 = T(ip.kappa1), k2 = T(ip.kappa2);
+  // damped inverse diagonal of the regularised Hessian, per parameter
+  const T s1 = om * A.ia, s2 = om * A.ib, s3 = om * B.ia, s4 = om * B.ib;
   T a1, b1, a2, b2;
+  V3<T> r;  // residual t_A(a1,b1) - t_B(a2,b2)
   if (ip.init_centroid) {
     a1 = b1 = a2 = b2 = T(1) / T(3);
+    r = fma3(a1, A.e1 + A.e2, fma3(-a2, B.e1 + B.e2, D0));
   } else {
     a1 = b1 = a2 = b2 = T(0);
+    r = D0;
   }
-  const T om = T(ip.omega), k1 = T(ip.kappa1), k2 = T(ip.kappa2);
-  for (int it = 0; it < ip.n_iter; ++it) {
-    // residual r = t_A(a1,b1) - t_B(a2,b2); grad of 1/2|r|^2
-    V3<T> r = fma3(a1, A.e1, fma3(b1, A.e2, fma3(-a2, B.e1, fma3(-b2, B.e2, D0))));
-    T g1 = dot(r, A.e1), g2 = dot(r, A.e2), g3 = -dot(r, B.e1), g4 = -dot(r, B.e2);
-    // diagonal (Jacobi) Newton step with regularised diagonal
-    a1 -= om * g1 * A.ia;
-    b1 -= om * g2 * A.ib;
-    a2 -= om * g3 * B.ia;
-    b2 -= om * g4 * B.ib;
+#pragma unroll
+  for (int it = 0; it < N; ++it) {
+    if (it > 0) r = fma3(a1, A.e1, fma3(b1, A.e2, fma3(-a2, B.e1, fma3(-b2, B.e2, D0))));
+    // gradient of 1/2 |r|^2 and the diagonal Newton step
+    a1 -= s1 * dot(r, A.e1);
+    b1 -= s2 * dot(r, A.e2);
+    a2 += s3 * dot(r, B.e1);
+    b2 += s4 * dot(r, B.e2);
     // constraint half-step
     penalty_half_step(a1, b1, k1, k2);
     penalty_half_step(a2, b2, k1, k2);
   }
   to_simplex(a1, b1);
   to_simplex(a2, b2);
-  th[0] = a1; th[1] = b1; th[2] = a2; th[3] = b2;
-  // points: p1 = a1 e1 + b1 e2 ; p2 = -D0 + a2 f1 + b2 f2 ; w = p2 - p1
+  // w = p2 - p1 between the two (feasible) iterate points
   V3<T> w = fma3(a2, B.e1, fma3(b2, B.e2, fma3(-a1, A.e1, fma3(-b1, A.e2, -D0))));
   T ww = dot(w, w);
-  // direction: between the iterate points, else between the centroids
-  V3<T> c = (T(1) / T(3)) * ((B.e1 + B.e2) - (A.e1 + A.e2)) - D0;
-  bool use_w = ww > T(1e-24) * (dot(A.e1, A.e1) + dot(B.e1, B.e1)) && ww > T(0);
-  V3<T> u = sel(use_w, w, c);
-  T uu = dot(u, u);
-  T inv = uu > T(0) ? rsqrt_t(uu) : T(0);
-  u = inv * u;
+  V3<T> u = rsq_fast(mx_(ww, T(1e-30))) * w;
   // support of A along u (max) and of B along u (min)
   T hA = mx_(T(0), mx_(dot(u, A.e1), dot(u, A.e2)));
-  T hB = -dot(u, D0) + mn_(T(0), mn_(dot(u, B.e1), dot(u, B.e2)));
-  *dist_up = sq_(ww);
-  return hB - hA;
+  T hB = mn_(T(0), mn_(dot(u, B.e1), dot(u, B.e2))) - dot(u, D0);
+  return ww > T(0) ? hB - hA : -T(INFINITY);
 }
 
 // Rounding slack of the bound above: the computed bound of a pair at true
-// distance d never exceeds d + slack.
+// distance d never exceeds d + slack (dot products of pair-local vectors in
+// precision T, a 1-ulp direction length error, rounded soup edges).
 template <typename T>
 DEM_HD T bound_slack(const Tri<T>& A, const Tri<T>& B, V3<T> D0, T delta) {
-  T size = absmax3(D0) + absmax3(A.e1) + absmax3(A.e2) + absmax3(B.e1) + absmax3(B.e2);
-  return T(64) * Eps<T>::u * (T(3) * size + ab_(delta));
+  return T(64) * Eps<T>::u * (T(3) * (absmax3(D0) + A.size + B.size) + ab_(delta));
 }
+
+// Size bound stored with each soup triangle: max|e1| + max|e2| (components).
+template <typename T>
+DEM_HD T tri_size(V3<T> e1, V3<T> e2) { return absmax3(e1) + absmax3(e2); }
 
 // ------------------------------------------------------------------ exact
 template <typename T>

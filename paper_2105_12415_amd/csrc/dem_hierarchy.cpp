@@ -86,8 +86,10 @@ dem_status dem_build_hierarchy(const double* verts, int32_t n_verts, const int32
     }
   }
   for (int l = 0; l + 1 < n_levels; ++l)
-    for (int64_t t = lb[l]; t < lb[l + 1]; ++t)
+    for (int64_t t = lb[l]; t < lb[l + 1]; ++t) {
       if (cc[t] == 0) return DEM_ERR_NOT_CONSERVATIVE;  // leaves only on the last level
+      if (cc[t] > DEM_MAX_CHILDREN) return DEM_ERR_ARG;
+    }
 
   // deviations: every fine vertex against every ancestor
   std::vector<double> dev(n, 0.0);

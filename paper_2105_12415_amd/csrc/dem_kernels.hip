@@ -39,7 +39,7 @@ constexpr int kWave = 64;
 template <typename T>
 struct alignas(16) SoupRec {
   T g[12];         // v0.xyz eps | e1.xyz ia | e2.xyz ib
-  int32_t topo[4]; // child_begin, child_count, particle, unused
+  int32_t topo[4]; // child_begin, child_count, particle, size bound (float bits)
 };
 
 struct Counters {
@@ -72,25 +72,27 @@ WsLayout ws_layout(int precision, int64_t n_tris, int64_t qcap, int64_t ncap) {
 template <typename T>
 __device__ __forceinline__ Tri<T> load_tri(const SoupRec<T>* __restrict__ s, int t, int& cb, int& cc,
                                            int& part) {
-  const SoupRec<T>& r = s[t];
+  // 32-bit byte offset from a uniform base (soups stay below 4 GiB)
+  const char* rp = reinterpret_cast<const char*>(s) + (uint32_t)t * (uint32_t)sizeof(SoupRec<T>);
   Tri<T> x;
+  int4 d;
   if constexpr (sizeof(T) == 4) {
-    const float4* p = reinterpret_cast<const float4*>(&r);
+    const float4* p = reinterpret_cast<const float4*>(rp);
     float4 a = p[0], b = p[1], c = p[2];
-    int4 d = reinterpret_cast<const int4*>(&r)[3];
+    d = reinterpret_cast<const int4*>(rp)[3];
     x.v0 = {a.x, a.y, a.z}; x.eps = a.w;
     x.e1 = {b.x, b.y, b.z}; x.ia = b.w;
     x.e2 = {c.x, c.y, c.z}; x.ib = c.w;
-    cb = d.x; cc = d.y; part = d.z;
   } else {
-    const double2* p = reinterpret_cast<const double2*>(&r);
+    const double2* p = reinterpret_cast<const double2*>(rp);
     double2 a0 = p[0], a1 = p[1], b0 = p[2], b1 = p[3], c0 = p[4], c1 = p[5];
-    int4 d = *reinterpret_cast<const int4*>(&r.topo[0]);
+    d = reinterpret_cast<const int4*>(rp)[6];
     x.v0 = {a0.x, a0.y, a1.x}; x.eps = a1.y;
     x.e1 = {b0.x, b0.y, b1.x}; x.ia = b1.y;
     x.e2 = {c0.x, c0.y, c1.x}; x.ib = c1.y;
-    cb = d.x; cc = d.y; part = d.z;
   }
+  cb = d.x; cc = d.y; part = d.z;
+  x.size = T(__int_as_float(d.w));
   return x;
 }
 
@@ -178,10 +180,13 @@ __global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, in
   r.g[0] = v0.x; r.g[1] = v0.y; r.g[2] = v0.z; r.g[3] = teps[t];
   r.g[4] = e1.x; r.g[5] = e1.y; r.g[6] = e1.z; r.g[7] = ia;
   r.g[8] = e2.x; r.g[9] = e2.y; r.g[10] = e2.z; r.g[11] = ib;
-  r.topo[0] = cbeg[t]; r.topo[1] = ccnt[t]; r.topo[2] = part; r.topo[3] = 0;
+  // size bound, rounded up when narrowed to float
+  const float sz = (float)(tri_size(e1, e2) * T(1.0 + 1.0 / 1048576.0));
+  r.topo[0] = cbeg[t]; r.topo[1] = ccnt[t]; r.topo[2] = part; r.topo[3] = __float_as_int(sz);
   soup[t] = r;
   T chk = v0.x + v0.y + v0.z + e1.x + e1.y + e1.z + e2.x + e2.y + e2.z;
   if (!isfinite(chk)) atomicOr(status, DEM_DEV_NONFINITE);
+  if (ccnt[t] < 0 || ccnt[t] > DEM_MAX_CHILDREN) atomicOr(status, DEM_DEV_BAD_TREE);
 }
 
 // One block per candidate pair: items covering range_i x range_j in chunks.
@@ -302,11 +307,31 @@ constexpr int kStageItems = 512;
 constexpr int kStageNear = 512;
 constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between checks
 
-template <typename T>
+// Logical block index with consecutive indices on the same XCD: hardware
+// dispatches workgroups round-robin over the 8 XCDs, each with its own L2,
+// and neighbouring work items share triangles (siblings in the tree).
+__device__ __forceinline__ uint32_t xcd_swizzle(uint32_t bid, uint32_t grid) {
+  constexpr uint32_t kXcd = 8;
+  if (grid % kXcd) return bid;
+  return (bid % kXcd) * (grid / kXcd) + bid / kXcd;
+}
+
+// Descent over one tree depth.  Work items are products of two triangle
+// ranges (the children of a surviving surrogate pair, or a chunk of the
+// roots); lanes take one child pair each, located through a block-wide scan
+// of the items' pair counts.
+#ifndef DEM_BLOCK_ORDER
+#define DEM_BLOCK_ORDER(b, g) xcd_swizzle(b, g)
+#endif
+
+constexpr int kOwnerCap = 4096;  // child pairs mapped to their item through LDS
+
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
   __shared__ int4 items[256];
   __shared__ int offs[257];
   __shared__ int wsum[16];
+  __shared__ uint8_t owner_s[kOwnerCap];
   __shared__ LdsQueue<int4, kStageItems> qi;
   __shared__ LdsQueue<int2, kStageNear> qn;
   const uint32_t count = min((uint64_t)*a.tail_in, (uint64_t)a.qcap);
@@ -314,16 +339,29 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
   unsigned long long my_evals = 0, my_surv = 0, my_near = 0;
   if (threadIdx.x == 0) { qi.n = 0; qn.n = 0; }
   // static grid-stride over batches of items (items carry similar work)
-  for (uint32_t b = blockIdx.x * (uint32_t)a.batch; b < count; b += gridDim.x * (uint32_t)a.batch) {
+  const uint32_t lb = DEM_BLOCK_ORDER(blockIdx.x, gridDim.x);
+  for (uint32_t b = lb * (uint32_t)a.batch; b < count; b += gridDim.x * (uint32_t)a.batch) {
     int n = (int)min((uint32_t)a.batch, count - b);
     int np = 0;
     if ((int)threadIdx.x < n) {
       int4 it = a.qin[b + threadIdx.x];
+      if (it.y < 1 || it.y > DEM_MAX_CHILDREN || it.w < 1 || it.w > DEM_MAX_CHILDREN) {
+        atomicOr(a.status, DEM_DEV_BAD_TREE);  // malformed tree: skip the item
+        it.y = it.w = 0;
+      }
       items[threadIdx.x] = it;
       np = it.y * it.w;
     }
     block_scan(np, offs, wsum, n);
     const int total = offs[n];
+    // small batches (the usual 4x4 children products) map pair -> item
+    // through an LDS table; large ones (root chunks) search the offsets
+    const bool mapped = total <= kOwnerCap && n <= 256;
+    if (mapped && (int)threadIdx.x < n) {
+      const int o = offs[threadIdx.x];
+      for (int q = 0; q < np; ++q) owner_s[o + q] = (uint8_t)threadIdx.x;
+    }
+    if (mapped) __syncthreads();
     for (int base = 0; base < total; base += bdim) {
       const int e = base + (int)threadIdx.x;
       bool push_item = false, push_near = false;
@@ -332,14 +370,18 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
       if (e < total) {
         // item owning flat index e: last k with offs[k] <= e
         int lo = 0, hi = n - 1;
-        while (lo < hi) {
-          int mid = (lo + hi + 1) >> 1;
-          if (offs[mid] <= e) lo = mid; else hi = mid - 1;
+        if (mapped) {
+          lo = owner_s[e];
+        } else {
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= e) lo = mid; else hi = mid - 1;
+          }
         }
         int4 it = items[lo];
         int l = e - offs[lo];
         int jn = it.w;
-        int qd = (int)((float)l * (1.0f / (float)jn));
+        int qd = (int)((float)l * rcp_fast((float)jn));
         int rr = l - qd * jn;
         if (rr < 0) { qd -= 1; rr += jn; }
         if (rr >= jn) { qd += 1; rr -= jn; }
@@ -349,8 +391,7 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
         Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
         Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_);
         V3<T> D0 = A.v0 - B.v0;
-        T th[4], up;
-        T L = iterate_and_bound(A, B, D0, a.ip, th, &up);
+        T L = iterate_bound<T, N>(A, B, D0, a.ip);
         T delta = A.eps + B.eps;
         bool fine = (cci == 0) && (ccj == 0);
         bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
@@ -396,7 +437,7 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
 }
 
 // FLAT: tile = (i range <= blockDim) x (j range <= TJ) of fine triangles.
-template <typename T, int TJ>
+template <typename T, int N, int TJ>
 __global__ void __launch_bounds__(256) k_flat(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
   __shared__ SoupRec<T> tj_s[TJ];
   __shared__ LdsQueue<int2, kStageFlat> qn;
@@ -420,8 +461,7 @@ __global__ void __launch_bounds__(256) k_flat(const SoupRec<T>* __restrict__ sou
         int cbj, ccj, pj_;
         Tri<T> B = load_tri(tj_s, k, cbj, ccj, pj_);
         V3<T> D0 = A.v0 - B.v0;
-        T th[4], up;
-        T L = iterate_and_bound(A, B, D0, a.ip, th, &up);
+        T L = iterate_bound<T, N>(A, B, D0, a.ip);
         T delta = A.eps + B.eps;
         bool keep = act && (a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta)));
         my_evals += act;
@@ -709,7 +749,7 @@ bool scene_ok(const dem_scene* s) {
 
 bool params_ok(const dem_params& p) {
   if (p.mode != DEM_MODE_FLAT && p.mode != DEM_MODE_HIER) return false;
-  if (p.n_iter < 0 || p.n_iter > 64) return false;
+  if (p.n_iter < 0 || p.n_iter > 8) return false;
   if (!(p.omega > 0.0f) || !(p.alpha_reg_rel >= 0.0f) || !(p.alpha_it_ratio > 0.0f)) return false;
   if (p.block < 64 || p.block > 256 || p.block % 64) return false;
   if (p.batch_items < 1 || p.batch_items > p.block) return false;
@@ -721,6 +761,26 @@ bool params_ok(const dem_params& p) {
   if (p.grid < 0) return false;
   if (p.n_events < 0 || (p.n_events > 0 && !p.events)) return false;
   return true;
+}
+
+// The Newton iteration count is a template parameter so the iteration is
+// fully unrolled; counts 0..8 are instantiated.
+template <typename T>
+void launch_level(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
+  switch (n_iter) {
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_level<T, N>), g, b, 0, st, soup, la); break;
+    DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
+#undef DEM_CASE
+  }
+}
+
+template <typename T>
+void launch_flat(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
+  switch (n_iter) {
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_flat<T, N, 64>), g, b, 0, st, soup, la); break;
+    DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
+#undef DEM_CASE
+  }
 }
 
 template <typename T>
@@ -771,7 +831,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         la.qout = q[(lev + 1) & 1];
         la.tail_out = &ctr->tail[lev + 1];
         la.depth = lev;
-        hipLaunchKernelGGL(k_level<T>, dim3(grid), dim3(p.block), 0, st, soup, la);
+        launch_level<T>(p.n_iter, dim3(grid), dim3(p.block), st, soup, la);
         mark();
       }
     } else {
@@ -785,8 +845,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
       la.qout = q[1];
       la.tail_out = &ctr->tail[1];
       la.depth = 0;
-      hipLaunchKernelGGL((k_flat<T, 64>), dim3(grid), dim3(p.flat_tile_i > 256 ? 256 : p.flat_tile_i),
-                         0, st, soup, la);
+      launch_flat<T>(p.n_iter, dim3(grid), dim3(p.flat_tile_i > 256 ? 256 : p.flat_tile_i), st, soup, la);
       mark();
     }
   }

@@ -26,6 +26,8 @@ static void bound_one(const double* P, const float* prm, double* out) {
   Tri<T> A, B;
   A.v0 = a0; A.e1 = a1 - a0; A.e2 = a2 - a0; A.eps = 0;
   B.v0 = b0; B.e1 = b1 - b0; B.e2 = b2 - b0; B.eps = 0;
+  A.size = tri_size(A.e1, A.e2);
+  B.size = tri_size(B.e1, B.e2);
   T areg = (T)prm[2];
   T n1 = dot(A.e1, A.e1), n2 = dot(A.e2, A.e2);
   T r = areg * T(0.5) * (n1 + n2);
@@ -41,12 +43,18 @@ static void bound_one(const double* P, const float* prm, double* out) {
   ip.kappa2 = (float)(rho / (2.0 * rho + 1.0));
   ip.init_centroid = (int)prm[4];
   V3<T> D0 = A.v0 - B.v0;
-  T th[4], up;
-  T L = iterate_and_bound(A, B, D0, ip, th, &up);
+  T L;
+  switch (ip.n_iter) {
+    case 0: L = iterate_bound<T, 0>(A, B, D0, ip); break;
+    case 1: L = iterate_bound<T, 1>(A, B, D0, ip); break;
+    case 2: L = iterate_bound<T, 2>(A, B, D0, ip); break;
+    case 4: L = iterate_bound<T, 4>(A, B, D0, ip); break;
+    case 8: L = iterate_bound<T, 8>(A, B, D0, ip); break;
+    default: L = -INFINITY;
+  }
   out[0] = L;
   out[1] = bound_slack(A, B, D0, T(0));
-  out[2] = up;
-  for (int k = 0; k < 4; ++k) out[3 + k] = th[k];
+  for (int k = 2; k < 7; ++k) out[k] = 0;
 }
 
 extern "C" void geom_exact(const double* pairs, long n, int use_double, double* out) {
