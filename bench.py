@@ -136,7 +136,7 @@ def kernel_times(torch, step: Step, K: int):
     handles = (C.c_void_p * n_ev)(*[C.c_void_p(e.cuda_event) for e in evs])
     eng.p.events = C.cast(handles, C.POINTER(C.c_void_p))
     eng.p.n_events = n_ev
-    n_launch = 3 + (eng.ds.n_levels_max if eng.p.mode == _abi.DEM_MODE_HIER else 1) + 1
+    n_launch = 3 + (eng.ds.n_levels_max if eng.p.mode == _abi.DEM_MODE_HIER else 1) + (2 if eng.p.certify else 1)
     acc = np.zeros(n_launch)
     bwd = 0.0
     evals = np.zeros(_abi.DEM_MAX_LEVELS)
@@ -276,8 +276,11 @@ def main():
             "flops_per_eval": flops_per_eval(n_iter), "evals_per_step": evals,
             "peak_published_packed_fp32": 157.3}
     flat_bytes = FLATTEN_BYTES_PER_TRI * ds.n_tris + FLATTEN_BYTES_PER_VERT * ds.n_verts
+    cert = bool(eng.p.certify)
     kernels = {"reset_ms": kt[0], "flatten_ms": kt[1], "seed_ms": kt[2], "levels_ms": level_ms,
-               "levels_ms_each": [round(x, 4) for x in kt[3:3 + L]], "near_ms": kt[3 + L],
+               "levels_ms_each": [round(x, 4) for x in kt[3:3 + L]],
+               "certify_ms": kt[3 + L] if cert else None, "fallback_ms": kt[3 + L + (1 if cert else 0)],
+               "near_ms": float(np.sum(kt[3 + L:])),
                "backward_ms": bwd_ms if backward else None,
                "flatten_GBs": flat_bytes / (kt[1] * 1e-3) / 1e9}
     out = {"metric": METRIC, "value": evals / (ms * 1e-3), "unit": "tri-pair evals/s", "n_gpus": 1,
@@ -292,7 +295,8 @@ def main():
            "roofline": roof, "kernels": kernels,
            "stats": {"evals_per_level": [int(x) for x in st["evals"][:L]],
                      "survivors_per_level": [int(x) for x in st["survivors"][:L]],
-                     "near": st["near"], "fallback": st["fallback"], "contacts": st["contacts"]}}
+                     "near": st["near"], "certified": st["certified"], "fallback": st["fallback"],
+                     "contacts": st["contacts"]}}
     if not args.no_flat:
         del eng, step
         torch.cuda.empty_cache()
@@ -301,7 +305,7 @@ def main():
         fevals = float(np.sum(fst["evals"]))
         out["flat"] = {"ms_per_step": fms, "ms_per_step_wall": fwall, "evals_per_step": fevals,
                        "evals_per_s": fevals / (fms * 1e-3), "contacts": fst["contacts"],
-                       "flat_kernel_ms": float(fkt[3]), "near_ms": float(fkt[4]),
+                       "flat_kernel_ms": float(fkt[3]), "near_ms": float(np.sum(fkt[4:])),
                        "flat_kernel_TFLOPs": flops_per_eval(n_iter) * fevals / (fkt[3] * 1e-3) / 1e12}
         out["speedup_vs_flat"] = fms / ms
         log(f"[bench] flat: {fms:.2f} ms/step, {fevals:.4g} evals/step")

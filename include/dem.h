@@ -175,22 +175,26 @@ typedef struct {
   float alpha_it_ratio;   /* alpha_iterative / alpha_regulariser */
   int32_t init_centroid;  /* 0: start the iteration at (a,b) = 0 as the paper does; 1: at the centroids */
   int32_t dense_distance; /* 1: threshold = +inf, every fine pair is reported with its exact distance */
-  int32_t certify;        /* 1: accept a near pair's distance from the iterate when the lower
-                             bound certifies it; 0: every near pair takes the exact fallback */
+  int32_t certify;        /* 1 (default): settle a near pair from its iterate snapped to the
+                             closest features when the separation bound certifies the distance
+                             (FP32: within 4e-6 d + 1e-7 size), else send it to the exact
+                             fallback; 0: every near pair takes the exact fallback */
   double energy_k;        /* k of E = k sum max(0, delta - d)^2 (used when dev_energy != NULL) */
-  int32_t block;          /* threads per block of the descent / near kernels (64..1024, multiple of 64) */
+  int32_t block;          /* threads per block of the descent / near kernels: 64, 128 or 256 */
   int32_t grid;           /* blocks of the persistent kernels (0 = 8 per compute unit) */
   int32_t batch_items;    /* work items a block claims at once (1..block) */
   int32_t flat_tile_i;    /* flat mode: i-triangles per tile (multiple of 64, <= 1024) */
   int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..256) */
   int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges */
-  int64_t queue_capacity; /* items per level queue */
-  int64_t near_capacity;  /* fine pairs the lower bound could not prune */
+  int64_t queue_capacity; /* items per level queue (>= 8; split into 8 equal segments, one
+                             filled per XCD, so allow for uneven fills) */
+  int64_t near_capacity;  /* fine pairs the lower bound could not prune (8 segments likewise) */
   /* Optional timing: an array of n_events hipEvent_t (host handles, created
    * by the caller).  events[0] is recorded before the first kernel launch of
    * dem_find_contacts and events[k] right after its k-th launch, in launch
    * order: reset, flatten, seed, then one launch per tree depth (HIER) or
-   * the flat tile kernel (FLAT), then the near-pair kernel.  Launches beyond
+   * the flat tile kernel (FLAT), then the certify kernel (if certify) and
+   * the exact fallback kernel.  Launches beyond
    * n_events - 1 are not bracketed.  NULL / 0 disables (use that when the
    * call is captured into a graph). */
   void* const* events;

@@ -224,13 +224,14 @@ class ContactEngine:
         if contact_capacity is None:
             contact_capacity = ds.n_fine_pairs() if self.p.dense_distance else max(1 << 16, 64 * ds.n_pairs)
         if self.p.dense_distance:
-            self.p.near_capacity = max(int(self.p.near_capacity), ds.n_fine_pairs())
+            # every fine pair is listed; segments fill unevenly
+            self.p.near_capacity = max(int(self.p.near_capacity), int(1.5 * ds.n_fine_pairs()) + 8 * 65536)
         if self.p.mode == _abi.DEM_MODE_FLAT:
             ti, tj = self.p.flat_tile_i, self.p.flat_tile_j
             F = ds.fine_count_host
             a, b = F[ds.pairs_host[:, 0]], F[ds.pairs_host[:, 1]]
             tiles = int(np.sum(((a + ti - 1) // ti) * ((b + tj - 1) // tj)))
-            self.p.queue_capacity = max(int(self.p.queue_capacity), tiles)
+            self.p.queue_capacity = max(int(self.p.queue_capacity), 2 * tiles + 8 * 64)
         self.contacts = ContactBuffers.alloc(contact_capacity, ds.dtype, dev)
         self.stats = torch.zeros(_abi.STATS_WORDS, dtype=torch.int64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -271,9 +272,14 @@ class ContactEngine:
 
     # ---------------------------------------------------------- host-side reads
     def counters(self) -> dict:
-        w = self.ws[(self.ws_ptr - self.ws.data_ptr()):][: 4 * 68].view(torch.int32).cpu().numpy()
-        w = w.astype(np.int64) & 0xFFFFFFFF
-        return {"head": w[0:33], "tail": w[33:66], "near": int(w[66])}
+        """Segment fills of the level queues, near list and fallback list
+        (host copy; layout of the library's counter block)."""
+        nseg, L = 8, _abi.DEM_MAX_LEVELS + 1
+        nw = L * nseg + 2 * nseg
+        off = self.ws_ptr - self.ws.data_ptr()
+        w = self.ws[off:off + 4 * nw].view(torch.int32).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        return {"tail": w[:L * nseg].reshape(L, nseg), "near": w[L * nseg:L * nseg + nseg],
+                "fb": w[L * nseg + nseg:]}
 
     def check(self) -> int:
         torch.cuda.synchronize(self.ds.device)
@@ -299,11 +305,14 @@ class ContactEngine:
                 self.contacts = ContactBuffers.alloc(int(self.count() * 1.25) + 1024, self.ds.dtype,
                                                      self.ds.device)
             grow = False
+            # lists are split into 8 segments: size for the fullest one
             if status & _abi.DEM_DEV_QUEUE_OVERFLOW:
-                self.p.queue_capacity = max(2 * self.p.queue_capacity, int(1.25 * ctr["tail"].max()) + 1024)
+                need = 8 * int(ctr["tail"].max())
+                self.p.queue_capacity = max(2 * self.p.queue_capacity, int(1.25 * need) + 1024)
                 grow = True
             if status & _abi.DEM_DEV_NEAR_OVERFLOW:
-                self.p.near_capacity = max(2 * self.p.near_capacity, int(1.25 * ctr["near"]) + 1024)
+                need = 8 * int(max(ctr["near"].max(), ctr["fb"].max()))
+                self.p.near_capacity = max(2 * self.p.near_capacity, int(1.25 * need) + 1024)
                 grow = True
             if grow:
                 self.ws = None

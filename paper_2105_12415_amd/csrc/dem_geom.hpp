@@ -165,16 +165,14 @@ DEM_HD void to_simplex(T& a, T& b) {
 // N modified-Newton iterations on J (Section 3: diagonal Newton step on the
 // distance term, then a half-step on the constraint penalties; N fixed as
 // in Algorithm 4) for triangles A, B in pair-local coordinates (A.v0 at the
-// origin, B's first vertex at -D0), then the lower bound on the distance
-// along the unit direction u between the two iterate points:
-//     d(A, B) >= min_k u.b_k - max_k u.a_k.
-// Returns the bound (-inf if the two points coincide: nothing is pruned).
+// origin, B's first vertex at -D0).  Leaves the parameters projected into
+// the two triangles.
 template <typename T, int N>
-DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip) {
+DEM_HD void iterate_theta(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip, T& a1,
+                          T& b1, T& a2, T& b2) {
   const T om = T(ip.omega), k1 = T(ip.kappa1), k2 = T(ip.kappa2);
   // damped inverse diagonal of the regularised Hessian, per parameter
   const T s1 = om * A.ia, s2 = om * A.ib, s3 = om * B.ia, s4 = om * B.ib;
-  T a1, b1, a2, b2;
   V3<T> r;  // residual t_A(a1,b1) - t_B(a2,b2)
   if (ip.init_centroid) {
     a1 = b1 = a2 = b2 = T(1) / T(3);
@@ -197,6 +195,16 @@ DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterPar
   }
   to_simplex(a1, b1);
   to_simplex(a2, b2);
+}
+
+// The iteration followed by the lower bound on the distance along the unit
+// direction u between the two iterate points:
+//     d(A, B) >= min_k u.b_k - max_k u.a_k.
+// Returns the bound (-inf if the two points coincide: nothing is pruned).
+template <typename T, int N>
+DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip) {
+  T a1, b1, a2, b2;
+  iterate_theta<T, N>(A, B, D0, ip, a1, b1, a2, b2);
   // w = p2 - p1 between the two (feasible) iterate points
   V3<T> w = fma3(a2, B.e1, fma3(b2, B.e2, fma3(-a1, A.e1, fma3(-b1, A.e2, -D0))));
   T ww = dot(w, w);
@@ -396,6 +404,38 @@ DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T
   out.wp[0] = wp0; out.wp[1] = wp1; out.wp[2] = wp2;
   out.wq[0] = wq0; out.wq[1] = wq1; out.wq[2] = wq2;
   out.feature = feat;
+}
+
+// ------------------------------------------------------------------ certificate
+// Certified hybrid result for a pair the bound did not prune (Algorithm 4's
+// "found a contact point / no contact / not terminated", with the heuristic
+// convergence test replaced by a proof): the iterate's point on A is snapped
+// to the exact closest point on B, that one back onto A, and once more onto
+// B (alternating projections converge to a closest pair of the two convex
+// sets).  With U = |q - p| (an upper bound: both points are feasible) and
+// the separation bound L* along u = (q - p)/U, the distance lies in
+// [L*, U]; when U - L* <= tol, U is accepted as the distance.  Otherwise the
+// pair is "not terminated" and needs the comparison-based fallback.
+template <typename T, int N>
+DEM_HD bool certify_pair(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip, T rel_tol,
+                         T abs_tol, T& d, V3<T>& p, V3<T>& q, T wp[3], T wq[3]) {
+  T a1, b1, a2, b2;
+  iterate_theta<T, N>(A, B, D0, ip, a1, b1, a2, b2);
+  const V3<T> z = {T(0), T(0), T(0)};
+  const V3<T> b0 = -D0;
+  V3<T> p1 = fma3(a1, A.e1, b1 * A.e2);
+  V3<T> q1;
+  point_tri(p1, b0, B.e1, B.e2, q1, wq);
+  point_tri(q1, z, A.e1, A.e2, p, wp);
+  T d2 = point_tri(p, b0, B.e1, B.e2, q, wq);
+  T U = sq_(d2);
+  V3<T> w = q - p;
+  V3<T> u = (U > T(0) ? T(1) / U : T(0)) * w;
+  T hA = mx_(T(0), mx_(dot(u, A.e1), dot(u, A.e2)));
+  T hB = mn_(T(0), mn_(dot(u, B.e1), dot(u, B.e2))) - dot(u, D0);
+  T Ls = hB - hA;
+  d = U;
+  return U > abs_tol && (U - Ls) <= rel_tol * U + abs_tol;
 }
 
 }  // namespace dem

@@ -42,18 +42,23 @@ struct alignas(16) SoupRec {
   int32_t topo[4]; // child_begin, child_count, particle, size bound (float bits)
 };
 
+// Every work list is split into kSeg segments with a tail counter each; a
+// block appends to segment blockIdx % kSeg (its XCD under round-robin
+// dispatch).  Appends from all compute units to one tail serialise in the
+// memory-side atomic unit; eight tails spread them.
+constexpr int kSeg = 8;
+
 struct Counters {
-  uint32_t head[DEM_MAX_LEVELS + 1];
-  uint32_t tail[DEM_MAX_LEVELS + 1];
-  uint32_t near_tail;
-  uint32_t near_head;
-  uint32_t pad[30];
+  uint32_t tail[DEM_MAX_LEVELS + 1][kSeg];  // level queues
+  uint32_t near_tail[kSeg];                 // fine pairs not pruned
+  uint32_t fb_tail[kSeg];                   // pairs the certificate could not settle
+  uint32_t pad[16];
 };
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct WsLayout {
-  size_t ctr, soup, qa, qb, near_, total;
+  size_t ctr, soup, qa, qb, near_, fb, total;
 };
 
 WsLayout ws_layout(int precision, int64_t n_tris, int64_t qcap, int64_t ncap) {
@@ -65,6 +70,7 @@ WsLayout ws_layout(int precision, int64_t n_tris, int64_t qcap, int64_t ncap) {
   L.qa = o; o = align_up(o + 16 * (size_t)qcap, 256);
   L.qb = o; o = align_up(o + 16 * (size_t)qcap, 256);
   L.near_ = o; o = align_up(o + 8 * (size_t)ncap, 256);
+  L.fb = o; o = align_up(o + 8 * (size_t)ncap, 256);
   L.total = o;
   return L;
 }
@@ -189,10 +195,11 @@ __global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, in
   if (ccnt[t] < 0 || ccnt[t] > DEM_MAX_CHILDREN) atomicOr(status, DEM_DEV_BAD_TREE);
 }
 
-// One block per candidate pair: items covering range_i x range_j in chunks.
+// One block per candidate pair: items covering range_i x range_j in chunks,
+// appended to segment blockIdx % kSeg of the level-0 list.
 __global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
                        const int32_t* __restrict__ rbeg, const int32_t* __restrict__ rcnt, int ci,
-                       int cj, int4* __restrict__ q, uint32_t* tail, int64_t cap,
+                       int cj, int4* __restrict__ q, uint32_t* tails, int64_t seg_cap,
                        uint32_t* status) {
   int pr = blockIdx.x;
   if (pr >= n_pairs) return;
@@ -200,9 +207,11 @@ __global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
   int bi = rbeg[pi], ni = rcnt[pi], bj = rbeg[pj], nj = rcnt[pj];
   int nci = (ni + ci - 1) / ci, ncj = (nj + cj - 1) / cj;
   int n = nci * ncj;
+  const uint32_t x = blockIdx.x % kSeg;
   __shared__ uint32_t base;
-  if (threadIdx.x == 0) base = n > 0 ? atomicAdd(tail, (uint32_t)n) : 0u;
+  if (threadIdx.x == 0) base = n > 0 ? atomicAdd(&tails[x], (uint32_t)n) : 0;
   __syncthreads();
+  int4* seg = q + (size_t)x * (size_t)seg_cap;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     int ii = k / ncj, jj = k - ii * ncj;
     int4 it;
@@ -211,8 +220,8 @@ __global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
     it.z = bj + jj * cj;
     it.w = min(cj, nj - jj * cj);
     uint64_t slot = (uint64_t)base + (uint64_t)k;
-    if (slot < (uint64_t)cap)
-      q[slot] = it;
+    if (slot < (uint64_t)seg_cap)
+      seg[slot] = it;
     else
       atomicOr(status, DEM_DEV_QUEUE_OVERFLOW);
   }
@@ -247,14 +256,13 @@ __device__ __forceinline__ void block_scan(int v, int* offs, int* wsum, int n) {
 
 struct LevelArgs {
   const int4* qin;
-  const uint32_t* tail_in;
-  uint32_t* head_in;
+  const uint32_t* tail_in;   // [kSeg]
   int4* qout;
-  uint32_t* tail_out;
-  int64_t qcap;
+  uint32_t* tail_out;        // [kSeg]
+  int64_t qcap;              // entries per segment
   int2* near_;
-  uint32_t* near_tail;
-  int64_t ncap;
+  uint32_t* near_tail;       // [kSeg]
+  int64_t ncap;              // entries per segment
   dem_stats* stats;
   uint32_t* status;
   int depth;
@@ -286,21 +294,49 @@ __device__ __forceinline__ void lds_append(bool pred, R rec, R* buf, uint32_t* n
   if (pred) buf[base + (uint32_t)__popcll(m & lt)] = rec;
 }
 
-// Copy an LDS queue to global memory at a reserved range (whole block).
+// Copy an LDS queue to global memory (whole block): one atomic on the tail of
+// this block's segment reserves the range.  seg_cap = entries per segment.
 template <typename R, int CAP>
-__device__ __forceinline__ void lds_flush(LdsQueue<R, CAP>& q, uint32_t* tail, R* out, int64_t cap,
+__device__ __forceinline__ void lds_flush(LdsQueue<R, CAP>& q, uint32_t* tails, R* out, int64_t seg_cap,
                                           uint32_t* status, uint32_t flag) {
-  if (threadIdx.x == 0) q.gbase = q.n ? atomicAdd(tail, q.n) : 0u;
+  const uint32_t x = blockIdx.x % kSeg;
+  if (threadIdx.x == 0) q.gbase = q.n ? atomicAdd(&tails[x], q.n) : 0u;
   __syncthreads();
   const uint32_t n = q.n, g = q.gbase;
+  R* seg = out + (size_t)x * (size_t)seg_cap;
   for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
     uint64_t slot = (uint64_t)g + k;
-    if (slot < (uint64_t)cap) out[slot] = q.buf[k];
+    if (slot < (uint64_t)seg_cap) seg[slot] = q.buf[k];
     else atomicOr(status, flag);
   }
   __syncthreads();
   if (threadIdx.x == 0) q.n = 0;
   __syncthreads();
+}
+
+// Consumer side of a segmented list: prefix of the segment fills.
+struct SegView {
+  uint32_t pre[kSeg + 1];
+};
+
+__device__ __forceinline__ void seg_view(SegView& v, const uint32_t* tails, int64_t seg_cap) {
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    v.pre[0] = 0;
+    for (int x = 0; x < kSeg; ++x) {
+      acc += (uint32_t)min((uint64_t)tails[x], (uint64_t)seg_cap);
+      v.pre[x + 1] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Storage index of the i-th entry (i < v.pre[kSeg]).
+__device__ __forceinline__ size_t seg_index(const SegView& v, uint32_t i, int64_t seg_cap) {
+  int x = 0;
+#pragma unroll
+  for (int k = 1; k < kSeg; ++k) x += (i >= v.pre[k]) ? 1 : 0;
+  return (size_t)x * (size_t)seg_cap + (i - v.pre[x]);
 }
 
 constexpr int kStageItems = 512;
@@ -324,17 +360,19 @@ __device__ __forceinline__ uint32_t xcd_swizzle(uint32_t bid, uint32_t grid) {
 #define DEM_BLOCK_ORDER(b, g) xcd_swizzle(b, g)
 #endif
 
-constexpr int kOwnerCap = 4096;  // child pairs mapped to their item through LDS
 
-template <typename T, int N>
-__global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
-  __shared__ int4 items[256];
-  __shared__ int offs[257];
+template <typename T, int N, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
+  // LDS sized to the block: one item per thread, stages of two rounds
+  __shared__ int4 items[BLOCK];
+  __shared__ int offs[BLOCK + 1];
   __shared__ int wsum[16];
-  __shared__ uint8_t owner_s[kOwnerCap];
-  __shared__ LdsQueue<int4, kStageItems> qi;
-  __shared__ LdsQueue<int2, kStageNear> qn;
-  const uint32_t count = min((uint64_t)*a.tail_in, (uint64_t)a.qcap);
+  __shared__ uint8_t owner_s[BLOCK * 16];
+  __shared__ LdsQueue<int4, 2 * BLOCK> qi;
+  __shared__ LdsQueue<int2, 2 * BLOCK> qn;
+  __shared__ SegView view;
+  seg_view(view, a.tail_in, a.qcap);
+  const uint32_t count = view.pre[kSeg];
   const uint32_t bdim = blockDim.x;
   unsigned long long my_evals = 0, my_surv = 0, my_near = 0;
   if (threadIdx.x == 0) { qi.n = 0; qn.n = 0; }
@@ -344,7 +382,7 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
     int n = (int)min((uint32_t)a.batch, count - b);
     int np = 0;
     if ((int)threadIdx.x < n) {
-      int4 it = a.qin[b + threadIdx.x];
+      int4 it = a.qin[seg_index(view, b + threadIdx.x, a.qcap)];
       if (it.y < 1 || it.y > DEM_MAX_CHILDREN || it.w < 1 || it.w > DEM_MAX_CHILDREN) {
         atomicOr(a.status, DEM_DEV_BAD_TREE);  // malformed tree: skip the item
         it.y = it.w = 0;
@@ -356,7 +394,7 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
     const int total = offs[n];
     // small batches (the usual 4x4 children products) map pair -> item
     // through an LDS table; large ones (root chunks) search the offsets
-    const bool mapped = total <= kOwnerCap && n <= 256;
+    const bool mapped = total <= BLOCK * 16 && n <= 256;
     if (mapped && (int)threadIdx.x < n) {
       const int o = offs[threadIdx.x];
       for (int q = 0; q < np; ++q) owner_s[o + q] = (uint8_t)threadIdx.x;
@@ -409,9 +447,9 @@ __global__ void __launch_bounds__(256) k_level(const SoupRec<T>* __restrict__ so
       lds_append(push_near, make_int2(ci, cj), qn.buf, &qn.n);
       __syncthreads();
       // flush when another round could overflow the stage (uniform test)
-      if (qi.n + bdim > (uint32_t)kStageItems)
+      if (qi.n + bdim > (uint32_t)(2 * BLOCK))
         lds_flush(qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
-      if (qn.n + bdim > (uint32_t)kStageNear)
+      if (qn.n + bdim > (uint32_t)(2 * BLOCK))
         lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
     }
     __syncthreads();
@@ -441,13 +479,15 @@ template <typename T, int N, int TJ>
 __global__ void __launch_bounds__(256) k_flat(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
   __shared__ SoupRec<T> tj_s[TJ];
   __shared__ LdsQueue<int2, kStageFlat> qn;
-  const uint32_t count = min((uint64_t)*a.tail_in, (uint64_t)a.qcap);
+  __shared__ SegView view;
+  seg_view(view, a.tail_in, a.qcap);
+  const uint32_t count = view.pre[kSeg];
   const uint32_t bdim = blockDim.x;
   unsigned long long my_evals = 0, my_near = 0;
   if (threadIdx.x == 0) qn.n = 0;
   __syncthreads();
   for (uint32_t b = blockIdx.x; b < count; b += gridDim.x) {
-    int4 it = a.qin[b];
+    int4 it = a.qin[seg_index(view, b, a.qcap)];
     // stage the j-triangles in LDS
     for (int k = threadIdx.x; k < it.w; k += bdim) tj_s[k] = soup[it.z + k];
     __syncthreads();
@@ -493,9 +533,11 @@ __global__ void __launch_bounds__(256) k_flat(const SoupRec<T>* __restrict__ sou
 }
 
 struct NearArgs {
-  const int2* near_;
+  const int2* near_;       // pairs to settle
   const uint32_t* near_tail;
   int64_t ncap;
+  int2* fb;                // certify pass: pairs left for the exact pass
+  uint32_t* fb_tail;
   int32_t* pi;
   int32_t* pj;
   int32_t* ti;
@@ -510,6 +552,7 @@ struct NearArgs {
   double* energy;
   dem_stats* stats;
   uint32_t* status;
+  IterParams ip;
 };
 
 template <typename T>
@@ -521,75 +564,14 @@ struct ContactRec {
 constexpr int kStageContacts = 512;
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
-  __shared__ LdsQueue<ContactRec<T>, kStageContacts> qc;
-  const uint32_t cnt = min((uint64_t)*a.near_tail, (uint64_t)a.ncap);
+__device__ __forceinline__ void write_contacts(LdsQueue<ContactRec<T>, kStageContacts>& qc,
+                                               const NearArgs& a) {
   T* dd = static_cast<T*>(a.d);
   T* xx = static_cast<T*>(a.x);
   T* nn = static_cast<T*>(a.n);
-  const uint32_t bdim = blockDim.x;
-  double e_acc = 0.0;
-  unsigned long long my_fb = 0, my_c = 0;
-  if (threadIdx.x == 0) qc.n = 0;
-  __syncthreads();
-  for (uint32_t base = blockIdx.x * bdim; base < cnt; base += gridDim.x * bdim) {
-    const uint32_t e = base + threadIdx.x;
-    bool emit = false;
-    ContactRec<T> rec;
-    if (e < cnt) {
-      int2 pr = a.near_[e];
-      int cbi, cci, cbj, ccj, pi_, pj_;
-      Tri<T> A = load_tri(soup, pr.x, cbi, cci, pi_);
-      Tri<T> B = load_tri(soup, pr.y, cbj, ccj, pj_);
-      V3<T> D0 = A.v0 - B.v0;
-      Closest<T> c;
-      exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, c);
-      ++my_fb;
-      T d = sq_(c.d2);
-      T delta = a.dense ? T(INFINITY) : A.eps + B.eps;
-      emit = d <= delta;
-      if (!isfinite(d)) atomicOr(a.status, DEM_DEV_NONFINITE);
-      // contact point at the centre of the overlap of the two environments
-      V3<T> w = c.q - c.p;
-      T lam = d > T(0) ? (d + A.eps - B.eps) / (T(2) * d) : T(0);
-      V3<T> xl = fma3(lam, w, c.p);
-      V3<T> nc = c.p - xl;
-      V3<T> xc = xl + A.v0;
-      rec.pi = pi_; rec.pj = pj_; rec.ti = pr.x; rec.tj = pr.y; rec.d = d;
-      rec.x[0] = xc.x; rec.x[1] = xc.y; rec.x[2] = xc.z;
-      rec.n[0] = nc.x; rec.n[1] = nc.y; rec.n[2] = nc.z;
-      if (emit && !a.dense) {
-        double pen = (double)delta - (double)d;
-        e_acc += a.k * pen * pen;
-      }
-      my_c += emit;
-    }
-    lds_append(emit, rec, qc.buf, &qc.n);
-    __syncthreads();
-    if (qc.n + bdim > (uint32_t)kStageContacts) {
-      if (threadIdx.x == 0) qc.gbase = atomicAdd(a.count, qc.n);
-      __syncthreads();
-      for (uint32_t k = threadIdx.x; k < qc.n; k += bdim) {
-        uint64_t slot = (uint64_t)qc.gbase + k;
-        const ContactRec<T>& r = qc.buf[k];
-        if (slot < (uint64_t)a.ccap) {
-          a.pi[slot] = r.pi; a.pj[slot] = r.pj; a.ti[slot] = r.ti; a.tj[slot] = r.tj;
-          dd[slot] = r.d;
-          xx[slot] = r.x[0]; xx[a.ccap + slot] = r.x[1]; xx[2 * a.ccap + slot] = r.x[2];
-          nn[slot] = r.n[0]; nn[a.ccap + slot] = r.n[1]; nn[2 * a.ccap + slot] = r.n[2];
-        } else {
-          atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) qc.n = 0;
-      __syncthreads();
-    }
-  }
-  // final flush
   if (threadIdx.x == 0) qc.gbase = qc.n ? atomicAdd(a.count, qc.n) : 0u;
   __syncthreads();
-  for (uint32_t k = threadIdx.x; k < qc.n; k += bdim) {
+  for (uint32_t k = threadIdx.x; k < qc.n; k += blockDim.x) {
     uint64_t slot = (uint64_t)qc.gbase + k;
     const ContactRec<T>& r = qc.buf[k];
     if (slot < (uint64_t)a.ccap) {
@@ -601,20 +583,115 @@ __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ sou
       atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) qc.n = 0;
+  __syncthreads();
+}
+
+// Certification tolerances (FP32 / FP64): accept U when U - L* <= rel U + abs,
+// abs proportional to the pair's size bounds.
+template <typename T>
+struct CertTol;
+template <>
+struct CertTol<float> {
+  static constexpr float rel = 4e-6f, abs = 1e-7f;
+};
+template <>
+struct CertTol<double> {
+  static constexpr double rel = 1e-13, abs = 1e-15;
+};
+
+// Settle near pairs (fine pairs the lower bound did not prune) and emit the
+// contacts, d <= eps_i + eps_j.  CERTIFY: the iterate + snap + certificate
+// of certify_pair(); pairs it cannot settle go to the fallback list.
+// Otherwise: the exact comparison-based distance for every listed pair.
+template <typename T, int N, bool CERTIFY>
+__global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
+  __shared__ LdsQueue<ContactRec<T>, kStageContacts> qc;
+  __shared__ LdsQueue<int2, kStageNear> qf;
+  __shared__ SegView view;
+  seg_view(view, a.near_tail, a.ncap);
+  const uint32_t cnt = view.pre[kSeg];
+  const uint32_t bdim = blockDim.x;
+  double e_acc = 0.0;
+  unsigned long long my_fb = 0, my_cert = 0, my_c = 0;
+  if (threadIdx.x == 0) { qc.n = 0; qf.n = 0; }
+  __syncthreads();
+  for (uint32_t base = blockIdx.x * bdim; base < cnt; base += gridDim.x * bdim) {
+    const uint32_t e = base + threadIdx.x;
+    bool emit = false, defer = false;
+    ContactRec<T> rec;
+    int2 pr = make_int2(0, 0);
+    if (e < cnt) {
+      pr = a.near_[seg_index(view, e, a.ncap)];
+      int cbi, cci, cbj, ccj, pi_, pj_;
+      Tri<T> A = load_tri(soup, pr.x, cbi, cci, pi_);
+      Tri<T> B = load_tri(soup, pr.y, cbj, ccj, pj_);
+      V3<T> D0 = A.v0 - B.v0;
+      T d;
+      V3<T> cp, cq;
+      bool settled = true;
+      if constexpr (CERTIFY) {
+        T wp[3], wq[3];
+        settled = certify_pair<T, N>(A, B, D0, a.ip, CertTol<T>::rel, CertTol<T>::abs * (A.size + B.size),
+                                     d, cp, cq, wp, wq);
+        my_cert += settled;
+        defer = !settled;
+      } else {
+        Closest<T> c;
+        exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, c);
+        ++my_fb;
+        d = sq_(c.d2);
+        cp = c.p;
+        cq = c.q;
+      }
+      if (settled) {
+        T delta = a.dense ? T(INFINITY) : A.eps + B.eps;
+        emit = d <= delta;
+        if (!isfinite(d)) atomicOr(a.status, DEM_DEV_NONFINITE);
+        // contact point at the centre of the overlap of the two environments
+        V3<T> w = cq - cp;
+        T lam = d > T(0) ? (d + A.eps - B.eps) / (T(2) * d) : T(0);
+        V3<T> xl = fma3(lam, w, cp);
+        V3<T> nc = cp - xl;
+        V3<T> xc = xl + A.v0;
+        rec.pi = pi_; rec.pj = pj_; rec.ti = pr.x; rec.tj = pr.y; rec.d = d;
+        rec.x[0] = xc.x; rec.x[1] = xc.y; rec.x[2] = xc.z;
+        rec.n[0] = nc.x; rec.n[1] = nc.y; rec.n[2] = nc.z;
+        if (emit && !a.dense) {
+          double pen = (double)delta - (double)d;
+          e_acc += a.k * pen * pen;
+        }
+        my_c += emit;
+      }
+    }
+    lds_append(emit, rec, qc.buf, &qc.n);
+    if constexpr (CERTIFY) lds_append(defer, pr, qf.buf, &qf.n);
+    __syncthreads();
+    if (qc.n + bdim > (uint32_t)kStageContacts) write_contacts(qc, a);
+    if constexpr (CERTIFY) {
+      if (qf.n + bdim > (uint32_t)kStageNear)
+        lds_flush(qf, a.fb_tail, a.fb, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+    }
+  }
+  write_contacts(qc, a);
+  if constexpr (CERTIFY) lds_flush(qf, a.fb_tail, a.fb, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
   if (a.energy) {
     double sum = wave_sum(e_acc);
     if (lane_id() == 0 && sum != 0.0) atomicAdd(a.energy, sum);
   }
   if (a.stats) {
-    unsigned long long s0 = my_fb, s1 = my_c;
+    unsigned long long s0 = my_fb, s1 = my_c, s2 = my_cert;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       s0 += __shfl_xor(s0, o);
       s1 += __shfl_xor(s1, o);
+      s2 += __shfl_xor(s2, o);
     }
     if (lane_id() == 0) {
       if (s0) atomicAdd(&a.stats->fallback, s0);
       if (s1) atomicAdd(&a.stats->contacts, s1);
+      if (s2) atomicAdd(&a.stats->certified, s2);
     }
   }
 }
@@ -751,13 +828,13 @@ bool params_ok(const dem_params& p) {
   if (p.mode != DEM_MODE_FLAT && p.mode != DEM_MODE_HIER) return false;
   if (p.n_iter < 0 || p.n_iter > 8) return false;
   if (!(p.omega > 0.0f) || !(p.alpha_reg_rel >= 0.0f) || !(p.alpha_it_ratio > 0.0f)) return false;
-  if (p.block < 64 || p.block > 256 || p.block % 64) return false;
+  if (p.block != 64 && p.block != 128 && p.block != 256) return false;
   if (p.batch_items < 1 || p.batch_items > p.block) return false;
   if (p.flat_tile_i < 64 || p.flat_tile_i > 1024 || p.flat_tile_i % 64) return false;
   if (p.flat_tile_j < 1 || p.flat_tile_j > 64) return false;
   if (p.seed_chunk < 1 || p.seed_chunk > 16) return false;
-  if (p.queue_capacity < 1 || p.queue_capacity > (int64_t)0xFFFFFFFF) return false;
-  if (p.near_capacity < 1 || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
+  if (p.queue_capacity < kSeg || p.queue_capacity > (int64_t)0xFFFFFFFF) return false;
+  if (p.near_capacity < kSeg || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.grid < 0) return false;
   if (p.n_events < 0 || (p.n_events > 0 && !p.events)) return false;
   return true;
@@ -765,19 +842,35 @@ bool params_ok(const dem_params& p) {
 
 // The Newton iteration count is a template parameter so the iteration is
 // fully unrolled; counts 0..8 are instantiated.
-template <typename T>
-void launch_level(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
+template <typename T, int BLOCK>
+void launch_level_b(int n_iter, dim3 g, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
   switch (n_iter) {
-#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_level<T, N>), g, b, 0, st, soup, la); break;
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_level<T, N, BLOCK>), g, dim3(BLOCK), 0, st, soup, la); break;
     DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
 #undef DEM_CASE
   }
 }
 
 template <typename T>
+void launch_level(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
+  if (b.x == 64) launch_level_b<T, 64>(n_iter, g, st, soup, la);
+  else if (b.x == 128) launch_level_b<T, 128>(n_iter, g, st, soup, la);
+  else launch_level_b<T, 256>(n_iter, g, st, soup, la);
+}
+
+template <typename T>
 void launch_flat(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
   switch (n_iter) {
 #define DEM_CASE(N) case N: hipLaunchKernelGGL((k_flat<T, N, 64>), g, b, 0, st, soup, la); break;
+    DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
+#undef DEM_CASE
+  }
+}
+
+template <typename T>
+void launch_near_certify(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const NearArgs& na) {
+  switch (n_iter) {
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_near<T, N, true>), g, b, 0, st, soup, na); break;
     DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
 #undef DEM_CASE
   }
@@ -808,11 +901,13 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
                      static_cast<const T*>(s->tri_eps), static_cast<const T*>(s->pose),
                      T(p.alpha_reg_rel), soup, status);
   mark();
+  // per-segment capacities
+  const int64_t qseg = p.queue_capacity / kSeg, nseg = p.near_capacity / kSeg;
   LevelArgs la;
-  la.qcap = p.queue_capacity;
+  la.qcap = qseg;
   la.near_ = nearl;
-  la.near_tail = &ctr->near_tail;
-  la.ncap = p.near_capacity;
+  la.near_tail = ctr->near_tail;
+  la.ncap = nseg;
   la.stats = stats;
   la.status = status;
   la.dense = p.dense_distance;
@@ -821,29 +916,25 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   if (n_pairs > 0) {
     if (p.mode == DEM_MODE_HIER) {
       hipLaunchKernelGGL(k_seed, dim3(n_pairs), dim3(256), 0, st, pairs, n_pairs, s->root_begin,
-                         s->root_count, p.seed_chunk, p.seed_chunk, q[0], &ctr->tail[0],
-                         p.queue_capacity, status);
+                         s->root_count, p.seed_chunk, p.seed_chunk, q[0], ctr->tail[0], qseg, status);
       mark();
       for (int lev = 0; lev < s->n_levels_max; ++lev) {
         la.qin = q[lev & 1];
-        la.tail_in = &ctr->tail[lev];
-        la.head_in = &ctr->head[lev];
+        la.tail_in = ctr->tail[lev];
         la.qout = q[(lev + 1) & 1];
-        la.tail_out = &ctr->tail[lev + 1];
+        la.tail_out = ctr->tail[lev + 1];
         la.depth = lev;
         launch_level<T>(p.n_iter, dim3(grid), dim3(p.block), st, soup, la);
         mark();
       }
     } else {
       hipLaunchKernelGGL(k_seed, dim3(n_pairs), dim3(256), 0, st, pairs, n_pairs, s->fine_begin,
-                         s->fine_count, p.flat_tile_i, p.flat_tile_j, q[0], &ctr->tail[0],
-                         p.queue_capacity, status);
+                         s->fine_count, p.flat_tile_i, p.flat_tile_j, q[0], ctr->tail[0], qseg, status);
       mark();
       la.qin = q[0];
-      la.tail_in = &ctr->tail[0];
-      la.head_in = &ctr->head[0];
+      la.tail_in = ctr->tail[0];
       la.qout = q[1];
-      la.tail_out = &ctr->tail[1];
+      la.tail_out = ctr->tail[1];
       la.depth = 0;
       launch_flat<T>(p.n_iter, dim3(grid), dim3(p.flat_tile_i > 256 ? 256 : p.flat_tile_i), st, soup, la);
       mark();
@@ -851,8 +942,10 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   }
   NearArgs na;
   na.near_ = nearl;
-  na.near_tail = &ctr->near_tail;
-  na.ncap = p.near_capacity;
+  na.near_tail = ctr->near_tail;
+  na.ncap = nseg;
+  na.fb = reinterpret_cast<int2*>(base + L.fb);
+  na.fb_tail = ctr->fb_tail;
   na.pi = out->pi; na.pj = out->pj; na.ti = out->ti; na.tj = out->tj;
   na.d = out->d; na.x = out->x; na.n = out->n;
   na.count = out->count;
@@ -862,7 +955,15 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   na.energy = energy;
   na.stats = stats;
   na.status = status;
-  hipLaunchKernelGGL(k_near<T>, dim3(grid), dim3(p.block), 0, st, soup, na);
+  na.ip = make_iter(p);
+  if (p.certify) {
+    launch_near_certify<T>(p.n_iter, dim3(grid), dim3(p.block), st, soup, na);
+    mark();
+    // the exact comparison-based pass over what the certificate left
+    na.near_ = na.fb;
+    na.near_tail = na.fb_tail;
+  }
+  hipLaunchKernelGGL((k_near<T, 0, false>), dim3(grid), dim3(p.block), 0, st, soup, na);
   mark();
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }

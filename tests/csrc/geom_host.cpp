@@ -70,3 +70,43 @@ extern "C" void geom_bound(const double* pairs, long n, int use_double, const fl
     else bound_one<float>(pairs + 18 * i, prm, out + 7 * i);
   }
 }
+
+template <typename T>
+static void certify_one(const double* P, const float* prm, double* out) {
+  V3<T> a0{(T)P[0], (T)P[1], (T)P[2]}, a1{(T)P[3], (T)P[4], (T)P[5]}, a2{(T)P[6], (T)P[7], (T)P[8]};
+  V3<T> b0{(T)P[9], (T)P[10], (T)P[11]}, b1{(T)P[12], (T)P[13], (T)P[14]}, b2{(T)P[15], (T)P[16], (T)P[17]};
+  Tri<T> A, B;
+  A.v0 = a0; A.e1 = a1 - a0; A.e2 = a2 - a0; A.eps = 0;
+  B.v0 = b0; B.e1 = b1 - b0; B.e2 = b2 - b0; B.eps = 0;
+  A.size = tri_size(A.e1, A.e2);
+  B.size = tri_size(B.e1, B.e2);
+  T areg = (T)prm[2];
+  T n1 = dot(A.e1, A.e1), n2 = dot(A.e2, A.e2);
+  T r = areg * T(0.5) * (n1 + n2);
+  A.ia = T(1) / (n1 + r); A.ib = T(1) / (n2 + r);
+  n1 = dot(B.e1, B.e1); n2 = dot(B.e2, B.e2);
+  r = areg * T(0.5) * (n1 + n2);
+  B.ia = T(1) / (n1 + r); B.ib = T(1) / (n2 + r);
+  IterParams ip;
+  ip.n_iter = 4;
+  ip.omega = prm[1];
+  double rho = prm[3];
+  ip.kappa1 = (float)(rho / (rho + 1.0));
+  ip.kappa2 = (float)(rho / (2.0 * rho + 1.0));
+  ip.init_centroid = (int)prm[4];
+  V3<T> D0 = A.v0 - B.v0;
+  T d, wp[3], wq[3];
+  V3<T> p, q;
+  T rel = sizeof(T) == 4 ? T(4e-6) : T(1e-13);
+  T ab = (sizeof(T) == 4 ? T(1e-7) : T(1e-15)) * (A.size + B.size);
+  bool ok = certify_pair<T, 4>(A, B, D0, ip, rel, ab, d, p, q, wp, wq);
+  out[0] = ok ? 1.0 : 0.0;
+  out[1] = d;
+}
+
+extern "C" void geom_certify(const double* pairs, long n, int use_double, const float* prm, double* out) {
+  for (long i = 0; i < n; ++i) {
+    if (use_double) certify_one<double>(pairs + 18 * i, prm, out + 2 * i);
+    else certify_one<float>(pairs + 18 * i, prm, out + 2 * i);
+  }
+}

@@ -26,6 +26,7 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.geom_exact.argtypes = [dp, C.c_long, C.c_int, dp]
         L.geom_bound.argtypes = [dp, C.c_long, C.c_int, C.POINTER(C.c_float), dp]
+        L.geom_certify.argtypes = [dp, C.c_long, C.c_int, C.POINTER(C.c_float), dp]
         _lib = L
     return _lib
 
@@ -46,3 +47,12 @@ def bound(pairs, double=True, n_iter=4, omega=1.0, areg=1e-4, rho=1e3, centroid=
     lib().geom_bound(P.ctypes.data_as(C.POINTER(C.c_double)), len(P), int(double),
                      prm.ctypes.data_as(C.POINTER(C.c_float)), out.ctypes.data_as(C.POINTER(C.c_double)))
     return {"L": out[:, 0], "slack": out[:, 1], "up": out[:, 2], "theta": out[:, 3:7]}
+
+
+def certify(pairs, double=True, omega=1.0, areg=1e-4, rho=1e3, centroid=0):
+    P = np.ascontiguousarray(np.asarray(pairs, np.float64).reshape(-1, 18))
+    prm = np.array([4, omega, areg, rho, centroid], np.float32)
+    out = np.zeros((len(P), 2))
+    lib().geom_certify(P.ctypes.data_as(C.POINTER(C.c_double)), len(P), int(double),
+                       prm.ctypes.data_as(C.POINTER(C.c_float)), out.ctypes.data_as(C.POINTER(C.c_double)))
+    return {"ok": out[:, 0] > 0, "d": out[:, 1]}

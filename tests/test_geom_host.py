@@ -47,3 +47,26 @@ def test_lower_bound_never_exceeds_distance(double, n_iter, omega, centroid):
     # the bound is informative for well separated pairs
     far = ref["d"] > _h(P)
     assert np.mean(b["L"][far] > 0.5 * ref["d"][far]) > 0.9
+
+
+def _contact_like_pairs(n, seed):
+    """Nearby pairs of bumped-sphere-like triangles: small triangles a short
+    gap apart with random orientations (the pairs the descent hands on)."""
+    rng = np.random.default_rng(seed)
+    c = rng.normal(size=(n, 3))
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    A = rng.uniform(-0.05, 0.05, (n, 3, 3))
+    B = rng.uniform(-0.05, 0.05, (n, 3, 3)) + (c * rng.uniform(0.0, 0.12, (n, 1)))[:, None, :]
+    return np.stack([A, B], 1) + rng.uniform(-20, 20, (n, 1, 1, 3))
+
+
+@pytest.mark.parametrize("double,r,a", [(True, 1e-12, 1e-13), (False, 1e-5, 1e-6)])
+def test_certified_distances_are_exact(double, r, a):
+    """Whenever the certificate accepts, the distance meets the parity bar."""
+    for P in (_contact_like_pairs(40000, 31).astype(np.float32).astype(np.float64), _cases()):
+        ref = oracle.tri_tri_batch(P)
+        c = host_geom.certify(P, double)
+        ok = c["ok"]
+        err = np.abs(c["d"][ok] - ref["d"][ok]) - (r * ref["d"][ok] + a * _h(P)[ok])
+        assert np.all(err <= 0), np.max(err)
+        assert ok.mean() > 0.3  # it settles a good share of pairs

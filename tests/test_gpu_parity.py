@@ -321,3 +321,18 @@ def test_pose_small_rigid_motion_within_rounding():
     for key in set(g) - set(o):
         assert abs(oracle.tri_tri(*pair_geom(fs, *key))["d"] - 0.1) <= tol["band"]
     assert len(common) > 100
+
+
+def test_certified_hybrid_matches_exact_fallback():
+    """certify=1 (iterate + snap + certificate, fallback for the rest) and
+    certify=0 (exact distance for every near pair) give the same contacts,
+    and both meet the oracle bar."""
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=50, name="cert")
+    ds, e1, r1 = run(scene, "hier", certify=1)
+    _, e0, r0 = run(scene, "hier", certify=0)
+    st = e1.stats_dict()
+    assert st["certified"] > 0 and st["certified"] + st["fallback"] == st["near"]
+    assert e0.stats_dict()["certified"] == 0
+    ref = oracle.find_contacts(oracle.fine_scene(scene))
+    compare_sets(scene, ds, r1, ref, TOL["f32"])
+    compare_sets(scene, ds, r0, ref, TOL["f32"])
