@@ -171,7 +171,8 @@ def kernel_times(torch, step: Step, K: int):
     return acc / K, bwd / K, stats_acc
 
 
-def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capacity):
+def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capacity, tune=True):
+    from paper_2105_12415_amd import autotune
     p = api.make_params(mode, **params_kw)
     eng = api.ContactEngine(ds, p, contact_capacity=contact_capacity, energy_k=1e4)
     step = Step(ds, eng, backward, K, torch)
@@ -181,6 +182,16 @@ def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capac
     status = eng.check()
     if status:
         raise RuntimeError(f"device status {status:#x}")
+    eng.tuned = None
+    if tune:
+        space = None
+        if mode == "flat":
+            space = {"flat_tile_i": (256, 128), "omega": (1.0, 0.5)}
+        space = {k: v for k, v in (space or autotune.HIER_SPACE).items() if k not in params_kw}
+        best, log = autotune.tune_engine(eng, lambda: step(0), space=space, reps=1 if mode == "flat" else 5)
+        eng.tuned = {"chosen": best, "candidates": len(log)}
+        step.pose(0)
+        eng.run()
     ms_graph, ms_wall, graph = time_graph(torch, step, K, warmup)
     status = eng.check()
     if status:
@@ -224,6 +235,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=60)
     ap.add_argument("--contact-capacity", type=int, default=1 << 23)
     ap.add_argument("--param", action="append", default=[], help="dem_params override, e.g. omega=0.5")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -259,7 +271,8 @@ def main():
         f"{ds.n_pairs} candidate pairs, {ds.n_fine_pairs()} fine pairs")
 
     eng, step, ms, ms_wall, kt, bwd_ms, st = run_mode(torch, api, ds, "hier", backward, K, args.warmup,
-                                                     params_kw, args.contact_capacity)
+                                                     params_kw, args.contact_capacity,
+                                                     tune=not args.no_autotune)
     evals = float(np.sum(st["evals"]))
     log(f"[bench] hier: {ms:.3f} ms/step (wall {ms_wall:.3f}), {evals:.4g} evals/step, "
         f"{st['contacts']:.0f} contacts, near {st['near']:.0f}")
@@ -291,7 +304,8 @@ def main():
                       f"per-step rigid perturbation, {K} steps captured in one HIP graph" if backward else
                       f"; forward contacts, {K} steps captured in one HIP graph"),
                       "particles": ds.n_particles, "triangles_all_levels": ds.n_tris,
-                      "candidate_pairs": ds.n_pairs, "fine_pairs": ds.n_fine_pairs(), "n_iter": n_iter},
+                      "candidate_pairs": ds.n_pairs, "fine_pairs": ds.n_fine_pairs(), "n_iter": n_iter,
+                      "autotuned": eng.tuned},
            "roofline": roof, "kernels": kernels,
            "stats": {"evals_per_level": [int(x) for x in st["evals"][:L]],
                      "survivors_per_level": [int(x) for x in st["survivors"][:L]],
@@ -301,9 +315,10 @@ def main():
         del eng, step
         torch.cuda.empty_cache()
         fe, fstep, fms, fwall, fkt, fbwd, fst = run_mode(torch, api, ds, "flat", backward, args.flat_steps,
-                                                       0, params_kw, args.contact_capacity)
+                                                       0, params_kw, args.contact_capacity,
+                                                       tune=not args.no_autotune)
         fevals = float(np.sum(fst["evals"]))
-        out["flat"] = {"ms_per_step": fms, "ms_per_step_wall": fwall, "evals_per_step": fevals,
+        out["flat"] = {"autotuned": fe.tuned, "ms_per_step": fms, "ms_per_step_wall": fwall, "evals_per_step": fevals,
                        "evals_per_s": fevals / (fms * 1e-3), "contacts": fst["contacts"],
                        "flat_kernel_ms": float(fkt[3]), "near_ms": float(np.sum(fkt[4:])),
                        "flat_kernel_TFLOPs": flops_per_eval(n_iter) * fevals / (fkt[3] * 1e-3) / 1e12}

@@ -1,0 +1,125 @@
+"""Autotuner for the launch shape and tiling of the contact path.
+
+Coordinate descent over a small space of dem_params knobs: each knob in
+turn takes every candidate value while the others hold their best values so
+far, and the fastest value stays.  Candidates are timed on the caller's own
+scene and step (HIP events on the current stream, median of a few repeats
+after a warm-up), so the choice reflects that workload's tree depths, item
+shapes and contact density.
+
+None of the knobs changes the result beyond the parity tolerances:
+``block``, ``grid``, ``batch_items``, ``seed_chunk`` and the flat tiles only
+change how work is laid out; ``omega`` damps the Newton step (the search
+direction of the lower bound, hence only how much is pruned) and
+``certify`` chooses between two exact ways of settling near pairs.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+HIER_SPACE: Dict[str, Sequence] = {
+    "batch_items": (32, 64, 128),
+    "grid": (1024, 2048, 4096),
+    "block": (256, 128),
+    "seed_chunk": (16, 8),
+    "omega": (1.0, 0.7, 0.5),
+    "certify": (0, 1),
+}
+
+FLAT_SPACE: Dict[str, Sequence] = {
+    "flat_tile_i": (256, 128),
+    "grid": (2048, 1024, 4096),
+    "omega": (1.0, 0.5),
+}
+
+
+def coordinate_descent(measure: Callable[[Dict], float], start: Dict, space: Dict[str, Sequence],
+                       sweeps: int = 1) -> Tuple[Dict, List[Tuple[Dict, float]]]:
+    """Minimise measure(params) one knob at a time; returns (best, log)."""
+    best = dict(start)
+    best_t = measure(best)
+    log = [(dict(best), best_t)]
+    seen = {tuple(sorted(best.items()))}
+    for _ in range(sweeps):
+        for knob, values in space.items():
+            for v in values:
+                cand = dict(best)
+                cand[knob] = v
+                key = tuple(sorted(cand.items()))
+                if key in seen:
+                    continue
+                seen.add(key)
+                t = measure(cand)
+                log.append((dict(cand), t))
+                if t < best_t:
+                    best, best_t = cand, t
+    return best, log
+
+
+def time_step(step: Callable[[], None], reps: int = 5, warmup: int = 1) -> float:
+    """Median milliseconds of step() on the current stream (HIP events)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequence]] = None,
+                reps: int = 5, cache: Optional[str] = None) -> Tuple[Dict, List[Tuple[Dict, float]]]:
+    """Tune engine.p in place for ``step`` (which must call engine.forward()).
+
+    The chosen values are applied to engine.p and returned; ``cache`` (a
+    JSON path) stores them keyed by a signature of the scene and mode, and a
+    later call with the same signature reuses them without timing.
+    """
+    from . import _abi
+    p = engine.p
+    if space is None:
+        space = HIER_SPACE if p.mode == _abi.DEM_MODE_HIER else FLAT_SPACE
+    ds = engine.ds
+    sig = f"{ds.n_tris}:{ds.n_verts}:{ds.n_pairs}:{ds.precision}:{p.mode}:{p.n_iter}"
+    if cache and os.path.exists(cache):
+        try:
+            stored = json.load(open(cache)).get(sig)
+        except (OSError, ValueError):
+            stored = None
+        if stored:
+            for k, v in stored.items():
+                setattr(p, k, v)
+            return stored, []
+    start = {k: getattr(p, k) for k in space}
+
+    def measure(cand: Dict) -> float:
+        for k, v in cand.items():
+            setattr(p, k, v)
+        t = time_step(step, reps=reps)
+        status = engine.check()
+        if status:
+            return float("inf")  # e.g. a capacity overflow: never prefer it
+        return t
+
+    best, log = coordinate_descent(measure, start, space)
+    for k, v in best.items():
+        setattr(p, k, v)
+    if cache:
+        data = {}
+        if os.path.exists(cache):
+            try:
+                data = json.load(open(cache))
+            except (OSError, ValueError):
+                data = {}
+        data[sig] = {k: (float(v) if isinstance(v, float) else int(v)) for k, v in best.items()}
+        with open(cache, "w") as f:
+            json.dump(data, f, indent=1)
+    return best, log

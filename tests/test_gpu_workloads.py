@@ -1,0 +1,157 @@
+"""GPU parity at the full benchmark sizes, checked on sampled particle pairs.
+
+The GPU runs the whole scene in the launch configuration the benchmark
+times (hierarchical, defaults); the FP64 oracle settles a seeded sample of
+candidate particle pairs exactly, and the GPU's contacts for those pairs are
+compared with the same bars as tests/test_gpu_parity.py.  For the fwd+bwd
+workload the adjoint is evaluated (through the C ABI) on the contacts of the
+sampled pairs only and compared with the oracle's gradient of the same
+pairs' energy.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen as sg
+from paper_2105_12415_amd import api
+
+from test_gpu_parity import TOL, longest_edge, say
+
+pytestmark = pytest.mark.gpu
+
+_SCENES = {}
+
+
+def _scene(name):
+    if name not in _SCENES:
+        s = sg.config3() if name == "lattice" else sg.config4()
+        ds = api.DeviceScene(s, device="cuda:0")
+        _SCENES[name] = (s, ds)
+    return _SCENES[name]
+
+
+def _sample(scene, n, seed, big_small_first=False):
+    rng = np.random.default_rng(seed)
+    P = np.asarray(scene.pairs)
+    idx = np.sort(rng.choice(len(P), n, replace=False))
+    return idx
+
+
+def _check_pairs(scene, ds, res, fs, idx, tol, extra=0.0):
+    """GPU contacts restricted to candidate pairs idx vs the oracle on them.
+    GPU triangle ids count all levels; fine_begin_host maps them to the
+    particle-local fine ids the oracle uses."""
+    P = np.asarray(scene.pairs)
+    ref = oracle.find_contacts(fs, pairs=P[idx])
+    sel = {(int(P[k, 0]), int(P[k, 1])) for k in idx}
+    lti = res["ti"] - ds.fine_begin_host[res["pi"]]
+    ltj = res["tj"] - ds.fine_begin_host[res["pj"]]
+    g = {}
+    for k in range(len(res["d"])):
+        key = (int(res["pi"][k]), int(res["pj"][k]))
+        if key in sel:
+            g[key + (int(lti[k]), int(ltj[k]))] = k
+    o = {(int(P[idx[p], 0]), int(P[idx[p], 1]), int(a), int(b)): k
+         for k, (p, a, b) in enumerate(zip(ref["pair"], ref["ti"], ref["tj"]))}
+    band = tol["band"] + 2 * extra
+    for key in set(o) - set(g):
+        assert abs(ref["d"][o[key]] - 0.1) <= band, ("missed", key, ref["d"][o[key]])
+    for key in set(g) - set(o):
+        A = fs.verts[fs.tris[fs.tri_begin[key[0]] + key[2]]]
+        B = fs.verts[fs.tris[fs.tri_begin[key[1]] + key[3]]]
+        assert abs(oracle.tri_tri(A, B)["d"] - 0.1) <= band, ("spurious", key)
+    common = sorted(set(g) & set(o))
+    for key in common:
+        dg, dr = res["d"][g[key]], ref["d"][o[key]]
+        A = fs.verts[fs.tris[fs.tri_begin[key[0]] + key[2]]]
+        B = fs.verts[fs.tris[fs.tri_begin[key[1]] + key[3]]]
+        assert abs(dg - dr) <= tol["r"] * dr + tol["a"] * longest_edge(A, B) + 2 * extra, key
+    return len(common), ref
+
+
+@pytest.mark.parametrize("name,n_sample", [("lattice", 24), ("big_small", 6)])
+def test_full_scene_sampled_pairs(name, n_sample):
+    scene, ds = _scene(name)
+    ds.set_pose(None)
+    eng = api.ContactEngine(ds, api.make_params("hier"), contact_capacity=1 << 23)
+    assert eng.run() == 0
+    res = eng.result()
+    say(f"[gpu-test] {name}: {len(res['d'])} contacts, stats {eng.stats_dict()['evals'][:9].tolist()}")
+    fs = oracle.fine_scene(scene)
+    idx = _sample(scene, n_sample, 7)
+    if name == "big_small":
+        # make sure both kinds of pairs (big-small, small-small) are sampled
+        P = np.asarray(scene.pairs)
+        ss = np.nonzero(P[:, 0] != 0)[0]
+        idx = np.unique(np.concatenate([idx[P[idx, 0] == 0][:4], ss[:2]]))
+    n, _ = _check_pairs(scene, ds, res, fs, idx, TOL["f32"])
+    assert n > 50
+
+
+def _grad_restricted(eng, ds, res_sel, k):
+    """dem_contact_backward on a contact list holding only res_sel's rows."""
+    n = len(res_sel)
+    cb = api.ContactBuffers.alloc(max(n, 1), ds.dtype, ds.device)
+    c = eng.contacts
+    idx = torch.as_tensor(res_sel, dtype=torch.int64, device=ds.device)
+    for name in ("pi", "pj", "ti", "tj", "d"):
+        getattr(cb, name)[:n] = getattr(c, name)[idx]
+    cb.count.fill_(n)
+    keep = eng.contacts
+    eng.contacts = cb
+    grad = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device=ds.device)
+    eng.backward(grad, energy=True)
+    torch.cuda.synchronize()
+    eng.contacts = keep
+    return grad.double().cpu().numpy().T, float(eng.energy_bwd.item())
+
+
+@pytest.mark.parametrize("step", [0, 9])
+def test_fwd_bwd_steps_sampled_gradient(step):
+    """Lattice fwd+bwd with the benchmark's per-step rigid perturbation
+    applied in the flatten kernel.  Step 0 is the identity; at step 9 the
+    oracle sees the exact FP64 rigid images, so the bar adds the FP32
+    rounding of the transform (8 ulp of the largest coordinate)."""
+    scene, ds = _scene("lattice")
+    P = ds.n_particles
+    Rs, ts = sg.rigid_perturbations(P, 10)
+    centres = np.array([p.centre for p in scene.particles])
+    shift = centres + ts[step] - np.einsum("pij,pj->pi", Rs[step], centres)
+    pose = np.concatenate([Rs[step].reshape(P, 9), shift], 1)
+    ds.set_pose(torch.as_tensor(pose, dtype=ds.dtype, device="cuda:0").contiguous())
+    eng = api.ContactEngine(ds, api.make_params("hier"), contact_capacity=1 << 23)
+    assert eng.run() == 0
+    res = eng.result()
+    moved = [(scene.world(p) - centres[p]) @ Rs[step][p].T + centres[p] + ts[step][p] for p in range(P)]
+    fs = oracle.fine_scene(scene, verts_override=moved)
+    cmax = max(np.abs(m).max() for m in moved)
+    extra = 0.0 if step == 0 else 8 * 2.0 ** -24 * cmax
+    idx = _sample(scene, 12, 11)
+    n, ref = _check_pairs(scene, ds, res, fs, idx, TOL["f32"], extra)
+    assert n > 50
+    # gradient of the sampled pairs' energy, adjoint through the C ABI
+    Pp = np.asarray(scene.pairs)
+    sel_pairs = {(int(Pp[k, 0]), int(Pp[k, 1])) for k in idx}
+    rows = [k for k in range(len(res["d"])) if (int(res["pi"][k]), int(res["pj"][k])) in sel_pairs]
+    g, E = _grad_restricted(eng, ds, rows, 1e4)
+    oracle.set_ambiguity_tol(1e-5)
+    ref = oracle.find_contacts(fs, pairs=Pp[idx])
+    E_ref, g_ref = oracle.energy_grad(fs, ref, 1e4, pairs=Pp[idx])
+    assert abs(E - E_ref) <= (1e-5 + (0 if step == 0 else 2e-4)) * E_ref
+    # intersecting pairs (d = 0) carry no gradient on either side; exclude
+    # non-unique closest points, the threshold band and tiny positive d
+    bad = (ref["ambiguous"] | (np.abs(ref["d"] - 0.1) <= TOL["f32"]["band"] + 2 * extra)
+           | ((ref["d"] > 0) & (ref["d"] < 1e-6)))
+    vi = fs.tris[fs.tri_begin[Pp[idx][ref["pair"], 0]] + ref["ti"]]
+    vj = fs.tris[fs.tri_begin[Pp[idx][ref["pair"], 1]] + ref["tj"]]
+    skip = np.unique(np.concatenate([vi[bad].ravel(), vj[bad].ravel()]))
+    touched = np.unique(np.concatenate([vi.ravel(), vj.ravel()]))
+    keep = np.setdiff1d(touched, skip)
+    gmax = np.abs(g_ref).max()
+    err = np.abs(g[keep] - g_ref[keep]).max() / gmax
+    # FP32 bar 1e-4 of the largest gradient; at step 9 the transform rounding
+    # (~1e-6 of the coordinates) perturbs closest points too
+    assert err <= (1e-4 if step == 0 else 1e-3), err
+    assert len(keep) > 0.6 * len(touched), (len(keep), len(touched), int(bad.sum()), len(bad))
+    ds.set_pose(None)
