@@ -1,11 +1,12 @@
 #!/usr/bin/env python3
 """Benchmark of the multiresolution contact-detection path on one MI355X.
 
-Default workload (``--config 5``): the 1000-sphere lattice (subdivision 3-5,
-radii log-uniform in [0.5, 2], gaps U(0, 0.1); FP32), forward + backward of
-the penalty contact energy k * sum max(0, delta - d)^2, k = 1e4, with a
-seeded rigid perturbation of every particle per step; K steps are captured
-in one HIP graph and replayed.  Configs 1-4 (forward only) are selectable.
+Default workload (``--workload lattice_fwd_bwd``): the 1000-sphere lattice
+(subdivision 3-5, radii log-uniform in [0.5, 2], gaps U(0, 0.1); FP32),
+forward + backward of the penalty contact energy k * sum max(0, delta - d)^2,
+k = 1e4, with a seeded rigid perturbation of every particle per step; K
+steps are captured in one HIP graph and replayed.  Forward-only workloads:
+two_spheres_s3_f64, two_spheres_s5, lattice, big_small.
 
 One JSON line is printed: tri-pair evaluations per second of the
 hierarchical step (``value``), its ms per step, the plain all-pairs (flat)
@@ -51,19 +52,26 @@ FLATTEN_BYTES_PER_TRI = 12 + 16 + 64  # indices, per-triangle static data, soup 
 FLATTEN_BYTES_PER_VERT = 12
 
 
-def workload(cfg: int):
+WORKLOADS = {
+    "two_spheres_s3_f64": ("two bumped unit spheres, subdivision 3 (1280 tris each), FP64, single level", False),
+    "two_spheres_s5": ("two bumped unit spheres, subdivision 5 (20480 tris each), levels s=3/4/5, FP32", False),
+    "lattice": ("1000 bumped spheres on a 10x10x10 lattice, subdivision 3-5, radii logU[0.5,2], "
+                "gaps U(0,0.1), full icosphere cascades, FP32", False),
+    "lattice_fwd_bwd": ("1000 bumped spheres on a 10x10x10 lattice, subdivision 3-5, radii logU[0.5,2], "
+                        "gaps U(0,0.1), full icosphere cascades, FP32", True),
+    "big_small": ("bumped sphere R=20 subdivision 7 (327680 tris) + 2000 R=0.5 subdivision-3 spheres "
+                  "on its surface, FP32", False),
+}
+
+
+def workload(name: str):
     import scenegen as sg
-    if cfg == 1:
-        return sg.config1(), "two bumped unit spheres, subdivision 3 (1280 tris each), FP64, single level"
-    if cfg == 2:
-        return sg.config2(), "two bumped unit spheres, subdivision 5 (20480 tris each), levels s=3/4/5, FP32"
-    if cfg in (3, 5):
-        return sg.config3(), ("1000 bumped spheres on a 10x10x10 lattice, subdivision 3-5, radii logU[0.5,2], "
-                              "gaps U(0,0.1), full icosphere cascades, FP32")
-    if cfg == 4:
-        return sg.config4(), ("bumped sphere R=20 subdivision 7 (327680 tris) + 2000 R=0.5 subdivision-3 spheres "
-                              "on its surface, FP32")
-    raise SystemExit(f"unknown config {cfg}")
+    if name not in WORKLOADS:
+        raise SystemExit(f"unknown workload {name}; one of {sorted(WORKLOADS)}")
+    make = {"two_spheres_s3_f64": sg.two_spheres_s3_f64, "two_spheres_s5": sg.two_spheres_s5_hier, "lattice": sg.lattice1000,
+            "lattice_fwd_bwd": sg.lattice1000, "big_small": sg.big_plus_small}[name]
+    desc, backward = WORKLOADS[name]
+    return make(), desc, backward
 
 
 class Step:
@@ -228,7 +236,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--workload", default="lattice_fwd_bwd", choices=sorted(WORKLOADS))
     ap.add_argument("--flat-steps", type=int, default=1)
     ap.add_argument("--no-flat", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -262,12 +270,11 @@ def main():
         k, v = kv.split("=")
         params_kw[k] = float(v) if "." in v or "e" in v else int(v)
 
-    scene, desc = workload(args.config)
-    backward = args.config == 5
+    scene, desc, backward = workload(args.workload)
     ds = api.DeviceScene(scene, device="cuda:0")
     K = args.steps
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    log(f"[bench] config {args.config}: {desc}; {ds.n_particles} particles, {ds.n_tris} triangles, "
+    log(f"[bench] {args.workload}: {desc}; {ds.n_particles} particles, {ds.n_tris} triangles, "
         f"{ds.n_pairs} candidate pairs, {ds.n_fine_pairs()} fine pairs")
 
     eng, step, ms, ms_wall, kt, bwd_ms, st = run_mode(torch, api, ds, "hier", backward, K, args.warmup,
@@ -300,7 +307,7 @@ def main():
            "steps": K, "warmup": args.warmup, "ms_per_step": ms, "ms_per_step_wall": ms_wall,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
            "data": "synthetic",
-           "config": {"workload": f"config {args.config}: {desc}" + ("; forward + backward (k=1e4), "
+           "config": {"workload": f"{args.workload}: {desc}" + ("; forward + backward (k=1e4), "
                       f"per-step rigid perturbation, {K} steps captured in one HIP graph" if backward else
                       f"; forward contacts, {K} steps captured in one HIP graph"),
                       "particles": ds.n_particles, "triangles_all_levels": ds.n_tris,

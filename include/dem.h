@@ -181,11 +181,11 @@ typedef struct {
                              fallback; 0: every near pair takes the exact fallback */
   double energy_k;        /* k of E = k sum max(0, delta - d)^2 (used when dev_energy != NULL) */
   int32_t block;          /* threads per block of the descent / near kernels: 64, 128 or 256 */
-  int32_t grid;           /* blocks of the persistent kernels (0 = 8 per compute unit) */
-  int32_t batch_items;    /* work items a block claims at once (1..block) */
+  int32_t grid;           /* blocks of the persistent kernels (0 = 2048; default 1024) */
+  int32_t batch_items;    /* work items a block claims at once (1..block; default 128) */
   int32_t flat_tile_i;    /* flat mode: i-triangles per tile (multiple of 64, <= 1024) */
   int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..256) */
-  int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges */
+  int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges (1..16; default 8) */
   int64_t queue_capacity; /* items per level queue (>= 8; split into 8 equal segments, one
                              filled per XCD, so allow for uneven fills) */
   int64_t near_capacity;  /* fine pairs the lower bound could not prune (8 segments likewise) */

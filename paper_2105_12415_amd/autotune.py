@@ -20,7 +20,7 @@ import os
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 HIER_SPACE: Dict[str, Sequence] = {
-    "batch_items": (32, 64, 128),
+    "batch_items": (128, 64, 32),
     "grid": (1024, 2048, 4096),
     "block": (256, 128),
     "seed_chunk": (16, 8),
@@ -103,7 +103,10 @@ def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequ
     def measure(cand: Dict) -> float:
         for k, v in cand.items():
             setattr(p, k, v)
-        t = time_step(step, reps=reps)
+        try:
+            t = time_step(step, reps=reps)
+        except _abi.DemError:
+            return float("inf")  # an invalid combination (e.g. batch > block)
         status = engine.check()
         if status:
             return float("inf")  # e.g. a capacity overflow: never prefer it

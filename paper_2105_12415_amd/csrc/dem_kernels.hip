@@ -829,7 +829,7 @@ bool params_ok(const dem_params& p) {
   if (p.n_iter < 0 || p.n_iter > 8) return false;
   if (!(p.omega > 0.0f) || !(p.alpha_reg_rel >= 0.0f) || !(p.alpha_it_ratio > 0.0f)) return false;
   if (p.block != 64 && p.block != 128 && p.block != 256) return false;
-  if (p.batch_items < 1 || p.batch_items > p.block) return false;
+  if (p.batch_items < 1 || p.batch_items > p.block) return false;  // one item per thread
   if (p.flat_tile_i < 64 || p.flat_tile_i > 1024 || p.flat_tile_i % 64) return false;
   if (p.flat_tile_j < 1 || p.flat_tile_j > 64) return false;
   if (p.seed_chunk < 1 || p.seed_chunk > 16) return false;
@@ -985,11 +985,11 @@ void dem_default_params(dem_params* p) {
   p->certify = 0;
   p->energy_k = 1e4;
   p->block = 256;
-  p->grid = 0;
-  p->batch_items = 64;
+  p->grid = 1024;
+  p->batch_items = 128;
   p->flat_tile_i = 256;
   p->flat_tile_j = 64;
-  p->seed_chunk = 16;
+  p->seed_chunk = 8;
   p->queue_capacity = 1 << 22;
   p->near_capacity = 1 << 22;
 }

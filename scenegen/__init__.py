@@ -170,8 +170,8 @@ class Scene:
         return int(np.sum(F[self.pairs[:, 0]] * F[self.pairs[:, 1]]))
 
 
-def _streams(config_id: int, n: int):
-    ss = np.random.SeedSequence(SEED, spawn_key=(config_id,))
+def _streams(stream_id: int, n: int):
+    ss = np.random.SeedSequence(SEED, spawn_key=(stream_id,))
     return [np.random.default_rng(c) for c in ss.spawn(n)]
 
 
@@ -219,21 +219,21 @@ def _pair_margin(bump=BUMP, eps0=EPS0) -> float:
 
 # --------------------------------------------------------------------------- workloads
 def two_spheres(s_fine: int, levels: Optional[Sequence[int]] = None, dtype: str = "f64",
-                sep: float = 2.02, config_id: int = 1, name: str = "two_spheres") -> Scene:
+                sep: float = 2.02, stream_id: int = 1, name: str = "two_spheres") -> Scene:
     """Two bumped unit spheres with centres ``sep`` apart along x."""
-    rngs = _streams(config_id, 2)
+    rngs = _streams(stream_id, 2)
     ps = [bumped_sphere(rngs[0], s_fine, 1.0, levels, centre=(0.0, 0.0, 0.0)),
           bumped_sphere(rngs[1], s_fine, 1.0, levels, centre=(sep, 0.0, 0.0))]
     return Scene(name, ps, np.array([[0, 1]], np.int32), dtype,
                  info={"s": s_fine, "levels": list(levels or [s_fine]), "sep": sep})
 
 
-def config1() -> Scene:
+def two_spheres_s3_f64() -> Scene:
     """Two s=3 bumped unit spheres (1280 tris each), FP64, flat all-pairs."""
     return two_spheres(3, None, "f64", 2.02, 1, "two_spheres_s3_f64_flat")
 
 
-def config2() -> Scene:
+def two_spheres_s5_hier() -> Scene:
     """Two s=5 bumped unit spheres (20480 tris each), FP32, levels s=3/4/5."""
     return two_spheres(5, [3, 4, 5], "f32", 2.02, 2, "two_spheres_s5_f32_hier345")
 
@@ -294,14 +294,14 @@ def _drop_lattice(R: np.ndarray, rng: np.random.Generator, n: int):
     return c
 
 
-def lattice_scene(n: int = 10, config_id: int = 3, s_choices=(3, 4, 5),
+def lattice_scene(n: int = 10, stream_id: int = 3, s_choices=(3, 4, 5),
                   r_range=(0.5, 2.0), name: str = "lattice") -> Scene:
     """n^3 bumped spheres: s ~ U(s_choices), R ~ logU(r_range), lattice gaps U(0,0.1).
 
     Every particle keeps the whole icosphere cascade s = 0..s_p as its hierarchy.
     """
     N = n ** 3
-    rngs = _streams(config_id, N + 1)
+    rngs = _streams(stream_id, N + 1)
     g_rng = rngs[N]
     s = g_rng.choice(np.asarray(s_choices), size=N)
     R = np.exp(g_rng.uniform(np.log(r_range[0]), np.log(r_range[1]), size=N))
@@ -317,7 +317,7 @@ def lattice_scene(n: int = 10, config_id: int = 3, s_choices=(3, 4, 5),
                        "subdiv_hist": np.bincount(s, minlength=6).tolist()})
 
 
-def config3() -> Scene:
+def lattice1000() -> Scene:
     """1000 bumped spheres on a 10^3 lattice, s in {3,4,5}, R logU[0.5,2], FP32."""
     return lattice_scene(10, 3, name="lattice1000_s345_f32")
 
@@ -342,9 +342,9 @@ def _cone_descend(dirs_big: np.ndarray, faces: List[np.ndarray], u: np.ndarray) 
 
 def size_disparate_scene(s_big: int = 7, R_big: float = 20.0, n_small: int = 2000,
                          s_small: int = 3, R_small: float = 0.5, gap=(-0.01, 0.05),
-                         config_id: int = 4, name: str = "big_plus_small") -> Scene:
+                         stream_id: int = 4, name: str = "big_plus_small") -> Scene:
     """One big bumped sphere plus ``n_small`` small ones resting on its surface."""
-    rngs = _streams(config_id, n_small + 2)
+    rngs = _streams(stream_id, n_small + 2)
     big = bumped_sphere(rngs[0], s_big, R_big, list(range(s_big + 1)), centre=(0, 0, 0))
     g_rng = rngs[1]
     k = np.arange(n_small) + 0.5
@@ -376,20 +376,20 @@ def size_disparate_scene(s_big: int = 7, R_big: float = 20.0, n_small: int = 200
                  info={"n_big_small": n_big_small, "n_small_small": int(len(pairs) - n_big_small)})
 
 
-def config4() -> Scene:
+def big_plus_small() -> Scene:
     """R=20 s=7 sphere (327680 tris) + 2000 R=0.5 s=3 spheres on it, FP32."""
     return size_disparate_scene(name="big_s7_plus_2000_small_s3_f32")
 
 
 # --------------------------------------------------------------------------- motion
-def rigid_perturbations(n_particles: int, n_steps: int, config_id: int = 5,
+def rigid_perturbations(n_particles: int, n_steps: int, stream_id: int = 5,
                         max_shift: float = 2e-3, max_angle: float = 2e-3):
     """Seeded per-step, per-particle small rigid motions (axis-angle, shift).
 
     Returns (rotations (n_steps, P, 3, 3), shifts (n_steps, P, 3)) about each
     particle's centre.  Step 0 is the identity.
     """
-    rng = _streams(config_id, 1)[0]
+    rng = _streams(stream_id, 1)[0]
     Rs = np.zeros((n_steps, n_particles, 3, 3))
     ts = np.zeros((n_steps, n_particles, 3))
     for st in range(n_steps):
@@ -421,7 +421,7 @@ def random_triangle_pairs(n: int, seed: int = 7, scale: float = 1.0, spread: flo
 
 
 __all__ = [
-    "Particle", "Scene", "icosphere", "bumped_sphere", "two_spheres", "config1", "config2",
-    "config3", "config4", "lattice_scene", "size_disparate_scene", "candidate_pairs",
+    "Particle", "Scene", "icosphere", "bumped_sphere", "two_spheres", "two_spheres_s3_f64", "two_spheres_s5_hier",
+    "lattice1000", "big_plus_small", "lattice_scene", "size_disparate_scene", "candidate_pairs",
     "rigid_perturbations", "random_rotation", "random_triangle_pairs", "EPS0", "BUMP", "SEED",
 ]

@@ -95,7 +95,7 @@ def _levels(p):
 
 
 def test_hierarchy_matches_oracle_eps():
-    s = sg.two_spheres(4, [0, 1, 2, 3, 4], "f32", config_id=31, name="h")
+    s = sg.two_spheres(4, [0, 1, 2, 3, 4], "f32", stream_id=31, name="h")
     t = oracle.tree(s)
     n0 = 0
     for k, p in enumerate(s.particles):
@@ -117,7 +117,7 @@ def test_hierarchy_matches_oracle_eps():
 
 
 def test_hierarchy_rejects_malformed():
-    p = sg.two_spheres(2, [1, 2], "f64", config_id=32).particles[0]
+    p = sg.two_spheres(2, [1, 2], "f64", stream_id=32).particles[0]
     tris, parent, sizes = _levels(p)
     w = p.world()
     bad = parent.copy()

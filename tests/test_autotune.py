@@ -24,7 +24,7 @@ def test_coordinate_descent_never_prefers_failures():
 def test_tuned_parameters_keep_the_contacts():
     import scenegen as sg
     from paper_2105_12415_amd import api
-    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=51, name="tune")
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, stream_id=51, name="tune")
     ds = api.DeviceScene(scene, device="cuda:0")
     ref = api.ContactEngine(ds, api.make_params("hier"))
     assert ref.run() == 0

@@ -93,7 +93,7 @@ def compare_sets(scene, ds, res, ref, tol, fs=None):
 # ------------------------------------------------------------------ distances
 def test_dense_fp64_all_distances_two_spheres_s3():
     """1,638,400 exact FP64 distances (flat, threshold +inf) vs the oracle."""
-    scene = sg.config1()
+    scene = sg.two_spheres_s3_f64()
     ds, eng, res = run(scene, "flat", dense_distance=1)
     F = len(scene.particles[0].fine)
     assert len(res["d"]) == F * F
@@ -114,7 +114,7 @@ def test_dense_fp64_all_distances_two_spheres_s3():
 
 @pytest.mark.parametrize("mode", ["flat", "hier"])
 def test_contacts_fp64_two_spheres_s3(mode):
-    scene = sg.config1()
+    scene = sg.two_spheres_s3_f64()
     ds, eng, res = run(scene, mode)
     ref = oracle.find_contacts(oracle.fine_scene(scene))
     n, og, orf = compare_sets(scene, ds, res, ref, TOL["f64"])
@@ -125,7 +125,7 @@ def test_contacts_fp64_two_spheres_s3(mode):
 
 @pytest.mark.parametrize("mode", ["flat", "hier"])
 def test_contacts_fp32_two_spheres_s4_levels(mode):
-    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=41, name="s4")
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, stream_id=41, name="s4")
     ds, eng, res = run(scene, mode)
     ref = oracle.find_contacts(oracle.fine_scene(scene))
     n, og, orf = compare_sets(scene, ds, res, ref, TOL["f32"])
@@ -140,7 +140,7 @@ def test_contacts_fp32_two_spheres_s4_levels(mode):
 
 def test_hier_equals_flat_and_oracle_config2():
     """Two s=5 spheres (20480 tris each), levels s=3/4/5, FP32: Lemma 1."""
-    scene = sg.config2()
+    scene = sg.two_spheres_s5_hier()
     ds, eng, res_h = run(scene, "hier")
     _, eng_f, res_f = run(scene, "flat")
     ref = oracle.find_contacts(oracle.fine_scene(scene))
@@ -157,7 +157,7 @@ def test_hier_equals_flat_and_oracle_config2():
 
 def test_lattice_mixed_depths():
     """27 spheres with s in {2,3} and radii 0.5-2: uneven depths per pair."""
-    scene = sg.lattice_scene(3, config_id=42, s_choices=(2, 3))
+    scene = sg.lattice_scene(3, stream_id=42, s_choices=(2, 3))
     ds, eng, res = run(scene, "hier")
     ref = oracle.find_contacts(oracle.fine_scene(scene))
     n, og, orf = compare_sets(scene, ds, res, ref, TOL["f32"])
@@ -196,16 +196,16 @@ def _grad_compare(scene, prec):
 
 
 def test_gradient_fp64():
-    _grad_compare(sg.two_spheres(3, [1, 2, 3], "f64", sep=2.03, config_id=43, name="g64"), "f64")
+    _grad_compare(sg.two_spheres(3, [1, 2, 3], "f64", sep=2.03, stream_id=43, name="g64"), "f64")
 
 
 def test_gradient_fp32():
-    _grad_compare(sg.two_spheres(4, [2, 3, 4], "f32", sep=2.03, config_id=44, name="g32"), "f32")
+    _grad_compare(sg.two_spheres(4, [2, 3, 4], "f32", sep=2.03, stream_id=44, name="g32"), "f32")
 
 
 # ------------------------------------------------------------------ failure handling
 def test_contact_overflow_reports_needed_count():
-    scene = sg.two_spheres(3, [1, 2, 3], "f32", sep=2.03, config_id=45, name="ovf")
+    scene = sg.two_spheres(3, [1, 2, 3], "f32", sep=2.03, stream_id=45, name="ovf")
     ds = api.DeviceScene(scene, device="cuda:0")
     eng = api.ContactEngine(ds, api.make_params("hier"), contact_capacity=7)
     eng.forward()
@@ -219,7 +219,7 @@ def test_contact_overflow_reports_needed_count():
 def test_zero_iterations_same_contacts():
     """N_it = 0 leaves only the centroid/vertex bound: more fallback work,
     same contact set."""
-    scene = sg.two_spheres(3, [1, 2, 3], "f32", sep=2.03, config_id=46, name="nit0")
+    scene = sg.two_spheres(3, [1, 2, 3], "f32", sep=2.03, stream_id=46, name="nit0")
     ds, e4, r4 = run(scene, "hier")
     _, e0, r0 = run(scene, "hier", n_iter=0)
     assert set(keyed(ds, r4)) == set(keyed(ds, r0))
@@ -228,7 +228,7 @@ def test_zero_iterations_same_contacts():
 
 # ------------------------------------------------------------------ graphs
 def test_graph_replay_matches_eager():
-    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=47, name="graph")
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, stream_id=47, name="graph")
     ds = api.DeviceScene(scene, device="cuda:0")
     eng = api.ContactEngine(ds, api.make_params("hier"), energy_k=1e4)
     eng.run()
@@ -268,7 +268,7 @@ def _rot90z():
 def test_pose_exact_rotation_matches_oracle():
     """A 90-degree rotation applied in the flatten kernel is exact in FP32:
     contacts must match the oracle on the rotated coordinates."""
-    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=48, name="pose90")
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, stream_id=48, name="pose90")
     ds = api.DeviceScene(scene, device="cuda:0")
     R = _rot90z()
     pose = np.concatenate([np.tile(R.reshape(1, 9), (ds.n_particles, 1)), np.zeros((ds.n_particles, 3))], 1)
@@ -288,10 +288,10 @@ def test_pose_small_rigid_motion_within_rounding():
     the flatten kernel, against the oracle on the exact FP64 rigid images;
     the bar adds the FP32 rounding of the transform (8 ulp of the largest
     coordinate) to the distance tolerance and the threshold band."""
-    scene = sg.lattice_scene(3, config_id=49, s_choices=(2, 3))
+    scene = sg.lattice_scene(3, stream_id=49, s_choices=(2, 3))
     ds = api.DeviceScene(scene, device="cuda:0")
     P = ds.n_particles
-    Rs, ts = sg.rigid_perturbations(P, 4, config_id=49)
+    Rs, ts = sg.rigid_perturbations(P, 4, stream_id=49)
     k = 3
     centres = np.array([p.centre for p in scene.particles])
     shift = centres + ts[k] - np.einsum("pij,pj->pi", Rs[k], centres)
@@ -327,7 +327,7 @@ def test_certified_hybrid_matches_exact_fallback():
     """certify=1 (iterate + snap + certificate, fallback for the rest) and
     certify=0 (exact distance for every near pair) give the same contacts,
     and both meet the oracle bar."""
-    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=50, name="cert")
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, stream_id=50, name="cert")
     ds, e1, r1 = run(scene, "hier", certify=1)
     _, e0, r0 = run(scene, "hier", certify=0)
     st = e1.stats_dict()

@@ -25,7 +25,7 @@ _SCENES = {}
 
 def _scene(name):
     if name not in _SCENES:
-        s = sg.config3() if name == "lattice" else sg.config4()
+        s = sg.lattice1000() if name == "lattice" else sg.big_plus_small()
         ds = api.DeviceScene(s, device="cuda:0")
         _SCENES[name] = (s, ds)
     return _SCENES[name]

@@ -8,13 +8,13 @@ import scenegen as sg
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    s = sg.config1()
+def two_spheres_s3():
+    s = sg.two_spheres_s3_f64()
     return s, oracle.fine_scene(s)
 
 
-def test_prereject_never_changes_the_set(cfg1):
-    _, fs = cfg1
+def test_prereject_never_changes_the_set(two_spheres_s3):
+    _, fs = two_spheres_s3
     a = oracle.find_contacts(fs, prereject=True)
     b = oracle.find_contacts(fs, prereject=False)
     assert a["tested"] < b["tested"]
@@ -24,10 +24,10 @@ def test_prereject_never_changes_the_set(cfg1):
     assert np.all(a["d"] <= 0.1) and len(a["d"]) > 100
 
 
-def test_dense_distances_certified(cfg1):
+def test_dense_distances_certified(two_spheres_s3):
     """All 1.64M distances of the two-sphere s=3 scene pass the separation
     certificate (or are intersections with coincident points)."""
-    s, fs = cfg1
+    s, fs = two_spheres_s3
     r = oracle.find_contacts(fs, delta=np.inf, prereject=False)
     F = len(s.particles[0].fine)
     assert len(r["d"]) == F * F
@@ -46,7 +46,7 @@ def test_dense_distances_certified(cfg1):
 
 
 def _tree_scene():
-    return sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, config_id=11, name="t")
+    return sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, stream_id=11, name="t")
 
 
 def test_surrogate_eps_against_sampling():
@@ -86,7 +86,7 @@ def test_surrogate_eps_against_sampling():
 def test_lemma1_exact_descent_equals_flat():
     """Lemma 1: with conservative surrogates the descent finds exactly the
     flat contact set (two spheres and a small lattice with mixed depths)."""
-    for s in (_tree_scene(), sg.lattice_scene(3, config_id=12, s_choices=(2, 3))):
+    for s in (_tree_scene(), sg.lattice_scene(3, stream_id=12, s_choices=(2, 3))):
         t = oracle.tree(s)
         dsc = oracle.descent(t)
         fs = oracle.fine_scene(s)
@@ -124,7 +124,7 @@ def _energy(fs, k, verts=None):
 
 
 def test_gradient_finite_differences():
-    s = sg.two_spheres(2, None, "f64", sep=2.04, config_id=13, name="fd")
+    s = sg.two_spheres(2, None, "f64", sep=2.04, stream_id=13, name="fd")
     fs = oracle.fine_scene(s)
     k = 1e4
     E, g, c = _energy(fs, k)
@@ -149,7 +149,7 @@ def test_gradient_finite_differences():
 
 
 def test_gradient_newton_third_law_and_torque():
-    s = sg.two_spheres(3, None, "f64", sep=2.03, config_id=14, name="n3")
+    s = sg.two_spheres(3, None, "f64", sep=2.03, stream_id=14, name="n3")
     fs = oracle.fine_scene(s)
     E, g, c = _energy(fs, 1e4)
     assert E > 0
