@@ -363,11 +363,12 @@ __device__ __forceinline__ uint32_t xcd_swizzle(uint32_t bid, uint32_t grid) {
 
 template <typename T, int N, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
-  // LDS sized to the block: one item per thread, stages of two rounds
+  // LDS sized to the block: one item per thread, stages of two rounds;
+  // under 20 KB at BLOCK = 256 so that eight blocks fit in a CU's 160 KB
   __shared__ int4 items[BLOCK];
   __shared__ int offs[BLOCK + 1];
   __shared__ int wsum[16];
-  __shared__ uint8_t owner_s[BLOCK * 16];
+  __shared__ uint8_t owner_s[BLOCK * 8];
   __shared__ LdsQueue<int4, 2 * BLOCK> qi;
   __shared__ LdsQueue<int2, 2 * BLOCK> qn;
   __shared__ SegView view;
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
     const int total = offs[n];
     // small batches (the usual 4x4 children products) map pair -> item
     // through an LDS table; large ones (root chunks) search the offsets
-    const bool mapped = total <= BLOCK * 16 && n <= 256;
+    const bool mapped = total <= BLOCK * 8 && n <= 256;
     if (mapped && (int)threadIdx.x < n) {
       const int o = offs[threadIdx.x];
       for (int q = 0; q < np; ++q) owner_s[o + q] = (uint8_t)threadIdx.x;
