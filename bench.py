@@ -195,8 +195,9 @@ def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capac
         space = None
         if mode == "flat":
             space = {"flat_tile_i": (256, 128), "omega": (1.0, 0.5)}
-        space = {k: v for k, v in (space or autotune.HIER_SPACE).items() if k not in params_kw}
-        best, log = autotune.tune_engine(eng, lambda: step(0), space=space, reps=1 if mode == "flat" else 5)
+        space = {k: v for k, v in (space or autotune.hier_space(ds.n_levels_max)).items()
+                 if k not in params_kw}
+        best, log = autotune.tune_engine(eng, lambda: step(0), space=space, reps=1 if mode == "flat" else 7)
         eng.tuned = {"chosen": best, "candidates": len(log)}
         step.pose(0)
         eng.run()

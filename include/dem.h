@@ -175,17 +175,23 @@ typedef struct {
   float alpha_it_ratio;   /* alpha_iterative / alpha_regulariser */
   int32_t init_centroid;  /* 0: start the iteration at (a,b) = 0 as the paper does; 1: at the centroids */
   int32_t dense_distance; /* 1: threshold = +inf, every fine pair is reported with its exact distance */
-  int32_t certify;        /* 1 (default): settle a near pair from its iterate snapped to the
-                             closest features when the separation bound certifies the distance
+  int32_t certify;        /* 1: settle a near pair from its iterate snapped to the closest
+                             features when the separation bound certifies the distance
                              (FP32: within 4e-6 d + 1e-7 size), else send it to the exact
-                             fallback; 0: every near pair takes the exact fallback */
+                             fallback; 0 (default): every near pair takes the exact fallback */
   double energy_k;        /* k of E = k sum max(0, delta - d)^2 (used when dev_energy != NULL) */
   int32_t block;          /* threads per block of the descent / near kernels: 64, 128 or 256 */
   int32_t grid;           /* blocks of the persistent kernels (0 = 2048; default 1024) */
   int32_t batch_items;    /* work items a block claims at once (1..block; default 128) */
   int32_t flat_tile_i;    /* flat mode: i-triangles per tile (multiple of 64, <= 1024) */
-  int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..256) */
+  int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..64) */
   int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges (1..16; default 8) */
+  /* Per-depth overrides of grid and batch_items for the descent launches
+   * (index = tree depth; 0 = use grid / batch_items).  Depths differ in item
+   * count and shape (few large root chunks at depth 0, millions of 4 x 4
+   * child products further down), so their best launch shapes differ. */
+  int32_t level_grid[DEM_MAX_LEVELS];
+  int32_t level_batch[DEM_MAX_LEVELS];
   int64_t queue_capacity; /* items per level queue (>= 8; split into 8 equal segments, one
                              filled per XCD, so allow for uneven fills) */
   int64_t near_capacity;  /* fine pairs the lower bound could not prune (8 segments likewise) */
@@ -201,7 +207,7 @@ typedef struct {
   int32_t n_events;
 } dem_params;
 
-/* Fill p with the defaults (N_it = 4, HIER mode, certify on). */
+/* Fill p with the defaults (N_it = 4, HIER mode, exact fallback, no per-depth overrides). */
 void dem_default_params(dem_params* p);
 
 /* ------------------------------------------------------------------ outputs */

@@ -8,10 +8,14 @@ after a warm-up), so the choice reflects that workload's tree depths, item
 shapes and contact density.
 
 None of the knobs changes the result beyond the parity tolerances:
-``block``, ``grid``, ``batch_items``, ``seed_chunk`` and the flat tiles only
-change how work is laid out; ``omega`` damps the Newton step (the search
-direction of the lower bound, hence only how much is pruned) and
-``certify`` chooses between two exact ways of settling near pairs.
+``block``, ``grid``, ``batch_items``, ``seed_chunk``, the per-depth
+``level_grid.d`` / ``level_batch.d`` and the flat tiles only change how work
+is laid out; ``omega`` damps the Newton step (the search direction of the
+lower bound, hence only how much is pruned) and ``certify`` chooses between
+two exact ways of settling near pairs.
+
+A knob named ``array.index`` addresses one element of an array field of
+dem_params (the per-depth launch shapes).
 """
 from __future__ import annotations
 
@@ -27,6 +31,34 @@ HIER_SPACE: Dict[str, Sequence] = {
     "omega": (1.0, 0.7, 0.5),
     "certify": (0, 1),
 }
+
+LEVEL_GRIDS = (512, 1024, 1536, 2048, 3072)
+LEVEL_BATCHES = (32, 64, 128, 256)
+
+
+def hier_space(n_levels: int) -> Dict[str, Sequence]:
+    """HIER_SPACE, then a grid and a batch size for each tree depth."""
+    space = dict(HIER_SPACE)
+    for d in range(n_levels):
+        space[f"level_grid.{d}"] = LEVEL_GRIDS
+        space[f"level_batch.{d}"] = LEVEL_BATCHES
+    return space
+
+
+def get_knob(p, name: str):
+    if "." in name:
+        field, idx = name.split(".")
+        return getattr(p, field)[int(idx)]
+    return getattr(p, name)
+
+
+def set_knob(p, name: str, value) -> None:
+    if "." in name:
+        field, idx = name.split(".")
+        getattr(p, field)[int(idx)] = value
+    else:
+        setattr(p, name, value)
+
 
 FLAT_SPACE: Dict[str, Sequence] = {
     "flat_tile_i": (256, 128),
@@ -85,9 +117,9 @@ def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequ
     """
     from . import _abi
     p = engine.p
-    if space is None:
-        space = HIER_SPACE if p.mode == _abi.DEM_MODE_HIER else FLAT_SPACE
     ds = engine.ds
+    if space is None:
+        space = hier_space(ds.n_levels_max) if p.mode == _abi.DEM_MODE_HIER else FLAT_SPACE
     sig = f"{ds.n_tris}:{ds.n_verts}:{ds.n_pairs}:{ds.precision}:{p.mode}:{p.n_iter}"
     if cache and os.path.exists(cache):
         try:
@@ -96,13 +128,13 @@ def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequ
             stored = None
         if stored:
             for k, v in stored.items():
-                setattr(p, k, v)
+                set_knob(p, k, v)
             return stored, []
-    start = {k: getattr(p, k) for k in space}
+    start = {k: get_knob(p, k) for k in space}
 
     def measure(cand: Dict) -> float:
         for k, v in cand.items():
-            setattr(p, k, v)
+            set_knob(p, k, v)
         try:
             t = time_step(step, reps=reps)
         except _abi.DemError:
@@ -114,7 +146,7 @@ def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequ
 
     best, log = coordinate_descent(measure, start, space)
     for k, v in best.items():
-        setattr(p, k, v)
+        set_knob(p, k, v)
     if cache:
         data = {}
         if os.path.exists(cache):

@@ -286,113 +286,173 @@ DEM_HD T point_tri(V3<T> x, V3<T> a, V3<T> e1, V3<T> e2, V3<T>& q, T w[3]) {
 // s of the closest points of the two lines (clamped), t optimal for that s
 // (clamped), then s re-optimised for a clamped t.  The line-line parameter
 // comes from triple products with the common normal d1 x d2, which stays
-// accurate in FP32 for nearly parallel segments.  Squared distance.
+// accurate in FP32 for nearly parallel segments.  The squared lengths of
+// the two directions and their reciprocals are passed in (they are shared by
+// the three edge pairs of each edge).  Returns the squared distance.
 template <typename T>
-DEM_HD T seg_seg(V3<T> p0, V3<T> d1, V3<T> q0, V3<T> d2, T& s, T& t, V3<T>& cp, V3<T>& cq) {
+DEM_HD T seg_seg_pre(V3<T> p0, V3<T> d1, T a, T ia, V3<T> q0, V3<T> d2, T e, T ie, T& s, T& t) {
   V3<T> r = p0 - q0;
-  T a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
-  T c = dot(d1, r), b = dot(d1, d2);
+  T f = dot(d2, r), c = dot(d1, r), b = dot(d1, d2);
   V3<T> n = cross(d1, d2);
   T nn = dot(n, n);
   bool skew = nn > T(64) * Eps<T>::u * Eps<T>::u * a * e && nn > T(0);
-  s = skew ? clamp01(dot(cross(-r, d2), n) / nn) : T(0);
-  T ie = e > T(0) ? T(1) / e : T(0);
-  T ia = a > T(0) ? T(1) / a : T(0);
+  T sl = clamp01(dot(cross(-r, d2), n) * rcp_fast(skew ? nn : T(1)));
+  s = skew ? sl : T(0);
   t = (b * s + f) * ie;
   T s_lo = clamp01(-c * ia);
   T s_hi = clamp01((b - c) * ia);
   bool lo = t < T(0), hi = t > T(1);
   s = lo ? s_lo : (hi ? s_hi : s);
   t = lo ? T(0) : (hi ? T(1) : t);
-  cp = fma3(s, d1, p0);
-  cq = fma3(t, d2, q0);
-  V3<T> dd = cp - cq;
+  V3<T> dd = fma3(s, d1, r) - t * d2;
   return dot(dd, dd);
 }
 
-// Does segment p0 -> p0 + d cross the plane of triangle (a, a+e1, a+e2)
-// inside the triangle?  Segments lying in the plane are left to the distance
-// tests.  On a hit x is the crossing point.
 template <typename T>
-DEM_HD bool seg_crosses(V3<T> p0, V3<T> d, V3<T> a, V3<T> e1, V3<T> e2, V3<T>& x) {
-  V3<T> n = cross(e1, e2);
-  T h0 = dot(n, p0 - a);
-  T h1 = dot(n, p0 + d - a);
-  bool straddle = (h0 <= T(0) && h1 >= T(0)) || (h0 >= T(0) && h1 <= T(0));
-  bool flat = (h0 == T(0) && h1 == T(0));
-  T den = h0 - h1;
-  T tt = den != T(0) ? h0 / den : T(0);
-  x = fma3(tt, d, p0);
-  // x inside: on the inner side of each edge (edge normals n x edge)
-  V3<T> b = a + e1, c = a + e2;
-  T s0 = dot(n, cross(e1, x - a));
-  T s1 = dot(n, cross(c - b, x - b));
-  T s2 = dot(n, cross(a - c, x - c));
-  bool inside = s0 >= T(0) && s1 >= T(0) && s2 >= T(0);
-  return straddle && !flat && inside && dot(n, n) > T(0);
+DEM_HD V3<T> pick3(int k, V3<T> x0, V3<T> x1, V3<T> x2) {
+  return sel(k == 0, x0, sel(k == 1, x1, x2));
+}
+template <typename T>
+DEM_HD T pick3(int k, T x0, T x1, T x2) {
+  return k == 0 ? x0 : (k == 1 ? x1 : x2);
 }
 
-// Exact distance between A = (a0, a0+e1, a0+e2) and B = (b0, b0+f1, b0+f2).
+// Crossing tests of the three edges of triangle X (vertices x_k, edges
+// x_k -> x_k+1, heights h_k of the vertices over Y's plane along n_Y) through
+// triangle Y (vertices y_k, edges g_k): an edge whose end heights differ in
+// sign meets the plane at one point, which must lie on the inner side of all
+// three edges of Y (in-plane inward normals n_Y x g_k).  The first hit in
+// edge order is kept.
+template <typename T>
+DEM_HD void crossings(const V3<T> (&X)[3], const V3<T> (&EX)[3], const T (&h)[3], const V3<T> (&Y)[3],
+                      const V3<T> (&EY)[3], V3<T> nY, bool ok, bool& hit, V3<T>& xh) {
+  const V3<T> m0 = cross(nY, EY[0]), m1 = cross(nY, EY[1]), m2 = cross(nY, EY[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T h0 = h[k], h1 = h[(k + 1) % 3];
+    const bool straddle = (h0 <= T(0) && h1 >= T(0)) || (h0 >= T(0) && h1 <= T(0));
+    const bool flat = h0 == T(0) && h1 == T(0);
+    const T den = h0 - h1;
+    const T tt = den != T(0) ? h0 * rcp_fast(den) : T(0);
+    const V3<T> x = fma3(tt, EX[k], X[k]);
+    const bool inside = dot(m0, x - Y[0]) >= T(0) && dot(m1, x - Y[1]) >= T(0) && dot(m2, x - Y[2]) >= T(0);
+    const bool c = ok && straddle && !flat && inside;
+    xh = sel(c && !hit, x, xh);
+    hit = hit || c;
+  }
+}
+
+// Vertices of X against the interior of triangle Y = (y0, y0+g1, y0+g2):
+// barycentric coordinates from the in-plane gradients (g2 x n)/|n|^2 and
+// (n x g1)/|n|^2, squared distance h^2/|n|^2 from the heights.  A candidate
+// replaces the best one only if strictly closer.
+template <typename T>
+DEM_HD void vertex_face(const V3<T> (&X)[3], const T (&h)[3], V3<T> y0, V3<T> g1, V3<T> g2, V3<T> nY,
+                        T nn, int feat0, T& best, T& bs, T& bt, int& feat) {
+  const T inn = nn > T(0) ? rcp_fast(nn) : T(0);
+  const V3<T> gs = cross(g2, nY), gt = cross(nY, g1);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const V3<T> r = X[k] - y0;
+    const T s = dot(r, gs) * inn, t = dot(r, gt) * inn;
+    const T din = h[k] * h[k] * inn;
+    const bool c = nn > T(0) && s >= T(0) && t >= T(0) && s + t <= T(1) && din < best;
+    best = c ? din : best;
+    bs = c ? s : bs;
+    bt = c ? t : bt;
+    feat = c ? feat0 + k : feat;
+  }
+}
+
+// Exact distance between A = (a0, a0+e1, a0+e2) and B = (b0, b0+f1, b0+f2)
+// by the comparison-based method (Section 3, direct distance calculation):
+//  1. six edge-through-triangle crossing tests (a hit means distance 0);
+//  2. otherwise the minimum over the six vertex-triangle and nine edge-edge
+//     distances.  A vertex whose projection onto the other triangle's plane
+//     falls outside that triangle has its closest point on one of that
+//     triangle's edges, and the edge-edge distance of an edge through the
+//     vertex is no larger, so only interior projections are candidates.
+// Per-triangle quantities (normal, heights of each vertex over the other
+// plane, edge reciprocals) are formed once; the search keeps (distance,
+// feature, two parameters) and the closest points and weights are rebuilt
+// for the winner only.
 template <typename T>
 DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T> f2,
                           Closest<T>& out) {
-  V3<T> A[3] = {a0, a0 + e1, a0 + e2};
-  V3<T> B[3] = {b0, b0 + f1, b0 + f2};
-  // crossings: edges of A through B, edges of B through A
+  const V3<T> A[3] = {a0, a0 + e1, a0 + e2};
+  const V3<T> B[3] = {b0, b0 + f1, b0 + f2};
+  const V3<T> EA[3] = {e1, e2 - e1, -e2};  // edge k: vertex k -> vertex k+1
+  const V3<T> EB[3] = {f1, f2 - f1, -f2};
+  const V3<T> nA = cross(e1, e2), nB = cross(f1, f2);
+  const T nnA = dot(nA, nA), nnB = dot(nB, nB);
+  // heights of A's vertices over B's plane and of B's over A's (unnormalised)
+  const T hA[3] = {dot(nB, A[0] - b0), dot(nB, A[1] - b0), dot(nB, A[2] - b0)};
+  const T hB[3] = {dot(nA, B[0] - a0), dot(nA, B[1] - a0), dot(nA, B[2] - a0)};
+  // 1. crossings
   bool hit = false;
   V3<T> xh = a0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    V3<T> x;
-    if (seg_crosses(A[k], A[(k + 1) % 3] - A[k], b0, f1, f2, x) && !hit) { hit = true; xh = x; }
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    V3<T> x;
-    if (seg_crosses(B[k], B[(k + 1) % 3] - B[k], a0, e1, e2, x) && !hit) { hit = true; xh = x; }
-  }
-  T best = T(INFINITY);
-  V3<T> bp = a0, bq = b0;
-  T wp0 = 1, wp1 = 0, wp2 = 0, wq0 = 1, wq1 = 0, wq2 = 0;
+  crossings(A, EA, hA, B, EB, nB, nnB > T(0), hit, xh);
+  crossings(B, EB, hB, A, EA, nA, nnA > T(0), hit, xh);
+  // 2a. vertices against the interior of the other triangle
+  T best = T(INFINITY), bs = T(0), bt = T(0);
   int feat = 0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {  // vertex k of A against B
-    V3<T> q;
-    T w[3];
-    T d2 = point_tri(A[k], b0, f1, f2, q, w);
-    if (d2 < best) {
-      best = d2; bp = A[k]; bq = q; feat = k;
-      wp0 = T(k == 0); wp1 = T(k == 1); wp2 = T(k == 2);
-      wq0 = w[0]; wq1 = w[1]; wq2 = w[2];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {  // vertex k of B against A
-    V3<T> q;
-    T w[3];
-    T d2 = point_tri(B[k], a0, e1, e2, q, w);
-    if (d2 < best) {
-      best = d2; bp = q; bq = B[k]; feat = 3 + k;
-      wp0 = w[0]; wp1 = w[1]; wp2 = w[2];
-      wq0 = T(k == 0); wq1 = T(k == 1); wq2 = T(k == 2);
-    }
-  }
-#pragma unroll
+  vertex_face(A, hA, b0, f1, f2, nB, nnB, 0, best, bs, bt, feat);
+  vertex_face(B, hB, a0, e1, e2, nA, nnA, 3, best, bs, bt, feat);
+  // 2b. edges against edges
+  // (the loop over A's edges stays rolled, its edge picked by selects, so
+  // that only three edge pairs are in flight at once: register pressure)
+#pragma unroll 1
   for (int i = 0; i < 3; ++i) {
+    const V3<T> Ai = pick3(i, A[0], A[1], A[2]), EAi = pick3(i, EA[0], EA[1], EA[2]);
+    const T aa = dot(EAi, EAi);
+    const T ia = aa > T(0) ? rcp_fast(aa) : T(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
+      const T ee = dot(EB[j], EB[j]);
+      const T ie = ee > T(0) ? rcp_fast(ee) : T(0);
       T s, t;
-      V3<T> cp, cq;
-      T d2 = seg_seg(A[i], A[(i + 1) % 3] - A[i], B[j], B[(j + 1) % 3] - B[j], s, t, cp, cq);
-      if (d2 < best) {
-        best = d2; bp = cp; bq = cq; feat = 6 + 3 * i + j;
-        wp0 = (i == 0) ? T(1) - s : ((i == 2) ? s : T(0));
-        wp1 = (i == 1) ? T(1) - s : ((i == 0) ? s : T(0));
-        wp2 = (i == 2) ? T(1) - s : ((i == 1) ? s : T(0));
-        wq0 = (j == 0) ? T(1) - t : ((j == 2) ? t : T(0));
-        wq1 = (j == 1) ? T(1) - t : ((j == 0) ? t : T(0));
-        wq2 = (j == 2) ? T(1) - t : ((j == 1) ? t : T(0));
-      }
+      const T d2 = seg_seg_pre(Ai, EAi, aa, ia, B[j], EB[j], ee, ie, s, t);
+      const bool c = d2 < best;
+      best = c ? d2 : best;
+      bs = c ? s : bs;
+      bt = c ? t : bt;
+      feat = c ? 6 + 3 * i + j : feat;
+    }
+  }
+  // closest points and weights of the winning feature
+  V3<T> bp, bq;
+  T wp[3], wq[3];
+  if (feat < 6) {
+    const bool fromB = feat >= 3;
+    const int k = fromB ? feat - 3 : feat;
+    // (component-wise selects: a select of whole structs would be lowered
+    // through private memory)
+    // (normal and height recomputed: keeping them live through the
+    // edge-edge search costs registers)
+    const V3<T> x = sel(fromB, pick3(k, B[0], B[1], B[2]), pick3(k, A[0], A[1], A[2]));
+    const V3<T> nY = sel(fromB, cross(e1, e2), cross(f1, f2));
+    const T h = dot(nY, x - sel(fromB, a0, b0));
+    const T nn = dot(nY, nY);
+    // foot of the perpendicular along the normal (no cancellation in q - p)
+    const V3<T> y = fma3(-h * rcp_fast(nn), nY, x);
+    bp = sel(fromB, y, x);
+    bq = sel(fromB, x, y);
+    const T w0 = T(1) - bs - bt;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const T bary = v == 0 ? w0 : (v == 1 ? bs : bt);
+      const T unit = T(v == k);
+      wp[v] = fromB ? bary : unit;
+      wq[v] = fromB ? unit : bary;
+    }
+  } else {
+    const int i = (feat - 6) / 3, j = (feat - 6) - 3 * ((feat - 6) / 3);
+    bp = fma3(bs, pick3(i, EA[0], EA[1], EA[2]), pick3(i, A[0], A[1], A[2]));
+    bq = fma3(bt, pick3(j, EB[0], EB[1], EB[2]), pick3(j, B[0], B[1], B[2]));
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      wp[v] = v == i ? T(1) - bs : (v == (i + 1) % 3 ? bs : T(0));
+      wq[v] = v == j ? T(1) - bt : (v == (j + 1) % 3 ? bt : T(0));
     }
   }
   if (hit) {
@@ -401,8 +461,8 @@ DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T
   out.d2 = best;
   out.p = bp;
   out.q = bq;
-  out.wp[0] = wp0; out.wp[1] = wp1; out.wp[2] = wp2;
-  out.wq[0] = wq0; out.wq[1] = wq1; out.wq[2] = wq2;
+  out.wp[0] = wp[0]; out.wp[1] = wp[1]; out.wp[2] = wp[2];
+  out.wq[0] = wq[0]; out.wq[1] = wq[1]; out.wq[2] = wq[2];
   out.feature = feat;
 }
 

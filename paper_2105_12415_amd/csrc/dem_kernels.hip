@@ -339,7 +339,6 @@ __device__ __forceinline__ size_t seg_index(const SegView& v, uint32_t i, int64_
   return (size_t)x * (size_t)seg_cap + (i - v.pre[x]);
 }
 
-constexpr int kStageItems = 512;
 constexpr int kStageNear = 512;
 constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between checks
 
@@ -837,6 +836,10 @@ bool params_ok(const dem_params& p) {
   if (p.queue_capacity < kSeg || p.queue_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.near_capacity < kSeg || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.grid < 0) return false;
+  for (int d = 0; d < DEM_MAX_LEVELS; ++d) {
+    if (p.level_grid[d] < 0) return false;
+    if (p.level_batch[d] < 0 || p.level_batch[d] > p.block) return false;  // one item per thread
+  }
   if (p.n_events < 0 || (p.n_events > 0 && !p.events)) return false;
   return true;
 }
@@ -890,7 +893,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   int n_launch = 0;
   auto mark = [&]() {
     if (p.events && n_launch < p.n_events)
-      hipEventRecord(reinterpret_cast<hipEvent_t>(p.events[n_launch]), st);
+      (void)hipEventRecord(reinterpret_cast<hipEvent_t>(p.events[n_launch]), st);
     ++n_launch;
   };
   mark();
@@ -925,7 +928,9 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         la.qout = q[(lev + 1) & 1];
         la.tail_out = ctr->tail[lev + 1];
         la.depth = lev;
-        launch_level<T>(p.n_iter, dim3(grid), dim3(p.block), st, soup, la);
+        la.batch = p.level_batch[lev] > 0 ? p.level_batch[lev] : p.batch_items;
+        const int g = p.level_grid[lev] > 0 ? p.level_grid[lev] : grid;
+        launch_level<T>(p.n_iter, dim3(g), dim3(p.block), st, soup, la);
         mark();
       }
     } else {

@@ -4,6 +4,7 @@ computation is launched here."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -35,6 +36,36 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(_abi.Stats) == 8 * (3 * 32 + 4)
     p = _abi.default_params()
     assert p.n_iter == 4 and p.mode == _abi.DEM_MODE_HIER and p.omega == 1.0
+    assert list(p.level_grid) == [0] * _abi.DEM_MAX_LEVELS and list(p.level_batch) == [0] * _abi.DEM_MAX_LEVELS
+
+
+def test_ctypes_layout_matches_c_compiler(tmp_path):
+    """Every field offset and struct size of the binding equals what a C
+    compiler makes of include/dem.h."""
+    structs = {"dem_build_opts": _abi.BuildOpts, "dem_hierarchy": _abi.Hierarchy, "dem_scene": _abi.Scene,
+               "dem_params": _abi.Params, "dem_contacts": _abi.Contacts, "dem_stats": _abi.Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dem.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, field, val = line.split()
+        py = structs[cname]
+        want = C.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(val) == want, (cname, field, int(val), want)
+        seen += 1
+    assert seen == sum(len(py._fields_) + 1 for py in structs.values())
 
 
 def test_status_strings():

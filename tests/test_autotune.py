@@ -20,6 +20,18 @@ def test_coordinate_descent_never_prefers_failures():
     assert best == {"a": 1}
 
 
+def test_per_depth_knobs_address_param_arrays():
+    from paper_2105_12415_amd import _abi
+    p = _abi.default_params()
+    space = autotune.hier_space(3)
+    assert "level_grid.2" in space and "level_batch.0" in space and "level_grid.3" not in space
+    autotune.set_knob(p, "level_grid.2", 1536)
+    autotune.set_knob(p, "level_batch.0", 64)
+    autotune.set_knob(p, "grid", 2048)
+    assert p.level_grid[2] == 1536 and p.level_batch[0] == 64 and p.grid == 2048
+    assert autotune.get_knob(p, "level_grid.2") == 1536 and autotune.get_knob(p, "level_grid.1") == 0
+
+
 @pytest.mark.gpu
 def test_tuned_parameters_keep_the_contacts():
     import scenegen as sg
@@ -32,7 +44,7 @@ def test_tuned_parameters_keep_the_contacts():
     eng = api.ContactEngine(ds, api.make_params("hier"))
     assert eng.run() == 0
     best, log = autotune.tune_engine(eng, lambda: eng.forward(), reps=2)
-    assert len(log) > 5 and set(best) == set(autotune.HIER_SPACE)
+    assert len(log) > 5 and set(best) == set(autotune.hier_space(ds.n_levels_max))
     assert eng.run() == 0
     r1 = eng.result()
     k0 = set(zip(r0["ti"].tolist(), r0["tj"].tolist()))

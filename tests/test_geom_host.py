@@ -34,6 +34,33 @@ def test_exact_distance_matches_oracle(double, r, a):
     assert np.allclose(np.linalg.norm(got["p2"] - got["p1"], axis=1), got["d"],
                        atol=(1e-12 if double else 1e-5) * (1 + _h(P)))
     assert np.all(got["w1"] >= -1e-6) and np.allclose(got["w1"].sum(1), 1, atol=1e-5)
+    assert np.all(got["w2"] >= -1e-6) and np.allclose(got["w2"].sum(1), 1, atol=1e-5)
+    # the weights reproduce the points (the adjoint scatters with them)
+    h = _h(P)[:, None]
+    tol = (1e-12 if double else 1e-5) * (1 + h)
+    sep = got["d"] > 0
+    assert np.all(np.abs(np.einsum("nk,nki->ni", got["w1"], P[:, 0]) - got["p1"])[sep] <= tol[sep])
+    assert np.all(np.abs(np.einsum("nk,nki->ni", got["w2"], P[:, 1]) - got["p2"])[sep] <= tol[sep])
+    # closest points are unique for separated pairs without a near tie
+    # between features (FP32: no other candidate within 1e-5 of the edge
+    # scale, the criterion the GPU gradient tests use): compare them, and the
+    # unit direction the adjoint uses, with the oracle's.  Rounding moves
+    # the points by ulps of h times the conditioning of the feature (nearly
+    # parallel edges), and the direction by that over d.
+    oracle.set_ambiguity_tol(1e-9 if double else 1e-5)
+    try:
+        amb = oracle.tri_tri_batch(P)["ambiguous"]
+    finally:
+        oracle.set_ambiguity_tol(1e-9)
+    uniq = sep & ~amb & (ref["d"] > 1e-3 * h[:, 0])
+    assert uniq.sum() > len(P) // 4
+    c = 1e-10 if double else 2e-5
+    ptol = c * h[uniq]
+    assert np.all(np.abs(got["p1"] - ref["p1"])[uniq] <= ptol)
+    assert np.all(np.abs(got["p2"] - ref["p2"])[uniq] <= ptol)
+    u_g = (got["p2"] - got["p1"])[uniq] / got["d"][uniq, None]
+    u_r = (ref["p2"] - ref["p1"])[uniq] / ref["d"][uniq, None]
+    assert np.all(np.abs(u_g - u_r) <= c * h[uniq] / ref["d"][uniq, None])
 
 
 @pytest.mark.parametrize("double", [True, False])
