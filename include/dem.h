@@ -163,6 +163,18 @@ typedef struct {
    * verts already are world coordinates.  Gradients are always with respect
    * to world positions. */
   const void* pose;
+  /* Optional lazy flattening (HIER mode): the surrogates whose children are
+   * fine triangles, grouped by tree depth: group d = fine_parents[
+   * fine_parent_begin[d] .. fine_parent_begin[d+1]) holds the depth-d
+   * parents (device array; fine_parent_begin is a host array inside this
+   * struct, fine_parent_begin[0] = 0, non-decreasing up to n_levels_max).
+   * With it, each step writes soup records for the surrogates and root
+   * triangles only; the fine children of a surrogate are written after the
+   * depth at which a pair containing that surrogate survived, so fine
+   * triangles that no descent reaches are never touched.  NULL: every
+   * triangle is written every step (always so in FLAT mode). */
+  const int32_t* fine_parents;
+  int32_t fine_parent_begin[DEM_MAX_LEVELS + 1];
 } dem_scene;
 
 /* ------------------------------------------------------------------ parameters */
@@ -197,11 +209,13 @@ typedef struct {
   int64_t near_capacity;  /* fine pairs the lower bound could not prune (8 segments likewise) */
   /* Optional timing: an array of n_events hipEvent_t (host handles, created
    * by the caller).  events[0] is recorded before the first kernel launch of
-   * dem_find_contacts and events[k] right after its k-th launch, in launch
-   * order: reset, flatten, seed, then one launch per tree depth (HIER) or
-   * the flat tile kernel (FLAT), then the certify kernel (if certify) and
-   * the exact fallback kernel.  Launches beyond
-   * n_events - 1 are not bracketed.  NULL / 0 disables (use that when the
+   * dem_find_contacts and events[k] right after its k-th launch slot, in
+   * order: reset, flatten, seed, then per tree depth d < n_levels_max two
+   * slots, the descent at depth d and the lazy flattening of the children of
+   * its surviving surrogates (an empty slot when nothing is launched) (HIER),
+   * or the flat tile kernel (FLAT), then the certify kernel (if certify) and
+   * the exact fallback kernel.  Slots beyond n_events - 1 are not
+   * bracketed.  NULL / 0 disables (use that when the
    * call is captured into a graph). */
   void* const* events;
   int32_t n_events;

@@ -49,7 +49,8 @@ class Scene(C.Structure):
                 ("verts", C.c_void_p), ("tri_verts", C.c_void_p), ("child_begin", C.c_void_p),
                 ("child_count", C.c_void_p), ("tri_particle", C.c_void_p), ("tri_eps", C.c_void_p),
                 ("root_begin", C.c_void_p), ("root_count", C.c_void_p),
-                ("fine_begin", C.c_void_p), ("fine_count", C.c_void_p), ("pose", C.c_void_p)]
+                ("fine_begin", C.c_void_p), ("fine_count", C.c_void_p), ("pose", C.c_void_p),
+                ("fine_parents", C.c_void_p), ("fine_parent_begin", C.c_int32 * (DEM_MAX_LEVELS + 1))]
 
 
 class Params(C.Structure):

@@ -63,10 +63,15 @@ class DeviceScene:
     fine triangles of particle p are [fine_begin[p], fine_begin[p]+fine_count[p]).
     ``verts`` is the (3, V) world-coordinate tensor the kernels read; replace
     its contents (same tensor) to move the particles.
+
+    ``lazy`` (default) hands the library the surrogates whose children are
+    fine, grouped by depth, so that a step writes fine soup records only for
+    the children of surrogates that survived in some pair; ``lazy=False``
+    writes every record every step.
     """
 
     def __init__(self, scene, device="cuda", coord_scale: Optional[float] = None,
-                 hier_levels: bool = True):
+                 hier_levels: bool = True, lazy: bool = True):
         self.scene = scene
         self.device = torch.device(device)
         self.precision = _abi.DEM_F64 if scene.dtype == "f64" else _abi.DEM_F32
@@ -75,6 +80,7 @@ class DeviceScene:
         if coord_scale is None:
             coord_scale = 1.25 * max(float(np.abs(w).max()) for w in worlds) + 1.0
         tv, cb, cc, tp, ep, rb, rc, fb, fc, vb = [], [], [], [], [], [], [], [], [], []
+        fine_par = {}  # depth -> global ids of surrogates whose children are fine
         nv = nt = 0
         n_levels_max = 1
         self.max_dev = 0.0
@@ -95,6 +101,11 @@ class DeviceScene:
             cc.append(h["child_count"])
             tp.append(np.full(n, p, np.int32))
             ep.append(h["eps_f64"] if self.precision == _abi.DEM_F64 else h["eps_f32"])
+            kids_fine = (h["child_count"] > 0) & (h["child_begin"] >= h["fine_begin"])
+            for lev in range(len(levels) - 1):
+                ids = np.nonzero(kids_fine[offs[lev]:offs[lev + 1]])[0] + offs[lev] + nt
+                if len(ids):
+                    fine_par.setdefault(lev, []).append(ids)
             rb.append(nt + h["root_begin"]); rc.append(h["root_count"])
             fb.append(nt + h["fine_begin"]); fc.append(h["fine_count"])
             vb.append(nv)
@@ -126,6 +137,15 @@ class DeviceScene:
         self.pairs = i32(self.pairs_host.T.copy())  # (2, P)
         self.coord_scale = coord_scale
         self.pose = None
+        self.lazy = lazy and n_levels_max > 1
+        groups = [np.concatenate(fine_par[d]) if d in fine_par else np.zeros(0, np.int64)
+                  for d in range(n_levels_max)]
+        self.fine_parent_begin_host = np.cumsum([0] + [len(g) for g in groups]).astype(np.int64)
+        self.fine_parents = i32(np.concatenate(groups) if groups else np.zeros(0)) if self.lazy else None
+        # records the flatten kernel writes every step (lazy: surrogates and roots)
+        cc_all = np.concatenate(cc)
+        n_fine_roots = int(sum(r for r, f in zip(rc, fc) if r == f))
+        self.n_eager_records = int(np.sum(cc_all > 0)) + n_fine_roots if self.lazy else nt
         self._refresh()
 
     def _refresh(self):
@@ -142,6 +162,12 @@ class DeviceScene:
         s.root_begin, s.root_count = self.root_begin.data_ptr(), self.root_count.data_ptr()
         s.fine_begin, s.fine_count = self.fine_begin.data_ptr(), self.fine_count.data_ptr()
         s.pose = None if self.pose is None else self.pose.data_ptr()
+        if self.lazy and len(self.fine_parents):
+            s.fine_parents = self.fine_parents.data_ptr()
+            for d, v in enumerate(self.fine_parent_begin_host):
+                s.fine_parent_begin[d] = int(v)
+        else:
+            s.fine_parents = None
         self.c = s
 
     def set_verts(self, verts: torch.Tensor):
@@ -169,12 +195,18 @@ class DeviceScene:
 
 # ------------------------------------------------------------------ calls
 def make_params(mode: str = "hier", **kw) -> _abi.Params:
+    """Default dem_params with overrides; ``name.index`` sets one element of
+    an array field (e.g. ``level_grid.3``)."""
     p = _abi.default_params()
     p.mode = _abi.DEM_MODE_HIER if mode == "hier" else _abi.DEM_MODE_FLAT
     for k, v in kw.items():
-        if not hasattr(p, k):
+        field, _, idx = k.partition(".")
+        if not hasattr(p, field):
             raise KeyError(k)
-        setattr(p, k, v)
+        if idx:
+            getattr(p, field)[int(idx)] = v
+        else:
+            setattr(p, field, v)
     return p
 
 

@@ -42,6 +42,11 @@ struct alignas(16) SoupRec {
   int32_t topo[4]; // child_begin, child_count, particle, size bound (float bits)
 };
 
+// Bit of topo[1] (above the child count) marking a surrogate whose children
+// are fine triangles.
+constexpr int kKidsFine = 1 << 16;
+constexpr int kCountMask = 0xFFFF;
+
 // Every work list is split into kSeg segments with a tail counter each; a
 // block appends to segment blockIdx % kSeg (its XCD under round-robin
 // dispatch).  Appends from all compute units to one tail serialise in the
@@ -58,7 +63,7 @@ struct Counters {
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct WsLayout {
-  size_t ctr, soup, qa, qb, near_, fb, total;
+  size_t ctr, soup, mark, qa, qb, near_, fb, total;
 };
 
 WsLayout ws_layout(int precision, int64_t n_tris, int64_t qcap, int64_t ncap) {
@@ -67,6 +72,7 @@ WsLayout ws_layout(int precision, int64_t n_tris, int64_t qcap, int64_t ncap) {
   size_t o = 0;
   L.ctr = o; o = align_up(o + sizeof(Counters), 256);
   L.soup = o; o = align_up(o + rec * (size_t)n_tris, 256);
+  L.mark = o; o = align_up(o + (size_t)n_tris, 256);
   L.qa = o; o = align_up(o + 16 * (size_t)qcap, 256);
   L.qb = o; o = align_up(o + 16 * (size_t)qcap, 256);
   L.near_ = o; o = align_up(o + 8 * (size_t)ncap, 256);
@@ -75,9 +81,11 @@ WsLayout ws_layout(int precision, int64_t n_tris, int64_t qcap, int64_t ncap) {
   return L;
 }
 
+// Soup record t: the triangle, its child range, particle and whether its
+// children are fine.
 template <typename T>
 __device__ __forceinline__ Tri<T> load_tri(const SoupRec<T>* __restrict__ s, int t, int& cb, int& cc,
-                                           int& part) {
+                                           int& part, bool& kids_fine) {
   // 32-bit byte offset from a uniform base (soups stay below 4 GiB)
   const char* rp = reinterpret_cast<const char*>(s) + (uint32_t)t * (uint32_t)sizeof(SoupRec<T>);
   Tri<T> x;
@@ -97,9 +105,17 @@ __device__ __forceinline__ Tri<T> load_tri(const SoupRec<T>* __restrict__ s, int
     x.e1 = {b0.x, b0.y, b1.x}; x.ia = b1.y;
     x.e2 = {c0.x, c0.y, c1.x}; x.ib = c1.y;
   }
-  cb = d.x; cc = d.y; part = d.z;
+  cb = d.x; cc = d.y & kCountMask; part = d.z;
+  kids_fine = (d.y & kKidsFine) != 0;
   x.size = T(__int_as_float(d.w));
   return x;
+}
+
+template <typename T>
+__device__ __forceinline__ Tri<T> load_tri(const SoupRec<T>* __restrict__ s, int t, int& cb, int& cc,
+                                           int& part) {
+  bool kf;
+  return load_tri(s, t, cb, cc, part, kf);
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -150,29 +166,43 @@ __global__ void k_zero_scalar(double* e) {
   if (threadIdx.x == 0) *e = 0.0;
 }
 
+// Flattening inputs (the scene's static arrays, the step's pose, the soup).
 template <typename T>
-__global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, int n_verts,
-                                                 const int32_t* __restrict__ tv, int n_tris,
-                                                 const int32_t* __restrict__ cbeg,
-                                                 const int32_t* __restrict__ ccnt,
-                                                 const int32_t* __restrict__ tpart,
-                                                 const T* __restrict__ teps,
-                                                 const T* __restrict__ pose, T areg_rel,
-                                                 SoupRec<T>* __restrict__ soup, uint32_t* status) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tris) return;
-  const T* X = verts;
-  const T* Y = verts + n_verts;
-  const T* Z = verts + 2 * (size_t)n_verts;
-  int i0 = tv[t], i1 = tv[n_tris + t], i2 = tv[2 * (size_t)n_tris + t];
+struct FlatArgs {
+  const T* verts;
+  int n_verts;
+  const int32_t* tv;
+  int n_tris;
+  const int32_t* cbeg;
+  const int32_t* ccnt;
+  const int32_t* tpart;
+  const T* teps;
+  const T* pose;
+  T areg_rel;
+  const int32_t* root_begin;
+  const int32_t* root_count;
+  const int32_t* fine_begin;
+  SoupRec<T>* soup;
+  uint8_t* mark;  // lazy mode: per-surrogate "a pair with it survived" flags
+  int lazy;
+  uint32_t* status;
+};
+
+// Soup record of triangle t: world vertices (pose applied), edges, the
+// regularised Newton diagonal and the topology word.
+template <typename T>
+__device__ __forceinline__ void flatten_one(const FlatArgs<T>& a, int t, int cb, int cc, int part) {
+  const T* X = a.verts;
+  const T* Y = a.verts + a.n_verts;
+  const T* Z = a.verts + 2 * (size_t)a.n_verts;
+  int i0 = a.tv[t], i1 = a.tv[a.n_tris + t], i2 = a.tv[2 * (size_t)a.n_tris + t];
   V3<T> v0 = {X[i0], Y[i0], Z[i0]};
   V3<T> v1 = {X[i1], Y[i1], Z[i1]};
   V3<T> v2 = {X[i2], Y[i2], Z[i2]};
   V3<T> e1 = v1 - v0, e2 = v2 - v0;
-  const int part = tpart[t];
-  if (pose) {
+  if (a.pose) {
     // rigid motion of the particle applied while flattening: world = R v + c
-    const T* P = pose + 12 * (size_t)part;
+    const T* P = a.pose + 12 * (size_t)part;
     V3<T> r0 = {P[0], P[1], P[2]}, r1 = {P[3], P[4], P[5]}, r2 = {P[6], P[7], P[8]};
     V3<T> c = {P[9], P[10], P[11]};
     v0 = V3<T>{dot(r0, v0), dot(r1, v0), dot(r2, v0)} + c;
@@ -180,19 +210,68 @@ __global__ void __launch_bounds__(256) k_flatten(const T* __restrict__ verts, in
     e2 = V3<T>{dot(r0, e2), dot(r1, e2), dot(r2, e2)};
   }
   T n1 = dot(e1, e1), n2 = dot(e2, e2);
-  T areg = areg_rel * T(0.5) * (n1 + n2);
+  T areg = a.areg_rel * T(0.5) * (n1 + n2);
   T ia = T(1) / (n1 + areg), ib = T(1) / (n2 + areg);
   SoupRec<T> r;
-  r.g[0] = v0.x; r.g[1] = v0.y; r.g[2] = v0.z; r.g[3] = teps[t];
+  r.g[0] = v0.x; r.g[1] = v0.y; r.g[2] = v0.z; r.g[3] = a.teps[t];
   r.g[4] = e1.x; r.g[5] = e1.y; r.g[6] = e1.z; r.g[7] = ia;
   r.g[8] = e2.x; r.g[9] = e2.y; r.g[10] = e2.z; r.g[11] = ib;
   // size bound, rounded up when narrowed to float
   const float sz = (float)(tri_size(e1, e2) * T(1.0 + 1.0 / 1048576.0));
-  r.topo[0] = cbeg[t]; r.topo[1] = ccnt[t]; r.topo[2] = part; r.topo[3] = __float_as_int(sz);
-  soup[t] = r;
+  // children of the last surrogate level start at the particle's fine range
+  const bool kids_fine = cc > 0 && cb >= a.fine_begin[part];
+  r.topo[0] = cb; r.topo[1] = cc | (kids_fine ? kKidsFine : 0); r.topo[2] = part;
+  r.topo[3] = __float_as_int(sz);
+  a.soup[t] = r;
   T chk = v0.x + v0.y + v0.z + e1.x + e1.y + e1.z + e2.x + e2.y + e2.z;
-  if (!isfinite(chk)) atomicOr(status, DEM_DEV_NONFINITE);
-  if (ccnt[t] < 0 || ccnt[t] > DEM_MAX_CHILDREN) atomicOr(status, DEM_DEV_BAD_TREE);
+  if (!isfinite(chk)) atomicOr(a.status, DEM_DEV_NONFINITE);
+}
+
+// Every triangle (eager), or the surrogates and root triangles only (lazy:
+// fine children are written by k_fine once a pair with their parent
+// survives).  Lazy mode also clears the surrogates' survival flags.
+template <typename T>
+__global__ void __launch_bounds__(256) k_flatten(FlatArgs<T> a) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_tris) return;
+  const int cc = a.ccnt[t];
+  if (cc < 0 || cc > DEM_MAX_CHILDREN) atomicOr(a.status, DEM_DEV_BAD_TREE);
+  const int part = a.tpart[t];
+  if (a.lazy) {
+    if (cc > 0) {
+      a.mark[t] = 0;
+    } else if ((uint32_t)(t - a.root_begin[part]) >= (uint32_t)a.root_count[part]) {
+      return;  // a fine triangle below a surrogate
+    }
+  }
+  flatten_one(a, t, a.cbeg[t], cc, part);
+}
+
+// Lazy mode, after the descent at depth d: the children of every depth-d
+// surrogate (parents[0 .. n)) that survived in some pair are written.  Four
+// lanes share a parent and take its children in turn, so sibling records
+// (contiguous) are written together.
+constexpr int kFineLanes = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fine(FlatArgs<T> a, const int32_t* __restrict__ parents, int n) {
+  const int64_t total = (int64_t)n * kFineLanes;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = parents[i / kFineLanes];
+    const int slot = (int)(i % kFineLanes);
+    if ((uint32_t)s >= (uint32_t)a.n_tris) {
+      if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
+      continue;
+    }
+    if (!a.mark[s]) continue;
+    const int cb = a.cbeg[s], cc = a.ccnt[s];
+    if (cc < 1 || cc > DEM_MAX_CHILDREN || cb < 0 || cb > a.n_tris - cc) {
+      if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
+      continue;
+    }
+    for (int c = cb + slot; c < cb + cc; c += kFineLanes) flatten_one(a, c, a.cbeg[c], a.ccnt[c], a.tpart[c]);
+  }
 }
 
 // One block per candidate pair: items covering range_i x range_j in chunks,
@@ -268,6 +347,7 @@ struct LevelArgs {
   int depth;
   int dense;
   int batch;
+  uint8_t* mark;             // lazy flattening: survival flags of surrogates (else null)
   IterParams ip;
 };
 
@@ -426,8 +506,9 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
         ci = it.x + qd;
         cj = it.z + rr;
         int cbi, cci, pi_, cbj, ccj, pj_;
-        Tri<T> A = load_tri(soup, ci, cbi, cci, pi_);
-        Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_);
+        bool kfi, kfj;
+        Tri<T> A = load_tri(soup, ci, cbi, cci, pi_, kfi);
+        Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_, kfj);
         V3<T> D0 = A.v0 - B.v0;
         T L = iterate_bound<T, N>(A, B, D0, a.ip);
         T delta = A.eps + B.eps;
@@ -438,6 +519,12 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
         // non-fine side unfolds); fine survivors go to the near list
         push_item = keep && !fine;
         push_near = keep && fine;
+        // lazy flattening: a surviving surrogate with fine children has them
+        // written before the next depth (plain byte stores of the same value)
+        if (a.mark && push_item) {
+          if (kfi) a.mark[ci] = 1;
+          if (kfj) a.mark[cj] = 1;
+        }
         nx.x = cci ? cbi : ci; nx.y = cci ? cci : 1;
         nx.z = ccj ? cbj : cj; nx.w = ccj ? ccj : 1;
         my_surv += push_item;
@@ -821,6 +908,13 @@ bool scene_ok(const dem_scene* s) {
   if (!s->verts || !s->tri_verts || !s->child_begin || !s->child_count || !s->tri_particle ||
       !s->tri_eps || !s->root_begin || !s->root_count || !s->fine_begin || !s->fine_count)
     return false;
+  if (s->fine_parents) {
+    if (s->fine_parent_begin[0] != 0) return false;
+    for (int d = 0; d < s->n_levels_max; ++d)
+      if (s->fine_parent_begin[d + 1] < s->fine_parent_begin[d] ||
+          s->fine_parent_begin[d + 1] > s->n_tris)
+        return false;
+  }
   return true;
 }
 
@@ -899,11 +993,25 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   mark();
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctr, stats, status, out->count, energy);
   mark();
-  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + 255) / 256), dim3(256), 0, st,
-                     static_cast<const T*>(s->verts), s->n_verts, s->tri_verts, s->n_tris,
-                     s->child_begin, s->child_count, s->tri_particle,
-                     static_cast<const T*>(s->tri_eps), static_cast<const T*>(s->pose),
-                     T(p.alpha_reg_rel), soup, status);
+  FlatArgs<T> fa;
+  fa.verts = static_cast<const T*>(s->verts);
+  fa.n_verts = s->n_verts;
+  fa.tv = s->tri_verts;
+  fa.n_tris = s->n_tris;
+  fa.cbeg = s->child_begin;
+  fa.ccnt = s->child_count;
+  fa.tpart = s->tri_particle;
+  fa.teps = static_cast<const T*>(s->tri_eps);
+  fa.pose = static_cast<const T*>(s->pose);
+  fa.areg_rel = T(p.alpha_reg_rel);
+  fa.root_begin = s->root_begin;
+  fa.root_count = s->root_count;
+  fa.fine_begin = s->fine_begin;
+  fa.soup = soup;
+  fa.mark = reinterpret_cast<uint8_t*>(base + L.mark);
+  fa.lazy = p.mode == DEM_MODE_HIER && s->fine_parents != nullptr;
+  fa.status = status;
+  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + 255) / 256), dim3(256), 0, st, fa);
   mark();
   // per-segment capacities
   const int64_t qseg = p.queue_capacity / kSeg, nseg = p.near_capacity / kSeg;
@@ -916,6 +1024,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   la.status = status;
   la.dense = p.dense_distance;
   la.batch = p.batch_items;
+  la.mark = nullptr;
   la.ip = make_iter(p);
   if (n_pairs > 0) {
     if (p.mode == DEM_MODE_HIER) {
@@ -929,8 +1038,16 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         la.tail_out = ctr->tail[lev + 1];
         la.depth = lev;
         la.batch = p.level_batch[lev] > 0 ? p.level_batch[lev] : p.batch_items;
+        la.mark = fa.lazy ? fa.mark : nullptr;
         const int g = p.level_grid[lev] > 0 ? p.level_grid[lev] : grid;
         launch_level<T>(p.n_iter, dim3(g), dim3(p.block), st, soup, la);
+        mark();
+        // lazy flattening: children of this depth's surviving parents
+        const int f0 = fa.lazy ? s->fine_parent_begin[lev] : 0;
+        const int nf = fa.lazy ? s->fine_parent_begin[lev + 1] - f0 : 0;
+        if (nf > 0)
+          hipLaunchKernelGGL(k_fine<T>, dim3(std::min((nf * kFineLanes + 255) / 256, 8192)), dim3(256), 0,
+                             st, fa, s->fine_parents + f0, nf);
         mark();
       }
     } else {
