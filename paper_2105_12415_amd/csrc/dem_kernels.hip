@@ -422,24 +422,15 @@ __device__ __forceinline__ size_t seg_index(const SegView& v, uint32_t i, int64_
 constexpr int kStageNear = 512;
 constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between checks
 
-// Logical block index with consecutive indices on the same XCD: hardware
-// dispatches workgroups round-robin over the 8 XCDs, each with its own L2,
-// and neighbouring work items share triangles (siblings in the tree).
-__device__ __forceinline__ uint32_t xcd_swizzle(uint32_t bid, uint32_t grid) {
-  constexpr uint32_t kXcd = 8;
-  if (grid % kXcd) return bid;
-  return (bid % kXcd) * (grid / kXcd) + bid / kXcd;
-}
-
 // Descent over one tree depth.  Work items are products of two triangle
 // ranges (the children of a surviving surrogate pair, or a chunk of the
 // roots); lanes take one child pair each, located through a block-wide scan
 // of the items' pair counts.
-#ifndef DEM_BLOCK_ORDER
-#define DEM_BLOCK_ORDER(b, g) xcd_swizzle(b, g)
-#endif
-
-
+//
+// The blocks of XCD x take the batches of segment x, the items that XCD
+// produced at the previous depth (hardware dispatches workgroups
+// round-robin over the 8 XCDs, so block b runs on XCD b % 8): a subtree of
+// the descent stays on one XCD, whose L2 already holds its triangles.
 template <typename T, int N, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
   // LDS sized to the block: one item per thread, stages of two rounds;
@@ -448,21 +439,24 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
   __shared__ int offs[BLOCK + 1];
   __shared__ int wsum[16];
   __shared__ uint8_t owner_s[BLOCK * 8];
-  __shared__ LdsQueue<int4, 2 * BLOCK> qi;
-  __shared__ LdsQueue<int2, 2 * BLOCK> qn;
+  __shared__ LdsQueue<int4, 3 * BLOCK> qi;
+  __shared__ LdsQueue<int2, 3 * BLOCK> qn;
   __shared__ SegView view;
   seg_view(view, a.tail_in, a.qcap);
-  const uint32_t count = view.pre[kSeg];
   const uint32_t bdim = blockDim.x;
+  const uint32_t batch = (uint32_t)a.batch;
   unsigned long long my_evals = 0, my_surv = 0, my_near = 0;
   if (threadIdx.x == 0) { qi.n = 0; qn.n = 0; }
-  // static grid-stride over batches of items (items carry similar work)
-  const uint32_t lb = DEM_BLOCK_ORDER(blockIdx.x, gridDim.x);
-  for (uint32_t b = lb * (uint32_t)a.batch; b < count; b += gridDim.x * (uint32_t)a.batch) {
-    int n = (int)min((uint32_t)a.batch, count - b);
+  // static: the blocks of XCD x (b % 8 == x) stride over segment x
+  const uint32_t x = blockIdx.x % kSeg;
+  const uint32_t per = gridDim.x / kSeg + ((blockIdx.x % kSeg) < (gridDim.x % kSeg) ? 1u : 0u);
+  const uint32_t fill = view.pre[x + 1] - view.pre[x];
+  for (uint32_t first = (blockIdx.x / kSeg) * batch; first < fill; first += per * batch) {
+    const int n = (int)min(batch, fill - first);
+    const int4* seg_items = a.qin + (size_t)x * (size_t)a.qcap + first;
     int np = 0;
     if ((int)threadIdx.x < n) {
-      int4 it = a.qin[seg_index(view, b + threadIdx.x, a.qcap)];
+      int4 it = seg_items[threadIdx.x];
       if (it.y < 1 || it.y > DEM_MAX_CHILDREN || it.w < 1 || it.w > DEM_MAX_CHILDREN) {
         atomicOr(a.status, DEM_DEV_BAD_TREE);  // malformed tree: skip the item
         it.y = it.w = 0;
@@ -480,7 +474,8 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
       for (int q = 0; q < np; ++q) owner_s[o + q] = (uint8_t)threadIdx.x;
     }
     if (mapped) __syncthreads();
-    for (int base = 0; base < total; base += bdim) {
+    int round = 0;
+    for (int base = 0; base < total; base += bdim, ++round) {
       const int e = base + (int)threadIdx.x;
       bool push_item = false, push_near = false;
       int4 nx = make_int4(0, 0, 0, 0);
@@ -532,12 +527,15 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
       }
       lds_append(push_item, nx, qi.buf, &qi.n);
       lds_append(push_near, make_int2(ci, cj), qn.buf, &qn.n);
-      __syncthreads();
-      // flush when another round could overflow the stage (uniform test)
-      if (qi.n + bdim > (uint32_t)(2 * BLOCK))
-        lds_flush(qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
-      if (qn.n + bdim > (uint32_t)(2 * BLOCK))
-        lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+      // check the stages every second round and at the batch's end: after a
+      // check at most BLOCK entries remain, two rounds add at most 2 * bdim
+      if ((round & 1) || base + (int)bdim >= total) {
+        __syncthreads();
+        if (qi.n + 2 * bdim > (uint32_t)(3 * BLOCK))
+          lds_flush(qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
+        if (qn.n + 2 * bdim > (uint32_t)(3 * BLOCK))
+          lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+      }
     }
     __syncthreads();
   }
