@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes as C
+import hashlib
 import json
 import os
 import sys
@@ -182,7 +183,13 @@ def kernel_times(torch, step: Step, K: int):
     return acc / K, bwd / K, stats_acc
 
 
-def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capacity, tune=True):
+TUNE_CACHE = os.path.join(ROOT, "paper_2105_12415_amd", "tuned_params.json")
+
+
+def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capacity, tune="cache",
+             tune_out=None):
+    """tune: "cache" (parameters the autotuner stored for this scene, else
+    time them now), "live" (time them now) or "off" (library defaults)."""
     from paper_2105_12415_amd import autotune
     p = api.make_params(mode, **params_kw)
     eng = api.ContactEngine(ds, p, contact_capacity=contact_capacity, energy_k=1e4)
@@ -194,14 +201,19 @@ def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capac
     if status:
         raise RuntimeError(f"device status {status:#x}")
     eng.tuned = None
-    if tune:
+    if tune != "off":
         space = None
         if mode == "flat":
             space = {"flat_tile_i": (256, 128), "omega": (1.0, 0.5)}
         space = {k: v for k, v in (space or autotune.hier_space(ds.n_levels_max)).items()
                  if k not in params_kw}
-        best, log = autotune.tune_engine(eng, lambda: step(0), space=space, reps=1 if mode == "flat" else 7)
-        eng.tuned = {"chosen": best, "candidates": len(log)}
+        cache = TUNE_CACHE if (tune == "cache" and mode == "hier" and not params_kw) else None
+        best, log = autotune.tune_engine(eng, lambda: step(0), space=space, reps=1 if mode == "flat" else 7,
+                                         cache=cache, write_cache=False)
+        eng.tuned = {"chosen": best, "candidates": len(log),
+                     "source": "stored by the autotuner" if (cache and not log) else "timed now"}
+        if tune_out and log and mode == "hier":
+            autotune.store(tune_out, autotune.signature(eng), best)
         step.pose(0)
         eng.run()
     ms_graph, ms_wall, graph = time_graph(torch, step, K, warmup)
@@ -211,6 +223,42 @@ def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capac
     kt, bwd_ms, st = kernel_times(torch, step, K)
     del graph
     return eng, step, ms_graph, ms_wall, kt, bwd_ms, st
+
+
+def launch_knobs(eng) -> dict:
+    """Every tunable launch/tile knob of the engine's parameters."""
+    from paper_2105_12415_amd import autotune
+    return {k: autotune.get_knob(eng.p, k) for k in autotune.hier_space(eng.ds.n_levels_max)}
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for f in ("dem_kernels.hip", "dem_geom.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2105_12415_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str, launch: dict, profiles_dir: str = None):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload (already scaled by the
+    copy calibration), if it was taken on these kernel sources with these
+    launch parameters; else (None, reason)."""
+    path = os.path.join(profiles_dir or os.path.join(ROOT, "profiles"), f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-json: "):
+            rec = json.loads(line[len("traffic-json: "):])
+    if rec is None or kernel not in rec.get("per_dispatch", {}):
+        return None, "counter summary lacks this kernel"
+    if rec.get("source_sha256") != kernel_sources_sha256():
+        return None, "kernel sources changed since the counters were taken"
+    prof = rec.get("launch", {})
+    if any(abs(float(prof.get(k, -1)) - float(v)) > 1e-6 for k, v in launch.items()):
+        return None, "launch parameters differ from the profiled run"
+    d = rec["per_dispatch"][kernel]
+    return d["read_bytes"] + d["write_bytes"], "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
 
 
 def cpu_baseline(scene, n_sample: int, backward: bool):
@@ -248,6 +296,9 @@ def main():
     ap.add_argument("--contact-capacity", type=int, default=1 << 23)
     ap.add_argument("--param", action="append", default=[], help="dem_params override, e.g. omega=0.5")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the autotuner's candidates now instead of using the stored result")
+    ap.add_argument("--tune-out", default=None, help="write a result timed now to this JSON file")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -283,7 +334,9 @@ def main():
 
     eng, step, ms, ms_wall, kt, bwd_ms, st = run_mode(torch, api, ds, "hier", backward, K, args.warmup,
                                                      params_kw, args.contact_capacity,
-                                                     tune=not args.no_autotune)
+                                                     tune="off" if args.no_autotune else
+                                                     ("live" if args.retune else "cache"),
+                                                     tune_out=args.tune_out)
     evals = float(np.sum(st["evals"]))
     log(f"[bench] hier: {ms:.3f} ms/step (wall {ms_wall:.3f}), {evals:.4g} evals/step, "
         f"{st['contacts']:.0f} contacts, near {st['near']:.0f}")
@@ -296,9 +349,12 @@ def main():
     dtype = "f64" if scene.dtype == "f64" else "f32"
     peak = PEAK_FP64_VALU_TFLOPS if dtype == "f64" else PEAK_FP32_VALU_TFLOPS
     achieved = fl / (level_ms * 1e-3) / 1e12
+    launch = launch_knobs(eng)
+    traffic, traffic_note = measured_traffic(args.workload, "k_level", launch)
     roof = {"bound": "alu", "kernel": f"k_level<{'double' if dtype == 'f64' else 'float'}>",
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "launches_per_step": L, "avg_launch_ms": level_ms / L,
+            "traffic": traffic, "traffic_note": traffic_note,
+            "launches_per_step": L, "avg_launch_ms": level_ms / L,
             "flops_per_eval": flops_per_eval(n_iter), "evals_per_step": evals,
             "peak_published_packed_fp32": 157.3}
     n_written = ds.n_eager_records
@@ -322,7 +378,7 @@ def main():
                       f"; forward contacts, {K} steps captured in one HIP graph"),
                       "particles": ds.n_particles, "triangles_all_levels": ds.n_tris,
                       "candidate_pairs": ds.n_pairs, "fine_pairs": ds.n_fine_pairs(), "n_iter": n_iter,
-                      "autotuned": eng.tuned},
+                      "autotuned": eng.tuned, "launch": launch},
            "roofline": roof, "kernels": kernels,
            "stats": {"evals_per_level": [int(x) for x in st["evals"][:L]],
                      "survivors_per_level": [int(x) for x in st["survivors"][:L]],
@@ -333,7 +389,7 @@ def main():
         torch.cuda.empty_cache()
         fe, fstep, fms, fwall, fkt, fbwd, fst = run_mode(torch, api, ds, "flat", backward, args.flat_steps,
                                                        0, params_kw, args.contact_capacity,
-                                                       tune=not args.no_autotune)
+                                                       tune="off" if args.no_autotune else "live")
         fevals = float(np.sum(fst["evals"]))
         out["flat"] = {"autotuned": fe.tuned, "ms_per_step": fms, "ms_per_step_wall": fwall, "evals_per_step": fevals,
                        "evals_per_s": fevals / (fms * 1e-3), "contacts": fst["contacts"],

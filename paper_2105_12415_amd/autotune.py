@@ -107,20 +107,41 @@ def time_step(step: Callable[[], None], reps: int = 5, warmup: int = 1) -> float
     return ts[len(ts) // 2]
 
 
+def signature(engine) -> str:
+    """Key of a tuning result: scene sizes, precision, mode and N_it."""
+    ds, p = engine.ds, engine.p
+    return f"{ds.n_tris}:{ds.n_verts}:{ds.n_pairs}:{ds.precision}:{p.mode}:{p.n_iter}"
+
+
+def store(path: str, sig: str, best: Dict) -> None:
+    """Add (or replace) one tuning result in the JSON file at path."""
+    data = {}
+    if os.path.exists(path):
+        try:
+            data = json.load(open(path))
+        except (OSError, ValueError):
+            data = {}
+    data[sig] = {k: (float(v) if isinstance(v, float) else int(v)) for k, v in best.items()}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+
+
 def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequence]] = None,
-                reps: int = 5, cache: Optional[str] = None) -> Tuple[Dict, List[Tuple[Dict, float]]]:
+                reps: int = 5, cache: Optional[str] = None,
+                write_cache: bool = True) -> Tuple[Dict, List[Tuple[Dict, float]]]:
     """Tune engine.p in place for ``step`` (which must call engine.forward()).
 
     The chosen values are applied to engine.p and returned; ``cache`` (a
-    JSON path) stores them keyed by a signature of the scene and mode, and a
-    later call with the same signature reuses them without timing.
+    JSON path) holds results keyed by a signature of the scene and mode: a
+    stored result is applied without timing (the returned log is then
+    empty), otherwise the timed result is added to it (if write_cache).
     """
     from . import _abi
     p = engine.p
     ds = engine.ds
     if space is None:
         space = hier_space(ds.n_levels_max) if p.mode == _abi.DEM_MODE_HIER else FLAT_SPACE
-    sig = f"{ds.n_tris}:{ds.n_verts}:{ds.n_pairs}:{ds.precision}:{p.mode}:{p.n_iter}"
+    sig = signature(engine)
     if cache and os.path.exists(cache):
         try:
             stored = json.load(open(cache)).get(sig)
@@ -147,14 +168,6 @@ def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequ
     best, log = coordinate_descent(measure, start, space)
     for k, v in best.items():
         set_knob(p, k, v)
-    if cache:
-        data = {}
-        if os.path.exists(cache):
-            try:
-                data = json.load(open(cache))
-            except (OSError, ValueError):
-                data = {}
-        data[sig] = {k: (float(v) if isinstance(v, float) else int(v)) for k, v in best.items()}
-        with open(cache, "w") as f:
-            json.dump(data, f, indent=1)
+    if cache and write_cache:
+        store(cache, sig, best)
     return best, log
