@@ -165,7 +165,9 @@ def tune_engine(engine, step: Callable[[], None], space: Optional[Dict[str, Sequ
             return float("inf")  # e.g. a capacity overflow: never prefer it
         return t
 
-    best, log = coordinate_descent(measure, start, space)
+    # two sweeps: a knob chosen early (the global grid) is revisited once the
+    # per-depth knobs have taken over the launches it first decided
+    best, log = coordinate_descent(measure, start, space, sweeps=2)
     for k, v in best.items():
         set_knob(p, k, v)
     if cache and write_cache:

@@ -696,19 +696,24 @@ __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ sou
   __shared__ LdsQueue<int2, kStageNear> qf;
   __shared__ SegView view;
   seg_view(view, a.near_tail, a.ncap);
-  const uint32_t cnt = view.pre[kSeg];
   const uint32_t bdim = blockDim.x;
   double e_acc = 0.0;
   unsigned long long my_fb = 0, my_cert = 0, my_c = 0;
   if (threadIdx.x == 0) { qc.n = 0; qf.n = 0; }
   __syncthreads();
-  for (uint32_t base = blockIdx.x * bdim; base < cnt; base += gridDim.x * bdim) {
+  // the blocks of XCD x (b % 8 == x) take segment x: the near pairs that XCD
+  // found at the last depth, whose triangles its L2 may still hold
+  const uint32_t x = blockIdx.x % kSeg;
+  const uint32_t per = gridDim.x / kSeg + ((blockIdx.x % kSeg) < (gridDim.x % kSeg) ? 1u : 0u);
+  const uint32_t fill = view.pre[x + 1] - view.pre[x];
+  const int2* seg = a.near_ + (size_t)x * (size_t)a.ncap;
+  for (uint32_t base = (blockIdx.x / kSeg) * bdim; base < fill; base += per * bdim) {
     const uint32_t e = base + threadIdx.x;
     bool emit = false, defer = false;
     ContactRec<T> rec;
     int2 pr = make_int2(0, 0);
-    if (e < cnt) {
-      pr = a.near_[seg_index(view, e, a.ncap)];
+    if (e < fill) {
+      pr = seg[e];
       int cbi, cci, cbj, ccj, pi_, pj_;
       Tri<T> A = load_tri(soup, pr.x, cbi, cci, pi_);
       Tri<T> B = load_tri(soup, pr.y, cbj, ccj, pj_);
