@@ -79,23 +79,31 @@ static double point_segment(const double p[3], const double a[3], const double b
   return t;
 }
 
+/* A triangle is degenerate (a segment or a point: no interior) when the sine
+ * of its angle at x0 is below 1e-12; FP64 rounding of the normal is ~1e-16. */
+static int degenerate(double nn, double a, double c) { return !(nn > 1e-24 * a * c) || !(nn > 0.0); }
+
 /* ------------------------------------------------- point against triangle */
 /* Closest point q on triangle (x0,x1,x2) to p, with barycentric weights w.
  * Minimises |x0 + u e1 + v e2 - p|^2 over u,v >= 0, u + v <= 1.  The
  * unconstrained minimiser is the answer when feasible; otherwise the minimum
- * lies on the boundary, i.e. on one of the three edges. Returns distance. */
+ * lies on the boundary, i.e. on one of the three edges.  The minimiser's
+ * coordinates are ratios of signed areas (triple products with the normal
+ * n = e1 x e2), which stay accurate for slivers; a degenerate triangle has
+ * only its boundary.  Returns distance. */
 static double point_triangle(const double p[3], const double x0[3], const double x1[3],
                              const double x2[3], double q[3], double w[3]) {
-  double e1[3], e2[3], r[3];
+  double e1[3], e2[3], r[3], n[3], t1[3], t2[3];
   sub3(x1, x0, e1);
   sub3(x2, x0, e2);
   sub3(p, x0, r);
-  double a = dot3(e1, e1), b = dot3(e1, e2), c = dot3(e2, e2);
-  double f = dot3(e1, r), g = dot3(e2, r);
-  double det = a * c - b * b;
-  if (det > 1e-300 * (a * c + 1e-300)) {
-    double u = (c * f - b * g) / det;
-    double v = (a * g - b * f) / det;
+  cross3(e1, e2, n);
+  double nn = dot3(n, n);
+  if (!degenerate(nn, dot3(e1, e1), dot3(e2, e2))) {
+    cross3(r, e2, t1);
+    cross3(e1, r, t2);
+    double u = dot3(n, t1) / nn;
+    double v = dot3(n, t2) / nn;
     if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
       q[0] = x0[0] + u * e1[0] + v * e2[0];
       q[1] = x0[1] + u * e1[1] + v * e2[1];
@@ -191,7 +199,9 @@ static int segment_pierces(const double p0[3], const double p1[3], const double 
   sub3(x2, x0, e2);
   cross3(e1, e2, n);
   double nn = dot3(n, n);
-  if (!(nn > 0.0)) return 0;
+  /* a degenerate triangle has no interior to cross: touching it shows up as a
+   * zero segment-segment or point distance */
+  if (degenerate(nn, dot3(e1, e1), dot3(e2, e2))) return 0;
   sub3(p0, x0, r0);
   sub3(p1, x0, r1);
   double h0 = dot3(n, r0), h1 = dot3(n, r1);
@@ -201,14 +211,14 @@ static int segment_pierces(const double p0[3], const double p1[3], const double 
   double d[3];
   sub3(p1, p0, d);
   axpy3(p0, t, d, x);
-  /* barycentric coordinates of x in the triangle (x lies in its plane) */
-  double r[3];
+  /* barycentric coordinates of x in the triangle (x lies in its plane), as
+   * ratios of signed areas */
+  double r[3], t1[3], t2[3];
   sub3(x, x0, r);
-  double a = dot3(e1, e1), b = dot3(e1, e2), c = dot3(e2, e2);
-  double f = dot3(e1, r), g = dot3(e2, r);
-  double det = a * c - b * b;
-  double u = (c * f - b * g) / det;
-  double v = (a * g - b * f) / det;
+  cross3(r, e2, t1);
+  cross3(e1, r, t2);
+  double u = dot3(n, t1) / nn;
+  double v = dot3(n, t2) / nn;
   if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
     w[0] = 1.0 - u - v; w[1] = u; w[2] = v;
     *s = t;

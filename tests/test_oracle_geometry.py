@@ -128,6 +128,59 @@ def test_dense_sampling_bound():
         assert m <= d + (_diam(A) + _diam(B)) / n + 1e-12
 
 
+def degenerate_pairs(n, seed=5):
+    """Pairs with a degenerate triangle: collinear vertices (a segment), a
+    repeated vertex, all three equal (a point), and a collinear triangle
+    against a sliver of relative width 1e-9."""
+    rng = np.random.default_rng(seed)
+    P = np.zeros((n, 2, 3, 3))
+    for i in range(n):
+        A = rng.uniform(-1, 1, (3, 3))
+        B = rng.uniform(-1, 1, (3, 3)) + rng.uniform(-1.5, 1.5, 3)
+        kind = i % 4
+        if kind == 0:
+            A[2] = A[0] + 0.37 * (A[1] - A[0])
+        elif kind == 1:
+            A[1] = A[0]
+        elif kind == 2:
+            A[1] = A[0]
+            A[2] = A[0]
+        else:
+            A[2] = A[0] + 0.37 * (A[1] - A[0])
+            B[1] = B[0] + 1e-9 * (B[2] - B[0])
+        P[i] = (A, B) if i % 8 < 4 else (B, A)
+    return P
+
+
+def test_degenerate_triangles_sampling():
+    """A triangle without interior (segment, point) is met only through its
+    boundary: no edge can cross it.  Brute force bounds d from both sides."""
+    P = degenerate_pairs(400)
+    res = oracle.tri_tri_batch(P)
+    n = 40
+    for k in range(0, len(P), 4):
+        A, B = P[k]
+        SA, SB = _sample_triangle(A, n), _sample_triangle(B, n)
+        m = np.min(np.linalg.norm(SA[:, None] - SB[None], axis=2))
+        d = res["d"][k]
+        assert m >= d - 1e-12, (k, d, m)
+        assert m <= d + (_diam(A) + _diam(B)) / n + 1e-12, (k, d, m)
+
+
+def test_degenerate_closed_forms():
+    # a collinear "triangle" (a segment) parallel to a face, above its interior
+    face = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [0.0, 2.0, 0.0]])
+    seg = np.array([[0.2, 0.3, 0.25], [0.8, 0.3, 0.25], [0.5, 0.3, 0.25]])
+    r = oracle.tri_tri(seg, face)
+    assert abs(r["d"] - 0.25) <= 1e-15 and r["feature"] != 15
+    # the segment passing through the face's plane inside it: distance 0
+    seg2 = np.array([[0.3, 0.3, -0.5], [0.3, 0.3, 0.5], [0.3, 0.3, 0.0]])
+    assert oracle.tri_tri(seg2, face)["d"] <= 1e-15
+    # a point: the point-to-triangle distance (nearest point on an edge here)
+    pt = np.array([[3.0, -1.0, 0.0]] * 3)
+    assert abs(oracle.tri_tri(pt, face)["d"] - np.hypot(1.0, 1.0)) <= 1e-15
+
+
 def test_point_triangle_and_segments_sampling():
     rng = np.random.default_rng(5)
     for _ in range(200):
