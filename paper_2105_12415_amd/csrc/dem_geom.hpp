@@ -301,7 +301,8 @@ DEM_HD T seg_seg_pre(V3<T> p0, V3<T> d1, T a, T ia, V3<T> q0, V3<T> d2, T e, T i
   t = (b * s + f) * ie;
   T s_lo = clamp01(-c * ia);
   T s_hi = clamp01((b - c) * ia);
-  bool lo = t < T(0), hi = t > T(1);
+  // a second segment of zero length is a point: t = 0 and s its projection
+  bool lo = t < T(0) || !(e > T(0)), hi = t > T(1);
   s = lo ? s_lo : (hi ? s_hi : s);
   t = lo ? T(0) : (hi ? T(1) : t);
   V3<T> dd = fma3(s, d1, r) - t * d2;

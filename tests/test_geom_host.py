@@ -20,7 +20,9 @@ def _cases():
     A = rng.uniform(-1, 1, (20000, 3, 3))
     B = A + rng.normal(0, 1e-3, A.shape) + rng.normal(0, 0.05, (20000, 1, 3))  # near parallel
     C = sg.random_triangle_pairs(20000, seed=23, scale=0.05, spread=0.2) + 20.0  # far from origin
-    return np.concatenate([P, np.stack([A, B], 1), C.astype(np.float32).astype(np.float64)])
+    from test_oracle_geometry import degenerate_pairs
+    D = degenerate_pairs(4000, seed=24)  # segments, points, slivers
+    return np.concatenate([P, np.stack([A, B], 1), C.astype(np.float32).astype(np.float64), D])
 
 
 @pytest.mark.parametrize("double,r,a", [(True, 1e-12, 1e-13), (False, 1e-5, 1e-6)])
@@ -61,6 +63,18 @@ def test_exact_distance_matches_oracle(double, r, a):
     u_g = (got["p2"] - got["p1"])[uniq] / got["d"][uniq, None]
     u_r = (ref["p2"] - ref["p1"])[uniq] / ref["d"][uniq, None]
     assert np.all(np.abs(u_g - u_r) <= c * h[uniq] / ref["d"][uniq, None])
+
+
+@pytest.mark.parametrize("double,r,a", [(True, 1e-12, 1e-13), (False, 1e-5, 1e-6)])
+def test_exact_distance_degenerate_triangles(double, r, a):
+    """Segments, points and slivers: the product's exact distance against the
+    oracle (pinned to brute force on the same cases)."""
+    from test_oracle_geometry import degenerate_pairs
+    P = degenerate_pairs(4000, seed=9)
+    ref = oracle.tri_tri_batch(P)
+    got = host_geom.exact(P, double)
+    err = np.abs(got["d"] - ref["d"]) - (r * ref["d"] + a * _h(P))
+    assert np.all(err <= 0), (np.max(err), int(np.argmax(err)))
 
 
 @pytest.mark.parametrize("double", [True, False])

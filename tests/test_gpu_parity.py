@@ -207,6 +207,53 @@ def test_lazy_flatten_matches_eager(case):
     assert np.allclose(ga, gb, rtol=1e-5, atol=1e-6 * np.abs(gb).max())
 
 
+def _degenerate_scene(dtype):
+    """Two s=2 spheres (levels 0..2) whose facing sides carry degenerate fine
+    triangles: a vertex collapsed onto its neighbour (a repeated vertex) and
+    a vertex moved to the middle of an opposite edge (collinear vertices)."""
+    scene = sg.two_spheres(2, [0, 1, 2], dtype, sep=2.03, stream_id=46, name="degenerate")
+    for p, sign in ((0, 1.0), (1, -1.0)):
+        part = scene.particles[p]
+        w = part.body @ part.rot.T
+        tris = part.fine
+        facing = np.argsort(-sign * w[tris].mean(1)[:, 0])[:12]  # faces towards the other sphere
+        for n, f in enumerate(facing[::2]):
+            i, j, k = tris[f]
+            if n % 2 == 0:
+                part.body[j] = part.body[i]
+            else:
+                part.body[k] = 0.5 * (part.body[i] + part.body[j])
+    return scene
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_degenerate_triangles_scene(prec):
+    """Segments and repeated vertices among the fine triangles: every fine
+    pair's exact distance (dense mode) and the hierarchical contact set
+    against the oracle."""
+    scene = _degenerate_scene(prec)
+    fs = oracle.fine_scene(scene)
+    tris = fs.tris
+    A = fs.verts[tris]
+    area2 = np.linalg.norm(np.cross(A[:, 1] - A[:, 0], A[:, 2] - A[:, 0]), axis=1)
+    assert np.sum(area2 <= 1e-12 * np.max(area2)) >= 6  # the scene really holds degenerate triangles
+    ds, eng, res = run(scene, "hier", dense_distance=1)
+    ref = oracle.find_contacts(fs, delta=np.inf, prereject=False)
+    g = keyed(ds, res)
+    o = oracle_keyed(scene, ref)
+    assert set(g) == set(o)
+    common = sorted(o)
+    dg = np.array([res["d"][g[k]] for k in common])
+    dr = np.array([ref["d"][o[k]] for k in common])
+    h = np.array([longest_edge(*pair_geom(fs, *k)) for k in common])
+    tol = TOL[prec]
+    err = np.abs(dg - dr) - (tol["r"] * dr + tol["a"] * h)
+    assert np.all(err <= 0), (np.max(err), common[int(np.argmax(err))])
+    ds, eng, res = run(scene, "hier")
+    n, _, _ = compare_sets(scene, ds, res, oracle.find_contacts(fs), tol, fs)
+    assert n > 10
+
+
 # ------------------------------------------------------------------ gradients
 def _grad_compare(scene, prec):
     tol = TOL[prec]
