@@ -183,7 +183,7 @@ def kernel_times(torch, step: Step, K: int):
     return acc / K, bwd / K, stats_acc
 
 
-TUNE_CACHE = os.path.join(ROOT, "paper_2105_12415_amd", "tuned_params.json")
+from paper_2105_12415_amd.autotune import STORED as TUNE_CACHE  # noqa: E402
 
 
 def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capacity, tune="cache",

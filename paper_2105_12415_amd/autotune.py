@@ -107,6 +107,24 @@ def time_step(step: Callable[[], None], reps: int = 5, warmup: int = 1) -> float
     return ts[len(ts) // 2]
 
 
+STORED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_params.json")
+
+
+def apply_stored(engine, path: str = STORED) -> Optional[Dict]:
+    """Apply the stored tuning result for the engine's scene (the launch
+    parameters the benchmark times), if there is one; returns it."""
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(signature(engine))
+    except (OSError, ValueError):
+        return None
+    if rec:
+        for k, v in rec.items():
+            set_knob(engine.p, k, v)
+    return rec
+
+
 def signature(engine) -> str:
     """Key of a tuning result: scene sizes, precision, mode and N_it."""
     ds, p = engine.ds, engine.p

@@ -254,6 +254,30 @@ def test_degenerate_triangles_scene(prec):
     assert n > 10
 
 
+@pytest.mark.parametrize("mode", ["hier", "flat"])
+@pytest.mark.parametrize("case", ["no_pairs", "far_apart"])
+def test_empty_inputs(mode, case):
+    """No candidate pairs, or a pair whose particles are too far apart for any
+    contact: no contacts, zero energy, zero gradient, clean status."""
+    scene = sg.two_spheres(2, [0, 1, 2], "f32", sep=2.03 if case == "no_pairs" else 3.0,
+                           stream_id=47, name=case)
+    if case == "no_pairs":
+        scene.pairs = np.zeros((0, 2), np.int32)
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params(mode), energy_k=1e4)
+    assert eng.run() == 0
+    res = eng.result()
+    assert len(res["d"]) == 0 and res["energy"] == 0.0
+    grad = torch.ones(3, ds.n_verts, dtype=ds.dtype, device="cuda:0")
+    eng.backward(grad, energy=True)
+    torch.cuda.synchronize()
+    assert eng.check() == 0
+    assert float(eng.energy_bwd.item()) == 0.0
+    assert bool(torch.all(grad == 1.0))  # accumulated into, nothing added
+    if case == "far_apart":
+        assert oracle.find_contacts(oracle.fine_scene(scene))["d"].size == 0
+
+
 # ------------------------------------------------------------------ gradients
 def _grad_compare(scene, prec):
     tol = TOL[prec]

@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import scenegen as sg
-from paper_2105_12415_amd import api
+from paper_2105_12415_amd import api, autotune
 
 from test_gpu_parity import TOL, longest_edge, say
 
@@ -70,11 +70,25 @@ def _check_pairs(scene, ds, res, fs, idx, tol, extra=0.0):
     return len(common), ref
 
 
+def _engine(ds):
+    """The engine in the launch configuration the benchmark times: the
+    autotuner's stored parameters for this scene where there are some."""
+    eng = api.ContactEngine(ds, api.make_params("hier"), contact_capacity=1 << 23)
+    autotune.apply_stored(eng)
+    return eng
+
+
+def test_lattice_uses_the_stored_launch_configuration():
+    scene, ds = _scene("lattice")
+    eng = api.ContactEngine(ds, api.make_params("hier"))
+    assert autotune.apply_stored(eng) is not None
+
+
 @pytest.mark.parametrize("name,n_sample", [("lattice", 24), ("big_small", 6)])
 def test_full_scene_sampled_pairs(name, n_sample):
     scene, ds = _scene(name)
     ds.set_pose(None)
-    eng = api.ContactEngine(ds, api.make_params("hier"), contact_capacity=1 << 23)
+    eng = _engine(ds)
     assert eng.run() == 0
     res = eng.result()
     say(f"[gpu-test] {name}: {len(res['d'])} contacts, stats {eng.stats_dict()['evals'][:9].tolist()}")
@@ -120,7 +134,7 @@ def test_fwd_bwd_steps_sampled_gradient(step):
     shift = centres + ts[step] - np.einsum("pij,pj->pi", Rs[step], centres)
     pose = np.concatenate([Rs[step].reshape(P, 9), shift], 1)
     ds.set_pose(torch.as_tensor(pose, dtype=ds.dtype, device="cuda:0").contiguous())
-    eng = api.ContactEngine(ds, api.make_params("hier"), contact_capacity=1 << 23)
+    eng = _engine(ds)
     assert eng.run() == 0
     res = eng.result()
     moved = [(scene.world(p) - centres[p]) @ Rs[step][p].T + centres[p] + ts[step][p] for p in range(P)]
