@@ -115,8 +115,10 @@ typedef struct {
  *           concatenated from the coarsest (level 0, the root model) to the
  *           finest (the particle triangulation).
  * parent    [n_tris] host: for a triangle of level l >= 1 the id (into
- *           tris) of its parent in level l-1; ignored for level 0.  Children
- *           of one parent must be contiguous and levels sorted by parent.
+ *           tris) of its parent: in level l-1 for surrogate levels, in any
+ *           earlier level for the last (fine) level, so that leaf sets may
+ *           sit at different depths; ignored for level 0.  Children of one
+ *           parent must be contiguous and levels sorted by parent.
  * level_sizes [n_levels] host: triangles per level (sum = n_tris).
  * eps0      epsilon of the fine triangles (uniform per particle, Section 2).
  * opts      may be NULL (defaults).
@@ -136,6 +138,62 @@ dem_status dem_build_hierarchy(const double* verts, int32_t n_verts, const int32
                                const int32_t* parent, const int32_t* level_sizes, int32_t n_levels,
                                double eps0, const dem_build_opts* opts, dem_hierarchy* out);
 void dem_hierarchy_free(dem_hierarchy* h);
+
+/*
+ * Surrogate trees for generic meshes (Appendix B, Algorithm 7, with the
+ * surrogate triangles of Appendix A).  Offline, host, FP64.
+ */
+typedef struct {
+  int32_t fanout;        /* N_surrogate: subsets per split and largest leaf set (2..DEM_MAX_CHILDREN) */
+  int32_t kmeans_iters;  /* Lloyd iterations of each k-means split */
+  int32_t fit_iters;     /* descent steps of each surrogate fit */
+  double beta_size;      /* exponent of the size term (>= 2) */
+  double alpha_area;     /* weight of the anti-degeneracy term (> 0; coordinates scaled by the set radius) */
+  double alpha_inside;   /* weight of the outer-normal term (>= 0) */
+  double beta_normal;    /* exponent of the outer-normal term (>= 1) */
+} dem_tree_opts;
+
+typedef struct {
+  int32_t n_verts;       /* the mesh's vertices, then three per surrogate */
+  double* verts;         /* [n_verts][3] */
+  int32_t n_tris;        /* surrogates + mesh triangles */
+  int32_t* tris;         /* [n_tris][3]: surrogates depth by depth, then the mesh triangles grouped by parent */
+  int32_t* parent;       /* [n_tris]: -1 for the root; a surrogate of depth d >= 1 hangs below depth
+                            d-1, a mesh triangle below any surrogate */
+  int32_t n_levels;      /* surrogate depths + 1 */
+  int32_t* level_sizes;  /* [n_levels]: surrogates per depth, then the number of mesh triangles */
+  int32_t* fine_order;   /* [number of mesh triangles]: input index of each mesh triangle in output order */
+} dem_surrogate_tree;
+
+/* Fill o with the defaults (fanout 8, 12 k-means iterations, 60 fit steps,
+ * beta_size 8, alpha_area 1e-3, alpha_inside 1, beta_normal 2). */
+void dem_default_tree_opts(dem_tree_opts* o);
+
+/*
+ * dem_build_surrogate_tree -- top-down surrogate tree of one particle.
+ *
+ * verts     [n_verts][3] host, FP64; tris [n_tris][3] host: the particle's
+ *           triangulation (any closed or open mesh).
+ * opts      may be NULL (defaults).
+ * out       library-allocated host arrays, released by
+ *           dem_surrogate_tree_free; its verts, tris, parent, level_sizes
+ *           and n_levels are the arguments dem_build_hierarchy takes.
+ *
+ * A set of more than fanout triangles is split into at most fanout subsets
+ * by k-means on the triangle centroids (farthest-point start), each subset
+ * gets a surrogate triangle, and the recursion continues; a set of at most
+ * fanout triangles becomes the children of its surrogate.  A surrogate
+ * triangle minimises Appendix A's functional: a high power of the distances
+ * from its vertices to the set's triangles (small), a penalty on its inverse
+ * squared area (not degenerate) and one on its vertices lying outside the
+ * set's triangles along its outer normal (nestled).  Epsilons are not set
+ * here: dem_build_hierarchy gives every surrogate the smallest conservative
+ * one, so any surrogate triangle is correct and the fit only matters for
+ * how much it prunes.  Returns DEM_ERR_ARG on malformed input.
+ */
+dem_status dem_build_surrogate_tree(const double* verts, int32_t n_verts, const int32_t* tris,
+                                    int32_t n_tris, const dem_tree_opts* opts, dem_surrogate_tree* out);
+void dem_surrogate_tree_free(dem_surrogate_tree* t);
 
 /* ------------------------------------------------------------------ scene */
 

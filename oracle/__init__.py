@@ -263,17 +263,20 @@ def tree(scene, verts_override=None) -> OracleTree:
         parent = np.full(n, -1, np.int64)
         cbeg = np.zeros(n, np.int64)
         ccnt = np.zeros(n, np.int64)
+        absolute = getattr(part, "parents_absolute", False)
         for l in range(1, len(part.levels)):
-            pa = part.parents[l].astype(np.int64) + offs[l - 1]
+            pa = part.parents[l].astype(np.int64) + (0 if absolute else offs[l - 1])
             parent[offs[l]:offs[l + 1]] = pa + nt
             ids = np.arange(offs[l], offs[l + 1])
-            # children of one parent are contiguous
-            first = np.full(offs[l] - offs[l - 1], -1, np.int64)
+            # children of one parent are contiguous; parents may sit in any
+            # earlier level (particle-local ids in pa)
+            first = np.full(offs[l], -1, np.int64)
             for i_loc, pp in zip(ids[::-1], pa[::-1]):
-                first[pp - offs[l - 1]] = i_loc
-            cnt = np.bincount(pa - offs[l - 1], minlength=offs[l] - offs[l - 1])
-            cbeg[offs[l - 1]:offs[l]] = first + nt
-            ccnt[offs[l - 1]:offs[l]] = cnt
+                first[pp] = i_loc
+            cnt = np.bincount(pa, minlength=offs[l])
+            has = cnt > 0
+            cbeg[:offs[l]][has] = first[has] + nt
+            ccnt[:offs[l]][has] = cnt[has]
         is_fine = ccnt == 0
         e = surrogate_eps(w, t_loc, np.where(parent >= 0, parent - nt, -1), is_fine, part.eps0)
         vs.append(w)

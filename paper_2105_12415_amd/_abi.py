@@ -26,11 +26,24 @@ DEM_MAX_CHILDREN = 16
 
 # Every exported symbol declared in include/dem.h.
 EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "dem_workspace_bytes",
-           "dem_find_contacts", "dem_contact_backward", "dem_status_string", "dem_version")
+           "dem_find_contacts", "dem_contact_backward", "dem_status_string", "dem_version",
+           "dem_default_tree_opts", "dem_build_surrogate_tree", "dem_surrogate_tree_free")
 
 
 class BuildOpts(C.Structure):
     _fields_ = [("coord_scale", C.c_double), ("rel_slack", C.c_double)]
+
+
+class TreeOpts(C.Structure):
+    _fields_ = [("fanout", C.c_int32), ("kmeans_iters", C.c_int32), ("fit_iters", C.c_int32),
+                ("beta_size", C.c_double), ("alpha_area", C.c_double), ("alpha_inside", C.c_double),
+                ("beta_normal", C.c_double)]
+
+
+class SurrogateTree(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("verts", C.POINTER(C.c_double)), ("n_tris", C.c_int32),
+                ("tris", C.POINTER(C.c_int32)), ("parent", C.POINTER(C.c_int32)), ("n_levels", C.c_int32),
+                ("level_sizes", C.POINTER(C.c_int32)), ("fine_order", C.POINTER(C.c_int32))]
 
 
 class Hierarchy(C.Structure):
@@ -100,6 +113,13 @@ def lib():
         L.dem_build_hierarchy.restype = C.c_int
         L.dem_hierarchy_free.argtypes = [C.POINTER(Hierarchy)]
         L.dem_hierarchy_free.restype = None
+        L.dem_default_tree_opts.argtypes = [C.POINTER(TreeOpts)]
+        L.dem_default_tree_opts.restype = None
+        L.dem_build_surrogate_tree.argtypes = [C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
+                                               C.c_int32, C.POINTER(TreeOpts), C.POINTER(SurrogateTree)]
+        L.dem_build_surrogate_tree.restype = C.c_int
+        L.dem_surrogate_tree_free.argtypes = [C.POINTER(SurrogateTree)]
+        L.dem_surrogate_tree_free.restype = None
         L.dem_default_params.argtypes = [C.POINTER(Params)]
         L.dem_default_params.restype = None
         L.dem_workspace_bytes.argtypes = [C.POINTER(Scene), C.c_int32, C.POINTER(Params)]

@@ -51,6 +51,38 @@ def build_hierarchy(verts: np.ndarray, tris: np.ndarray, parent: np.ndarray, lev
     return out
 
 
+def build_surrogate_tree(verts: np.ndarray, tris: np.ndarray, **opts) -> dict:
+    """dem_build_surrogate_tree on one mesh (k-means splits, Appendix A
+    surrogates); ``opts`` override dem_tree_opts fields.  Returns numpy
+    copies: verts (mesh then surrogate vertices), tris, parent, level_sizes,
+    fine_order and the levels as a list of triangle arrays."""
+    V = np.ascontiguousarray(verts, np.float64).reshape(-1, 3)
+    T = np.ascontiguousarray(tris, np.int32).reshape(-1, 3)
+    o = _abi.TreeOpts()
+    lib().dem_default_tree_opts(C.byref(o))
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    t = _abi.SurrogateTree()
+    st = lib().dem_build_surrogate_tree(V.ctypes.data_as(C.POINTER(C.c_double)), len(V),
+                                        T.ctypes.data_as(C.POINTER(C.c_int32)), len(T), C.byref(o),
+                                        C.byref(t))
+    check(st, "dem_build_surrogate_tree")
+    try:
+        n = t.n_tris
+        out = {"verts": np.ctypeslib.as_array(t.verts, (t.n_verts, 3)).copy(),
+               "tris": np.ctypeslib.as_array(t.tris, (n, 3)).copy(),
+               "parent": np.ctypeslib.as_array(t.parent, (n,)).copy(),
+               "level_sizes": np.ctypeslib.as_array(t.level_sizes, (t.n_levels,)).copy(),
+               "fine_order": np.ctypeslib.as_array(t.fine_order, (len(T),)).copy()}
+    finally:
+        lib().dem_surrogate_tree_free(C.byref(t))
+    offs = np.cumsum([0] + list(out["level_sizes"]))
+    out["levels"] = [out["tris"][offs[l]:offs[l + 1]] for l in range(len(offs) - 1)]
+    return out
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -91,8 +123,9 @@ class DeviceScene:
             tris = np.concatenate(levels).astype(np.int32)
             parent = np.full(len(tris), -1, np.int32)
             if hier_levels:
+                absolute = getattr(part, "parents_absolute", False)
                 for l in range(1, len(levels)):
-                    parent[offs[l]:offs[l + 1]] = part.parents[l] + offs[l - 1]
+                    parent[offs[l]:offs[l + 1]] = part.parents[l] + (0 if absolute else offs[l - 1])
             h = build_hierarchy(worlds[p], tris, parent, sizes, part.eps0, coord_scale)
             self.max_dev = max(self.max_dev, h["max_dev"])
             n = len(tris)

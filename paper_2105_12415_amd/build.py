@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdem.so")
-SOURCES = ["dem_kernels.hip", "dem_hierarchy.cpp"]
+SOURCES = ["dem_kernels.hip", "dem_hierarchy.cpp", "dem_surrogate.cpp"]
 ARCH = os.environ.get("DEM_OFFLOAD_ARCH", "gfx950")
 
 

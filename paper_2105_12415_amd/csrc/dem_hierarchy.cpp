@@ -69,13 +69,16 @@ dem_status dem_build_hierarchy(const double* verts, int32_t n_verts, const int32
   }
   if (coord_scale == 0.0) coord_scale = maxc;
 
-  // children ranges from the parent links
+  // children ranges from the parent links: a surrogate of level l >= 1 hangs
+  // below level l-1; a fine triangle (last level) below a surrogate of any
+  // level (trees whose leaf sets sit at different depths)
   std::vector<int32_t> cb(n, 0), cc(n, 0);
   for (int l = 1; l < n_levels; ++l) {
+    const int64_t lo = (l == n_levels - 1) ? 0 : lb[l - 1];
     int32_t prev = -1;
     for (int64_t t = lb[l]; t < lb[l + 1]; ++t) {
       int32_t p = parent[t];
-      if (p < lb[l - 1] || p >= lb[l]) return DEM_ERR_NOT_CONSERVATIVE;
+      if (p < lo || p >= lb[l]) return DEM_ERR_NOT_CONSERVATIVE;
       if (p < prev) return DEM_ERR_NOT_CONSERVATIVE;  // children must be grouped by parent
       if (p != prev) {
         if (cc[p] != 0) return DEM_ERR_NOT_CONSERVATIVE;

@@ -134,6 +134,7 @@ class Particle:
     radius: float                    # nominal radius R
     subdiv: List[int]                # icosphere subdivision of each level
     eps0: float = EPS0
+    parents_absolute: bool = False   # parents[l] index all of the particle's triangles, not level l-1
 
     @property
     def n_verts(self) -> int:
@@ -379,6 +380,45 @@ def size_disparate_scene(s_big: int = 7, R_big: float = 20.0, n_small: int = 200
 def big_plus_small() -> Scene:
     """R=20 s=7 sphere (327680 tris) + 2000 R=0.5 s=3 spheres on it, FP32."""
     return size_disparate_scene(name="big_s7_plus_2000_small_s3_f32")
+
+
+# --------------------------------------------------------------------------- generic meshes
+def bumped_torus(rng: np.random.Generator, nu: int, nv: int, R: float, r: float, bump: float = BUMP):
+    """A torus around the z axis (tube radius r + U(-bump, bump) per vertex),
+    triangulated from an nu x nv parameter grid with outward orientation: a
+    closed mesh with no nesting, for surrogate trees built from scratch.
+    Returns (verts (nu*nv, 3) f64, tris (2*nu*nv, 3) int32)."""
+    u = 2 * np.pi * np.arange(nu) / nu
+    v = 2 * np.pi * np.arange(nv) / nv
+    U, Vv = np.meshgrid(u, v, indexing="ij")
+    rr = r + rng.uniform(-bump, bump, size=U.shape)
+    X = (R + rr * np.cos(Vv)) * np.cos(U)
+    Y = (R + rr * np.cos(Vv)) * np.sin(U)
+    Z = rr * np.sin(Vv)
+    verts = np.stack([X, Y, Z], -1).reshape(-1, 3)
+    idx = lambda i, j: (i % nu) * nv + (j % nv)
+    tris = []
+    for i in range(nu):
+        for j in range(nv):
+            a, b, c, d = idx(i, j), idx(i + 1, j), idx(i + 1, j + 1), idx(i, j + 1)
+            tris += [(a, b, c), (a, c, d)]
+    return verts, np.array(tris, np.int32)
+
+
+def two_tori(nu: int = 48, nv: int = 24, R: float = 1.0, r: float = 0.35, gap: float = 0.02,
+             stream_id: int = 6):
+    """Two bumped tori side by side along x, rims ``gap`` apart before the
+    bumps, each with a random rotation about its own axis; meshes only.
+    Returns [(verts, tris, rot, centre), ...]."""
+    rngs = _streams(stream_id, 2)
+    out = []
+    for k in range(2):
+        verts, tris = bumped_torus(rngs[k], nu, nv, R, r)
+        ang = rngs[k].uniform(0, 2 * np.pi)
+        rot = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1.0]])
+        centre = np.array([k * (2 * (R + r) + gap), 0.0, 0.0])
+        out.append((verts, tris, rot, centre))
+    return out
 
 
 # --------------------------------------------------------------------------- motion

@@ -278,6 +278,24 @@ def test_empty_inputs(mode, case):
         assert oracle.find_contacts(oracle.fine_scene(scene))["d"].size == 0
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_generic_mesh_surrogate_trees(prec):
+    """Two bumped tori (a parametric mesh, no nesting) with surrogate trees
+    from the library's k-means builder: leaf sets at different depths, fine
+    triangles below surrogates of several levels.  Hierarchical contacts
+    against the oracle and against the flat path."""
+    from generic_mesh import two_tori_scene
+    scene, _ = two_tori_scene(prec)
+    fs = oracle.fine_scene(scene)
+    ref = oracle.find_contacts(fs)
+    ds, eng, res = run(scene, "hier")
+    assert ds.n_levels_max >= 4 and ds.lazy
+    n, _, _ = compare_sets(scene, ds, res, ref, TOL[prec], fs)
+    assert n > 100
+    _, _, flat = run(scene, "flat")
+    assert set(keyed(ds, flat)) == set(keyed(ds, res))
+
+
 # ------------------------------------------------------------------ gradients
 def _grad_compare(scene, prec):
     tol = TOL[prec]
