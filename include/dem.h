@@ -69,6 +69,7 @@ typedef enum { DEM_MODE_FLAT = 0, DEM_MODE_HIER = 1 } dem_mode;
 #define DEM_DEV_NEAR_OVERFLOW 0x4u    /* near-pair list exceeded near_capacity */
 #define DEM_DEV_NONFINITE 0x8u        /* a non-finite coordinate or distance was met */
 #define DEM_DEV_BAD_TREE 0x10u        /* a child count outside 0..DEM_MAX_CHILDREN */
+#define DEM_DEV_FRONTIER_OVERFLOW 0x20u /* active sets outgrew dem_frontier's capacity or memory set */
 
 #define DEM_MAX_LEVELS 32
 #define DEM_MAX_CHILDREN 16           /* children per surrogate (N_surrogate <= 16) */
@@ -233,6 +234,11 @@ typedef struct {
    * triangle is written every step (always so in FLAT mode). */
   const int32_t* fine_parents;
   int32_t fine_parent_begin[DEM_MAX_LEVELS + 1];
+  /* Needed by dem_frontier_step only (may be NULL for the other calls):
+   * the parent of every triangle (-1 for root triangles) and its depth in its
+   * particle's tree (root triangles 0, children one more than their parent). */
+  const int32_t* tri_parent;  /* [n_tris] */
+  const uint8_t* tri_depth;   /* [n_tris] */
 } dem_scene;
 
 /* ------------------------------------------------------------------ parameters */
@@ -249,6 +255,9 @@ typedef struct {
                              features when the separation bound certifies the distance
                              (FP32: within 4e-6 d + 1e-7 size), else send it to the exact
                              fallback; 0 (default): every near pair takes the exact fallback */
+  int32_t prune_exact;    /* dem_frontier_step: 1 = decide "in range" with the exact comparison-based
+                             distance (Section 3) instead of the iteration's lower bound; 0 (default) =
+                             the iteration, as in dem_find_contacts */
   double energy_k;        /* k of E = k sum max(0, delta - d)^2 (used when dev_energy != NULL) */
   int32_t block;          /* threads per block of the descent / near kernels: 64, 128 or 256 */
   int32_t grid;           /* blocks of the persistent kernels (0 = 2048; default 1024) */
@@ -312,6 +321,9 @@ typedef struct {
   unsigned long long fallback;  /* near pairs sent to the comparison-based distance */
   unsigned long long contacts;  /* contacts found */
   unsigned long long items[DEM_MAX_LEVELS];     /* work items consumed at each depth */
+  unsigned long long frontier_leaves;    /* active pairs evaluated by dem_frontier_step */
+  unsigned long long frontier_unfolded;  /* active pairs replaced by their child pairs (widening) */
+  unsigned long long frontier_collapsed; /* child groups replaced by their parent pair (narrowing) */
 } dem_stats;
 
 /* Bytes of device workspace dem_find_contacts needs for this scene and
@@ -366,6 +378,98 @@ dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* cont
                                 const double* grad_E, void* grad_verts, double* energy_out,
                                 const void* workspace, size_t workspace_bytes,
                                 uint32_t* dev_status, dem_stream_t stream);
+
+/* ------------------------------------------------------------------ frontier */
+
+/*
+ * Persistent active sets (Section 5.3: the multiscale Picard scheme of
+ * Algorithm 6, which keeps an active set per particle pair between Picard
+ * iterations and time steps, unfolds at most one tree level per iteration,
+ * widens and narrows the sets, and vetoes repeated removals with a memory set
+ * U).  Pairwise form, as in dem_find_contacts: the active set of a candidate
+ * particle pair is a set of triangle pairs ("leaves") that covers every pair
+ * of its fine triangles exactly once.
+ *
+ * Leaf record (four int32): {t_i, t_j, flags, info}
+ *   t_i, t_j  global triangle ids (particles pairs[0][k], pairs[1][k]);
+ *   flags     bit 0: the pair is in the memory set (its child pairs were once
+ *             replaced by it); bit d (1..31): the pair's ancestor at depth
+ *             d-1 is in the memory set, so the sibling group at depth d may
+ *             not be narrowed;
+ *   info      bits 0-7 index in the sibling group, 8-16 group size (0 for
+ *             root pairs), 17-21 pair depth D (steps of unfolding from the
+ *             root pair), bit 22/23: side i/j was unfolded to reach depth D.
+ * The leaves of a buffer are in depth-first order: the root pairs of
+ * candidate pair 0 (t_i-major), their descendants in place, then pair 1, ...
+ * so every sibling group whose members are all leaves is contiguous.
+ */
+typedef struct {
+  int64_t capacity;        /* leaves each buffer holds (< 2^32) */
+  int32_t* leaves[2];      /* two device buffers of [capacity][4] leaf records */
+  uint32_t* state;         /* device [4]: {buffer holding the active sets (0/1), leaf count,
+                              leaves the last call needed, 0} */
+  int64_t memory_capacity; /* slots of the memory set: a power of two >= 64 */
+  uint64_t* memory;        /* device [memory_capacity]: hash set of pairs (t_i << 32 | t_j) */
+} dem_frontier;
+
+/* Bytes of device workspace dem_frontier_init / dem_frontier_step need
+ * (triangle soup, near list, per-leaf outcome words, scan partials,
+ * counters).  The step's soup sits where dem_contact_backward reads it, so
+ * the workspace also serves the backward pass of the step's contacts.
+ * 0 on bad input. */
+size_t dem_frontier_workspace_bytes(const dem_scene* scene, int32_t n_pairs, const dem_params* p,
+                                    int64_t frontier_capacity);
+
+/*
+ * dem_frontier_init -- active sets = all root-triangle pairs of every
+ * candidate pair (Algorithm 6, initial statement); clears the memory set.
+ *
+ * pairs      device [2][n_pairs] particle ids, as for dem_find_contacts; a
+ *            leaf's candidate pair is not stored, so the same pairs in the
+ *            same order are expected for as long as the active sets are kept.
+ * p          the parameters the steps will use (NULL = defaults).
+ * f          host struct of device pointers (see dem_frontier).
+ * workspace  >= dem_frontier_workspace_bytes(scene, n_pairs, p, f->capacity).
+ * dev_status device uint32: cleared, then DEM_DEV_FRONTIER_OVERFLOW if the
+ *            root pairs exceed f->capacity (state then holds 0 leaves and
+ *            the number needed).
+ */
+dem_status dem_frontier_init(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
+                             const dem_params* p, const dem_frontier* f, void* workspace,
+                             size_t workspace_bytes, uint32_t* dev_status, dem_stream_t stream);
+
+/*
+ * dem_frontier_step -- one Picard iteration's contact detection on the
+ * active sets at the scene's current positions.
+ *
+ * Every leaf is evaluated once (the iteration's lower bound, or the exact
+ * distance if p->prune_exact):
+ *   - out of range (d > eps_i + eps_j certainly): "no contact";
+ *   - two fine triangles in range: settled by the exact comparison-based
+ *     distance and reported in `out` if d <= eps_i + eps_j (else "no
+ *     contact");
+ *   - a surrogate in range: replaced by its child pairs (only the non-fine
+ *     side unfolds), one level per call (widening).
+ * A sibling group whose members are all leaves and all "no contact" is
+ * replaced by its parent pair, which enters the memory set, unless the
+ * parent already is in it (narrowing with the veto of the memory set).
+ * If nothing widens or narrows, the active sets stay where they are;
+ * otherwise the rewritten sets go to the other buffer and state[0] flips.
+ *
+ * scene      as for dem_find_contacts, with tri_parent and tri_depth set.
+ * p          parameters (mode is ignored); NULL = defaults.
+ * out, dev_energy  as for dem_find_contacts (this call's contacts).
+ * dev_stats  evals[] counts leaves by pair depth; frontier_* counters.
+ * dev_status cleared, then DEM_DEV_* bits.  On DEM_DEV_FRONTIER_OVERFLOW
+ *            the active sets are left unchanged and state[2] holds the
+ *            leaf count the rewrite needed.
+ * The contacts can be differentiated with dem_contact_backward on this
+ * call's workspace.
+ */
+dem_status dem_frontier_step(const dem_scene* scene, const dem_params* p, const dem_frontier* f,
+                             const dem_contacts* out, void* workspace, size_t workspace_bytes,
+                             dem_stats* dev_stats, uint32_t* dev_status, double* dev_energy,
+                             dem_stream_t stream);
 
 const char* dem_status_string(dem_status s);
 

@@ -21,13 +21,15 @@ DEM_DEV_QUEUE_OVERFLOW = 0x2
 DEM_DEV_NEAR_OVERFLOW = 0x4
 DEM_DEV_NONFINITE = 0x8
 DEM_DEV_BAD_TREE = 0x10
+DEM_DEV_FRONTIER_OVERFLOW = 0x20
 DEM_MAX_LEVELS = 32
 DEM_MAX_CHILDREN = 16
 
 # Every exported symbol declared in include/dem.h.
 EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "dem_workspace_bytes",
            "dem_find_contacts", "dem_contact_backward", "dem_status_string", "dem_version",
-           "dem_default_tree_opts", "dem_build_surrogate_tree", "dem_surrogate_tree_free")
+           "dem_default_tree_opts", "dem_build_surrogate_tree", "dem_surrogate_tree_free",
+           "dem_frontier_workspace_bytes", "dem_frontier_init", "dem_frontier_step")
 
 
 class BuildOpts(C.Structure):
@@ -63,14 +65,15 @@ class Scene(C.Structure):
                 ("child_count", C.c_void_p), ("tri_particle", C.c_void_p), ("tri_eps", C.c_void_p),
                 ("root_begin", C.c_void_p), ("root_count", C.c_void_p),
                 ("fine_begin", C.c_void_p), ("fine_count", C.c_void_p), ("pose", C.c_void_p),
-                ("fine_parents", C.c_void_p), ("fine_parent_begin", C.c_int32 * (DEM_MAX_LEVELS + 1))]
+                ("fine_parents", C.c_void_p), ("fine_parent_begin", C.c_int32 * (DEM_MAX_LEVELS + 1)),
+                ("tri_parent", C.c_void_p), ("tri_depth", C.c_void_p)]
 
 
 class Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_iter", C.c_int32), ("omega", C.c_float),
                 ("alpha_reg_rel", C.c_float), ("alpha_it_ratio", C.c_float),
                 ("init_centroid", C.c_int32), ("dense_distance", C.c_int32), ("certify", C.c_int32),
-                ("energy_k", C.c_double), ("block", C.c_int32), ("grid", C.c_int32),
+                ("prune_exact", C.c_int32), ("energy_k", C.c_double), ("block", C.c_int32), ("grid", C.c_int32),
                 ("batch_items", C.c_int32), ("flat_tile_i", C.c_int32), ("flat_tile_j", C.c_int32),
                 ("seed_chunk", C.c_int32),
                 ("level_grid", C.c_int32 * DEM_MAX_LEVELS), ("level_batch", C.c_int32 * DEM_MAX_LEVELS),
@@ -87,7 +90,14 @@ class Contacts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("evals", C.c_uint64 * DEM_MAX_LEVELS), ("survivors", C.c_uint64 * DEM_MAX_LEVELS),
                 ("near", C.c_uint64), ("certified", C.c_uint64), ("fallback", C.c_uint64),
-                ("contacts", C.c_uint64), ("items", C.c_uint64 * DEM_MAX_LEVELS)]
+                ("contacts", C.c_uint64), ("items", C.c_uint64 * DEM_MAX_LEVELS),
+                ("frontier_leaves", C.c_uint64), ("frontier_unfolded", C.c_uint64),
+                ("frontier_collapsed", C.c_uint64)]
+
+
+class Frontier(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("leaves", C.c_void_p * 2), ("state", C.c_void_p),
+                ("memory_capacity", C.c_int64), ("memory", C.c_void_p)]
 
 
 STATS_WORDS = C.sizeof(Stats) // 8
@@ -130,6 +140,14 @@ def lib():
         L.dem_contact_backward.argtypes = [C.POINTER(Scene), C.POINTER(Contacts), C.c_double, vp, vp,
                                            vp, vp, C.c_size_t, vp, vp]
         L.dem_contact_backward.restype = C.c_int
+        L.dem_frontier_workspace_bytes.argtypes = [C.POINTER(Scene), C.c_int32, C.POINTER(Params), C.c_int64]
+        L.dem_frontier_workspace_bytes.restype = C.c_size_t
+        L.dem_frontier_init.argtypes = [C.POINTER(Scene), vp, C.c_int32, C.POINTER(Params), C.POINTER(Frontier),
+                                        vp, C.c_size_t, vp, vp]
+        L.dem_frontier_init.restype = C.c_int
+        L.dem_frontier_step.argtypes = [C.POINTER(Scene), C.POINTER(Params), C.POINTER(Frontier),
+                                        C.POINTER(Contacts), vp, C.c_size_t, vp, vp, vp, vp]
+        L.dem_frontier_step.restype = C.c_int
         L.dem_status_string.argtypes = [C.c_int]
         L.dem_status_string.restype = C.c_char_p
         L.dem_version.argtypes = []

@@ -103,7 +103,7 @@ class DeviceScene:
     """
 
     def __init__(self, scene, device="cuda", coord_scale: Optional[float] = None,
-                 hier_levels: bool = True, lazy: bool = True):
+                 hier_levels: bool = True, lazy: bool = True, rel_slack: float = 1e-6):
         self.scene = scene
         self.device = torch.device(device)
         self.precision = _abi.DEM_F64 if scene.dtype == "f64" else _abi.DEM_F32
@@ -112,6 +112,7 @@ class DeviceScene:
         if coord_scale is None:
             coord_scale = 1.25 * max(float(np.abs(w).max()) for w in worlds) + 1.0
         tv, cb, cc, tp, ep, rb, rc, fb, fc, vb = [], [], [], [], [], [], [], [], [], []
+        tpar, tdep = [], []  # parent (global id, -1 for roots) and tree depth of every triangle
         fine_par = {}  # depth -> global ids of surrogates whose children are fine
         nv = nt = 0
         n_levels_max = 1
@@ -126,7 +127,12 @@ class DeviceScene:
                 absolute = getattr(part, "parents_absolute", False)
                 for l in range(1, len(levels)):
                     parent[offs[l]:offs[l + 1]] = part.parents[l] + (0 if absolute else offs[l - 1])
-            h = build_hierarchy(worlds[p], tris, parent, sizes, part.eps0, coord_scale)
+            h = build_hierarchy(worlds[p], tris, parent, sizes, part.eps0, coord_scale, rel_slack)
+            depth = np.zeros(len(tris), np.int64)
+            for l in range(1, len(levels)):
+                depth[offs[l]:offs[l + 1]] = depth[parent[offs[l]:offs[l + 1]]] + 1
+            tpar.append(np.where(parent >= 0, parent + nt, -1))
+            tdep.append(depth)
             self.max_dev = max(self.max_dev, h["max_dev"])
             n = len(tris)
             tv.append(h["tri_verts"] + nv)
@@ -157,6 +163,10 @@ class DeviceScene:
         self.child_begin = i32(np.concatenate(cb))
         self.child_count = i32(np.concatenate(cc))
         self.tri_particle = i32(np.concatenate(tp))
+        self.tri_parent_host = np.concatenate(tpar).astype(np.int32)
+        self.tri_depth_host = np.concatenate(tdep).astype(np.uint8)
+        self.tri_parent = i32(self.tri_parent_host)
+        self.tri_depth = torch.as_tensor(self.tri_depth_host, device=d)
         self.tri_eps = torch.as_tensor(np.concatenate(ep), dtype=self.dtype, device=d)
         self.root_begin, self.root_count = i32(rb), i32(rc)
         self.fine_begin_host = np.array(fb, np.int64)
@@ -195,6 +205,8 @@ class DeviceScene:
         s.root_begin, s.root_count = self.root_begin.data_ptr(), self.root_count.data_ptr()
         s.fine_begin, s.fine_count = self.fine_begin.data_ptr(), self.fine_count.data_ptr()
         s.pose = None if self.pose is None else self.pose.data_ptr()
+        s.tri_parent = self.tri_parent.data_ptr()
+        s.tri_depth = self.tri_depth.data_ptr()
         if self.lazy and len(self.fine_parents):
             s.fine_parents = self.fine_parents.data_ptr()
             for d, v in enumerate(self.fine_parent_begin_host):
@@ -385,11 +397,7 @@ class ContactEngine:
         raise DemError("capacities kept overflowing")
 
     def stats_dict(self) -> dict:
-        s = self.stats.cpu().numpy().view(np.uint64)
-        L = _abi.DEM_MAX_LEVELS
-        return {"evals": s[0:L].astype(np.int64), "survivors": s[L:2 * L].astype(np.int64),
-                "near": int(s[2 * L]), "certified": int(s[2 * L + 1]), "fallback": int(s[2 * L + 2]),
-                "contacts": int(s[2 * L + 3]), "items": s[2 * L + 4:3 * L + 4].astype(np.int64)}
+        return _stats_dict(self.stats)
 
     def result(self) -> dict:
         """Host copy of the contacts (after run())."""
@@ -399,6 +407,166 @@ class ContactEngine:
                 "ti": c.ti[:n].cpu().numpy(), "tj": c.tj[:n].cpu().numpy(),
                 "d": c.d[:n].double().cpu().numpy(), "x": c.x[:, :n].double().cpu().numpy().T,
                 "n": c.n[:, :n].double().cpu().numpy().T, "energy": float(self.energy.item())}
+
+
+def _stats_dict(stats: torch.Tensor) -> dict:
+    s = stats.cpu().numpy().view(np.uint64)
+    L = _abi.DEM_MAX_LEVELS
+    return {"evals": s[0:L].astype(np.int64), "survivors": s[L:2 * L].astype(np.int64),
+            "near": int(s[2 * L]), "certified": int(s[2 * L + 1]), "fallback": int(s[2 * L + 2]),
+            "contacts": int(s[2 * L + 3]), "items": s[2 * L + 4:3 * L + 4].astype(np.int64),
+            "frontier_leaves": int(s[3 * L + 4]), "frontier_unfolded": int(s[3 * L + 5]),
+            "frontier_collapsed": int(s[3 * L + 6])}
+
+
+class FrontierEngine:
+    """Persistent active sets for one scene: dem_frontier_init once, then
+    dem_frontier_step per Picard iteration or time step (Algorithm 6).
+
+    Buffers (two leaf buffers, the device state word, the memory set, the
+    contacts and the workspace) are allocated here with torch; ``step()``
+    enqueues one call on the current stream without synchronising.
+    """
+
+    def __init__(self, ds: DeviceScene, params: Optional[_abi.Params] = None,
+                 capacity: Optional[int] = None, memory_capacity: Optional[int] = None,
+                 contact_capacity: Optional[int] = None, energy_k: float = 1e4):
+        self.ds = ds
+        self.p = params if params is not None else make_params("hier")
+        self.p.energy_k = float(energy_k)
+        dev = ds.device
+        rc = ds.root_count_host
+        P = ds.pairs_host
+        self.n_roots = int(np.sum(rc[P[:, 0]] * rc[P[:, 1]])) if len(P) else 0
+        cap = int(capacity) if capacity is not None else max(1 << 16, 64 * self.n_roots)
+        mem = int(memory_capacity) if memory_capacity is not None else max(1 << 12, cap // 2)
+        self.memory_capacity = 1 << (max(64, mem) - 1).bit_length()
+        self.memory = torch.empty(self.memory_capacity, dtype=torch.int64, device=dev)
+        self.state = torch.zeros(4, dtype=torch.int32, device=dev)
+        self._alloc_leaves(cap)
+        if contact_capacity is None:
+            contact_capacity = max(1 << 16, 64 * ds.n_pairs)
+        self.contacts = ContactBuffers.alloc(contact_capacity, ds.dtype, dev)
+        self.stats = torch.zeros(_abi.STATS_WORDS, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.energy = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.energy_bwd = torch.zeros(1, dtype=torch.float64, device=dev)
+        self._alloc_ws()
+
+    def _alloc_leaves(self, cap: int):
+        self.capacity = int(cap)
+        self.leaf_bufs = [torch.zeros(self.capacity, 4, dtype=torch.int32, device=self.ds.device)
+                          for _ in range(2)]
+
+    def _alloc_ws(self):
+        nbytes = lib().dem_frontier_workspace_bytes(C.byref(self.ds.c), self.ds.n_pairs, C.byref(self.p),
+                                                    self.capacity)
+        if nbytes == 0:
+            raise DemError("dem_frontier_workspace_bytes rejected the scene or parameters")
+        self.ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.ds.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = self.ws.data_ptr() + off
+        self.ws_bytes = int(nbytes)
+
+    def c(self) -> _abi.Frontier:
+        f = _abi.Frontier()
+        f.capacity = self.capacity
+        f.leaves[0] = self.leaf_bufs[0].data_ptr()
+        f.leaves[1] = self.leaf_bufs[1].data_ptr()
+        f.state = self.state.data_ptr()
+        f.memory_capacity = self.memory_capacity
+        f.memory = self.memory.data_ptr()
+        return f
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.ds.device).cuda_stream)
+
+    def init(self):
+        f = self.c()
+        st = lib().dem_frontier_init(C.byref(self.ds.c), _ptr(self.ds.pairs), self.ds.n_pairs, C.byref(self.p),
+                                     C.byref(f), C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.status),
+                                     self._stream())
+        check(st, "dem_frontier_init")
+        if self.check() & _abi.DEM_DEV_FRONTIER_OVERFLOW:
+            need = int(self.state_host()[2])
+            self._alloc_leaves(max(2 * self.capacity, int(1.25 * need) + 1024))
+            self._alloc_ws()
+            return self.init()
+
+    def step(self, with_energy: bool = True):
+        f = self.c()
+        cs = self.contacts.c()
+        st = lib().dem_frontier_step(C.byref(self.ds.c), C.byref(self.p), C.byref(f), C.byref(cs),
+                                     C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.stats), _ptr(self.status),
+                                     _ptr(self.energy) if with_energy else None, self._stream())
+        check(st, "dem_frontier_step")
+
+    def backward(self, grad_verts: torch.Tensor, grad_E: Optional[torch.Tensor] = None, energy: bool = False):
+        """dem_contact_backward on the last step's contacts."""
+        assert grad_verts.shape == (3, self.ds.n_verts) and grad_verts.dtype == self.ds.dtype
+        cs = self.contacts.c()
+        st = lib().dem_contact_backward(C.byref(self.ds.c), C.byref(cs), float(self.p.energy_k),
+                                        _ptr(grad_E), _ptr(grad_verts),
+                                        _ptr(self.energy_bwd) if energy else None,
+                                        C.c_void_p(self.ws_ptr), self.ws_bytes, _ptr(self.status),
+                                        self._stream())
+        check(st, "dem_contact_backward")
+
+    # ---------------------------------------------------------- host-side reads
+    def check(self) -> int:
+        torch.cuda.synchronize(self.ds.device)
+        return int(self.status.item()) & 0xFFFFFFFF
+
+    def state_host(self) -> np.ndarray:
+        return self.state.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+
+    def leaves(self) -> np.ndarray:
+        """(n, 4) int64 leaf records {t_i, t_j, flags, info} of the current sets."""
+        cur, n = (int(v) for v in self.state_host()[:2])
+        return self.leaf_bufs[cur][:n].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+
+    def count(self) -> int:
+        return int(self.contacts.count.item()) & 0xFFFFFFFF
+
+    def run_step(self, with_energy: bool = True, max_retries: int = 6) -> int:
+        """step() + synchronise; on overflow the sets are unchanged, so the
+        capacities grow and the same step runs again."""
+        for _ in range(max_retries):
+            self.step(with_energy)
+            status = self.check()
+            if status & _abi.DEM_DEV_NONFINITE:
+                raise DemError("non-finite coordinates or distances")
+            if status & _abi.DEM_DEV_BAD_TREE:
+                raise DemError("malformed surrogate tree (child counts)")
+            over = (_abi.DEM_DEV_CONTACT_OVERFLOW | _abi.DEM_DEV_NEAR_OVERFLOW | _abi.DEM_DEV_FRONTIER_OVERFLOW)
+            if not status & over:
+                return status
+            if status & _abi.DEM_DEV_CONTACT_OVERFLOW:
+                self.contacts = ContactBuffers.alloc(int(self.count() * 1.25) + 1024, self.ds.dtype, self.ds.device)
+            if status & _abi.DEM_DEV_NEAR_OVERFLOW:
+                self.p.near_capacity = 2 * int(self.p.near_capacity)
+            if status & _abi.DEM_DEV_FRONTIER_OVERFLOW:
+                need = int(self.state_host()[2])
+                if need <= self.capacity:
+                    raise DemError("frontier memory set is full: initialise again with a larger memory_capacity")
+                old = self.leaves()
+                self._alloc_leaves(max(2 * self.capacity, int(1.25 * need) + 1024))
+                self.leaf_bufs[0][:len(old)] = torch.as_tensor(old.astype(np.int64).astype(np.uint32).view(np.int32),
+                                                               device=self.ds.device)
+                self.state.copy_(torch.tensor([0, len(old), len(old), 0], dtype=torch.int32))
+            self.ws = None
+            self._alloc_ws()
+        raise DemError("capacities kept overflowing")
+
+    def stats_dict(self) -> dict:
+        return _stats_dict(self.stats)
+
+    def result(self) -> dict:
+        n = min(self.count(), self.contacts.capacity)
+        c = self.contacts
+        return {"pi": c.pi[:n].cpu().numpy(), "pj": c.pj[:n].cpu().numpy(),
+                "ti": c.ti[:n].cpu().numpy(), "tj": c.tj[:n].cpu().numpy(),
+                "d": c.d[:n].double().cpu().numpy(), "energy": float(self.energy.item())}
 
 
 class DemContactEnergy(torch.autograd.Function):

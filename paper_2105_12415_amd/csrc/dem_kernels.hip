@@ -57,7 +57,10 @@ struct Counters {
   uint32_t tail[DEM_MAX_LEVELS + 1][kSeg];  // level queues
   uint32_t near_tail[kSeg];                 // fine pairs not pruned
   uint32_t fb_tail[kSeg];                   // pairs the certificate could not settle
-  uint32_t pad[16];
+  uint32_t fr_unfold;                       // frontier step: leaves that widen
+  uint32_t fr_collapse;                     // frontier step: sibling groups that narrow
+  uint32_t fr_skip;                         // frontier step: leave the active sets as they are
+  uint32_t pad[13];
 };
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -422,6 +425,9 @@ __device__ __forceinline__ size_t seg_index(const SegView& v, uint32_t i, int64_
 constexpr int kStageNear = 512;
 constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between checks
 
+// Outcome of a frontier leaf in a step (byte 0 of its outcome word).
+constexpr uint32_t kOutPrune = 0, kOutKeep = 1, kOutUnfold = 2, kOutNear = 3;
+
 // Descent over one tree depth.  Work items are products of two triangle
 // ranges (the children of a surviving surrogate pair, or a chunk of the
 // roots); lanes take one child pair each, located through a block-wide scan
@@ -638,6 +644,12 @@ struct NearArgs {
   dem_stats* stats;
   uint32_t* status;
   IterParams ip;
+  // frontier step: list entries are leaf indices; the leaves live in
+  // fr_buf[fr_state[0]] and each settled leaf's outcome byte is written
+  const int4* fr_buf0;
+  const int4* fr_buf1;
+  const uint32_t* fr_state;
+  uint8_t* fr_meta;
 };
 
 template <typename T>
@@ -690,7 +702,9 @@ struct CertTol<double> {
 // contacts, d <= eps_i + eps_j.  CERTIFY: the iterate + snap + certificate
 // of certify_pair(); pairs it cannot settle go to the fallback list.
 // Otherwise: the exact comparison-based distance for every listed pair.
-template <typename T, int N, bool CERTIFY>
+// FR: entries are frontier leaf indices (see k_fr_eval); the leaf's outcome
+// becomes "contact" or "no contact".
+template <typename T, int N, bool CERTIFY, bool FR>
 __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
   __shared__ LdsQueue<ContactRec<T>, kStageContacts> qc;
   __shared__ LdsQueue<int2, kStageNear> qf;
@@ -714,9 +728,15 @@ __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ sou
     int2 pr = make_int2(0, 0);
     if (e < fill) {
       pr = seg[e];
+      int ta = pr.x, tb = pr.y;
+      if constexpr (FR) {
+        const int4 lf = (a.fr_state[0] ? a.fr_buf1 : a.fr_buf0)[pr.x];
+        ta = lf.x;
+        tb = lf.y;
+      }
       int cbi, cci, cbj, ccj, pi_, pj_;
-      Tri<T> A = load_tri(soup, pr.x, cbi, cci, pi_);
-      Tri<T> B = load_tri(soup, pr.y, cbj, ccj, pj_);
+      Tri<T> A = load_tri(soup, ta, cbi, cci, pi_);
+      Tri<T> B = load_tri(soup, tb, cbj, ccj, pj_);
       V3<T> D0 = A.v0 - B.v0;
       T d;
       V3<T> cp, cq;
@@ -745,7 +765,8 @@ __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ sou
         V3<T> xl = fma3(lam, w, cp);
         V3<T> nc = cp - xl;
         V3<T> xc = xl + A.v0;
-        rec.pi = pi_; rec.pj = pj_; rec.ti = pr.x; rec.tj = pr.y; rec.d = d;
+        rec.pi = pi_; rec.pj = pj_; rec.ti = ta; rec.tj = tb; rec.d = d;
+        if constexpr (FR) a.fr_meta[4 * (size_t)pr.x] = (uint8_t)(emit ? kOutKeep : kOutPrune);
         rec.x[0] = xc.x; rec.x[1] = xc.y; rec.x[2] = xc.z;
         rec.n[0] = nc.x; rec.n[1] = nc.y; rec.n[2] = nc.z;
         if (emit && !a.dense) {
@@ -891,6 +912,420 @@ __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__
   }
 }
 
+// ------------------------------------------------------------------ frontier
+// Persistent active sets (Section 5.3, Algorithm 6 in pairwise form; the
+// leaf record and buffer layout are described with dem_frontier in dem.h).
+//
+// One dem_frontier_step:
+//   k_fr_eval   every leaf: in range or not (lower bound, or exact distance);
+//               fine pairs in range go to the near list; per-leaf outcome
+//               word (meta) = outcome | group index << 8 | n << 16 with n =
+//               the group size at a group's first leaf that may narrow, or
+//               the child-pair count of a leaf that widens
+//   k_near<FR>  exact distance of the fine pairs, contacts, outcome byte
+//   k_fr_group  a group's first leaf checks that its n members follow it in
+//               order, all leaves and all "no contact"; marks them (cm)
+//   k_fr_count  output leaves per block of a contiguous leaf range
+//   k_fr_scan   block offsets (one block)
+//   k_fr_emit   rewrite in depth-first order into the other buffer: copies,
+//               parents of narrowed groups (inserted into the memory set),
+//               child pairs of widened leaves (memory set looked up)
+//   k_fr_finish switch buffers when something changed
+constexpr unsigned long long kMemEmpty = ~0ull;
+constexpr int kScanThreads = 1024;
+constexpr int kFrBlock = 256;
+constexpr int kMemProbes = 64;
+
+__device__ __forceinline__ uint32_t fr_depth(uint32_t info) { return (info >> 17) & 31u; }
+__device__ __forceinline__ uint32_t fr_gidx(uint32_t info) { return info & 255u; }
+__device__ __forceinline__ uint32_t fr_gsize(uint32_t info) { return (info >> 8) & 511u; }
+__device__ __forceinline__ uint32_t fr_info(uint32_t g, uint32_t n, uint32_t D, uint32_t si, uint32_t sj) {
+  return g | (n << 8) | (D << 17) | (si << 22) | (sj << 23);
+}
+
+struct FrontierArgs {
+  int4* buf0;
+  int4* buf1;
+  uint32_t* state;              // {current buffer, leaf count, leaves needed, 0}
+  int64_t cap;
+  unsigned long long* mem;      // memory set (open addressing)
+  uint64_t mem_mask;
+  uint32_t* meta;               // [cap] per-leaf outcome word
+  uint8_t* cm;                  // [cap] narrowing marks: 2 = group's first leaf, 1 = other member
+  unsigned long long* part;     // [grid + 1] output leaves per block -> offsets
+  const int32_t* tri_parent;
+  const uint8_t* tri_depth;
+  const int32_t* cbeg;
+  const int32_t* ccnt;
+  int n_tris;
+  Counters* ctr;
+  int2* near_;
+  uint32_t* near_tail;
+  int64_t ncap;
+  dem_stats* stats;
+  uint32_t* status;
+  IterParams ip;
+};
+
+__device__ __forceinline__ uint32_t fr_count(const FrontierArgs& a) {
+  return (uint32_t)min((uint64_t)a.state[1], (uint64_t)a.cap);
+}
+
+__device__ __forceinline__ unsigned long long mem_key(int ta, int tb) {
+  return ((unsigned long long)(uint32_t)ta << 32) | (uint32_t)tb;
+}
+
+__device__ __forceinline__ uint64_t mem_slot(unsigned long long key, uint64_t mask) {
+  return (uint64_t)((key * 0x9E3779B97F4A7C15ull) >> 29) & mask;
+}
+
+// Slots are never cleared within a run of steps, so a probe chain up to a
+// stored key holds no empty slot: a lookup may stop at the first empty one.
+__device__ bool mem_contains(const FrontierArgs& a, unsigned long long key) {
+  uint64_t h = mem_slot(key, a.mem_mask);
+  for (int k = 0; k < kMemProbes; ++k) {
+    const unsigned long long v = a.mem[h];
+    if (v == key) return true;
+    if (v == kMemEmpty) return false;
+    h = (h + 1) & a.mem_mask;
+  }
+  atomicOr(a.status, DEM_DEV_FRONTIER_OVERFLOW);
+  return false;
+}
+
+__device__ void mem_insert(const FrontierArgs& a, unsigned long long key) {
+  uint64_t h = mem_slot(key, a.mem_mask);
+  for (int k = 0; k < kMemProbes; ++k) {
+    const unsigned long long v = atomicCAS(&a.mem[h], kMemEmpty, key);
+    if (v == kMemEmpty || v == key) return;
+    h = (h + 1) & a.mem_mask;
+  }
+  atomicOr(a.status, DEM_DEV_FRONTIER_OVERFLOW);
+}
+
+// Exclusive prefix sums of v[0..n) in place, total to v[n]; one block of
+// kScanThreads threads, each summing a contiguous slice first.
+__device__ void block_scan_u64(unsigned long long* v, uint32_t n) {
+  __shared__ unsigned long long wsum[kScanThreads / kWave];
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t lo = min(threadIdx.x * per, n), hi = min(lo + per, n);
+  unsigned long long s = 0;
+  for (uint32_t k = lo; k < hi; ++k) s += v[k];
+  const int lane = lane_id(), wid = threadIdx.x / kWave;
+  unsigned long long x = s;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    unsigned long long y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long acc = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+      unsigned long long t = wsum[w];
+      wsum[w] = acc;
+      acc += t;
+    }
+    v[n] = acc;
+  }
+  __syncthreads();
+  unsigned long long run = x - s + wsum[wid];
+  for (uint32_t k = lo; k < hi; ++k) {
+    unsigned long long t = v[k];
+    v[k] = run;
+    run += t;
+  }
+}
+
+// Contiguous leaf range of block b (a multiple of blockDim), so that the
+// output keeps the depth-first order.
+__device__ __forceinline__ void fr_range(uint32_t n, uint32_t& lo, uint32_t& hi) {
+  const uint32_t G = gridDim.x, B = blockDim.x;
+  const uint32_t per = ((n + G - 1) / G + B - 1) / B * B;
+  lo = min((uint64_t)blockIdx.x * per, (uint64_t)n);
+  hi = min((uint64_t)lo + per, (uint64_t)n);
+}
+
+template <typename T, int N, bool EXACT>
+__global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restrict__ soup, FrontierArgs a) {
+  __shared__ LdsQueue<int2, kStageNear> qn;
+  __shared__ uint32_t hist[DEM_MAX_LEVELS];
+  const uint32_t n = fr_count(a);
+  const int4* __restrict__ lin = a.state[0] ? a.buf1 : a.buf0;
+  if (threadIdx.x == 0) qn.n = 0;
+  if (threadIdx.x < DEM_MAX_LEVELS) hist[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.state[2] = n;
+  __syncthreads();
+  uint32_t my_unf = 0, my_near = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint32_t i = base + threadIdx.x;
+    bool near = false;
+    const int4 lf = i < n ? lin[i] : make_int4(0, 0, 0, 0);
+    const bool valid = (uint32_t)lf.x < (uint32_t)a.n_tris && (uint32_t)lf.y < (uint32_t)a.n_tris;
+    if (i < n && !valid) {
+      atomicOr(a.status, DEM_DEV_BAD_TREE);  // not a leaf this library wrote: the sets stay as they are
+      a.meta[i] = kOutKeep;
+      a.cm[i] = 0;
+    }
+    if (i < n && valid) {
+      int cbi, cci, pi_, cbj, ccj, pj_;
+      Tri<T> A = load_tri(soup, lf.x, cbi, cci, pi_);
+      Tri<T> B = load_tri(soup, lf.y, cbj, ccj, pj_);
+      V3<T> D0 = A.v0 - B.v0;
+      const T delta = A.eps + B.eps;
+      bool keep;
+      if constexpr (EXACT) {
+        Closest<T> c;
+        exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, c);
+        keep = !(sq_(c.d2) > delta);
+      } else {
+        const T L = iterate_bound<T, N>(A, B, D0, a.ip);
+        keep = !(L > delta + bound_slack(A, B, D0, delta));
+      }
+      const uint32_t info = (uint32_t)lf.w, flags = (uint32_t)lf.z;
+      const uint32_t D = fr_depth(info), g = fr_gidx(info), gn = fr_gsize(info);
+      // first leaf of a group that may narrow (not vetoed by the memory set)
+      const uint32_t head = (D >= 1 && g == 0 && gn >= 1 && !((flags >> D) & 1u)) ? gn : 0u;
+      uint32_t out, nn;
+      if (!keep) {
+        out = kOutPrune; nn = head;
+      } else if (cci == 0 && ccj == 0) {
+        out = kOutNear; nn = head;  // settled by k_near
+      } else {
+        out = kOutUnfold; nn = (uint32_t)(cci ? cci : 1) * (uint32_t)(ccj ? ccj : 1);
+      }
+      a.meta[i] = out | (g << 8) | (nn << 16);
+      a.cm[i] = 0;
+      near = out == kOutNear;
+      my_unf += out == kOutUnfold;
+      my_near += near;
+      atomicAdd(&hist[D], 1u);
+    }
+    lds_append(near, make_int2((int)i, 0), qn.buf, &qn.n);
+    __syncthreads();
+    if (qn.n + blockDim.x > (uint32_t)kStageNear)
+      lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+  }
+  __syncthreads();
+  lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    my_unf += __shfl_xor(my_unf, o);
+    my_near += __shfl_xor(my_near, o);
+  }
+  if (lane_id() == 0) {
+    if (my_unf) atomicAdd(&a.ctr->fr_unfold, my_unf);
+    if (a.stats && my_near) atomicAdd(&a.stats->near, (unsigned long long)my_near);
+  }
+  if (a.stats && threadIdx.x < DEM_MAX_LEVELS && hist[threadIdx.x])
+    atomicAdd(&a.stats->evals[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
+  if (a.stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats->frontier_leaves, (unsigned long long)n);
+}
+
+// Narrowing: a group's first leaf checks its n - 1 followers.  In depth-first
+// order a member that is not a leaf is followed by its own first descendant
+// leaf, whose group index is 0, so the check fails exactly when some member
+// is not a leaf or not "no contact".
+__global__ void __launch_bounds__(kFrBlock) k_fr_group(FrontierArgs a) {
+  const uint32_t n = fr_count(a);
+  uint32_t my = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t m = a.meta[i];
+    const uint32_t gn = m >> 16;
+    if ((m & 255u) != kOutPrune || gn == 0 || ((m >> 8) & 255u) != 0) continue;
+    if ((uint64_t)i + gn > n) continue;
+    bool all = true;
+    for (uint32_t j = 1; j < gn && all; ++j) {
+      const uint32_t mj = a.meta[i + j];
+      all = (mj & 255u) == kOutPrune && ((mj >> 8) & 255u) == j;
+    }
+    if (!all) continue;
+    a.cm[i] = 2;
+    for (uint32_t j = 1; j < gn; ++j) a.cm[i + j] = 1;
+    ++my;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) my += __shfl_xor(my, o);
+  if (lane_id() == 0 && my) atomicAdd(&a.ctr->fr_collapse, my);
+}
+
+__device__ __forceinline__ bool fr_skip(const FrontierArgs& a) {
+  constexpr uint32_t bad = DEM_DEV_NEAR_OVERFLOW | DEM_DEV_CONTACT_OVERFLOW | DEM_DEV_NONFINITE |
+                           DEM_DEV_BAD_TREE | DEM_DEV_FRONTIER_OVERFLOW;
+  return (a.ctr->fr_unfold == 0 && a.ctr->fr_collapse == 0) || (*a.status & bad) || a.ctr->fr_skip;
+}
+
+__device__ __forceinline__ uint32_t fr_out_count(uint32_t m, uint8_t c) {
+  if (c == 2) return 1;
+  if (c == 1) return 0;
+  return (m & 255u) == kOutUnfold ? (m >> 16) : 1u;
+}
+
+__global__ void __launch_bounds__(kFrBlock) k_fr_count(FrontierArgs a) {
+  __shared__ unsigned long long wsum[kFrBlock / kWave];
+  if (fr_skip(a)) return;
+  uint32_t lo, hi;
+  fr_range(fr_count(a), lo, hi);
+  unsigned long long s = 0;
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += fr_out_count(a.meta[i], a.cm[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane_id() == 0) wsum[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += wsum[w];
+    a.part[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_fr_scan(FrontierArgs a, uint32_t n_blocks) {
+  if (fr_skip(a)) return;
+  block_scan_u64(a.part, n_blocks);
+  if (threadIdx.x == 0) {
+    const unsigned long long total = a.part[n_blocks];
+    a.state[2] = (uint32_t)min(total, 0xFFFFFFFFull);
+    if (total > (unsigned long long)a.cap) {
+      atomicOr(a.status, DEM_DEV_FRONTIER_OVERFLOW);
+      a.ctr->fr_skip = 1;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kFrBlock) k_fr_emit(FrontierArgs a) {
+  __shared__ int4 lf_s[kFrBlock];
+  __shared__ uint32_t m_s[kFrBlock];
+  __shared__ uint8_t c_s[kFrBlock];
+  __shared__ int offs[kFrBlock + 1];
+  __shared__ int wsum[kFrBlock / kWave];
+  __shared__ int skip;
+  // one decision per block: the status word may gain a memory-set overflow
+  // bit from other blocks while this kernel runs
+  if (threadIdx.x == 0) skip = fr_skip(a);
+  __syncthreads();
+  if (skip) return;
+  const uint32_t cur = a.state[0];
+  const int4* __restrict__ lin = cur ? a.buf1 : a.buf0;
+  int4* __restrict__ lout = cur ? a.buf0 : a.buf1;
+  uint32_t lo, hi;
+  fr_range(fr_count(a), lo, hi);
+  unsigned long long obase = a.part[blockIdx.x];
+  const int B = blockDim.x;
+  for (uint32_t t0 = lo; t0 < hi; t0 += B) {
+    const uint32_t i = t0 + threadIdx.x;
+    int c = 0;
+    if (i < hi) {
+      lf_s[threadIdx.x] = lin[i];
+      m_s[threadIdx.x] = a.meta[i];
+      c_s[threadIdx.x] = a.cm[i];
+      c = (int)fr_out_count(m_s[threadIdx.x], c_s[threadIdx.x]);
+    }
+    block_scan(c, offs, wsum, B);
+    const int total = offs[B];
+    for (int e = threadIdx.x; e < total; e += B) {
+      // owner: last k with offs[k] <= e (zero-count entries before it share offsets)
+      int lo2 = 0, hi2 = B - 1;
+      while (lo2 < hi2) {
+        int mid = (lo2 + hi2 + 1) >> 1;
+        if (offs[mid] <= e) lo2 = mid; else hi2 = mid - 1;
+      }
+      const int4 lf = lf_s[lo2];
+      const uint32_t m = m_s[lo2];
+      const uint32_t l = (uint32_t)(e - offs[lo2]);
+      const uint32_t flags = (uint32_t)lf.z, info = (uint32_t)lf.w;
+      const uint32_t D = fr_depth(info);
+      int4 r = lf;
+      if (c_s[lo2] == 2) {
+        // narrowing: the group's parent pair, now in the memory set
+        const int pa = (info >> 22) & 1u ? a.tri_parent[lf.x] : lf.x;
+        const int pb = (info >> 23) & 1u ? a.tri_parent[lf.y] : lf.y;
+        const uint32_t D1 = D - 1;
+        uint32_t ninfo = 0;
+        if (D1 > 0) {
+          const uint32_t sa = a.tri_depth[pa] == D1, sb = a.tri_depth[pb] == D1;
+          const int ppa = sa ? a.tri_parent[pa] : pa, ppb = sb ? a.tri_parent[pb] : pb;
+          const uint32_t na = sa ? (uint32_t)a.ccnt[ppa] : 1u, nb = sb ? (uint32_t)a.ccnt[ppb] : 1u;
+          const uint32_t ia = sa ? (uint32_t)(pa - a.cbeg[ppa]) : 0u, ib = sb ? (uint32_t)(pb - a.cbeg[ppb]) : 0u;
+          ninfo = fr_info(ia * nb + ib, na * nb, D1, sa, sb);
+        }
+        mem_insert(a, mem_key(pa, pb));
+        r = make_int4(pa, pb, (int)((flags & ((1u << D) - 1u)) | 1u), (int)ninfo);
+      } else if ((m & 255u) == kOutUnfold) {
+        // widening: child pair l, children of a non-fine side only
+        const int na = a.ccnt[lf.x], nb = a.ccnt[lf.y];
+        const uint32_t si = na > 0, sj = nb > 0;
+        const uint32_t nbj = sj ? (uint32_t)nb : 1u;
+        const uint32_t ia = l / nbj, ib = l - ia * nbj;
+        const int ca = si ? a.cbeg[lf.x] + (int)ia : lf.x;
+        const int cb = sj ? a.cbeg[lf.y] + (int)ib : lf.y;
+        const uint32_t D1 = D + 1;
+        const uint32_t nflags = (flags & ~1u) | ((flags & 1u) << D1) | (mem_contains(a, mem_key(ca, cb)) ? 1u : 0u);
+        r = make_int4(ca, cb, (int)nflags, (int)fr_info(l, m >> 16, D1, si, sj));
+      }
+      lout[obase + (unsigned long long)e] = r;
+    }
+    obase += (unsigned long long)total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_fr_finish(FrontierArgs a) {
+  if (threadIdx.x != 0) return;
+  if (a.stats) {
+    a.stats->frontier_unfolded = a.ctr->fr_unfold;
+    a.stats->frontier_collapsed = a.ctr->fr_collapse;
+  }
+  if (fr_skip(a)) return;
+  a.state[0] ^= 1u;
+  a.state[1] = a.state[2];
+}
+
+// Initial active sets: every root pair of every candidate pair.
+__global__ void k_fr_init_count(const int32_t* __restrict__ pairs, int n_pairs, const int32_t* __restrict__ rcnt,
+                                unsigned long long* pc) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_pairs; k += gridDim.x * blockDim.x)
+    pc[k] = (unsigned long long)rcnt[pairs[k]] * (unsigned long long)rcnt[pairs[n_pairs + k]];
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_fr_init_scan(unsigned long long* pc, int n_pairs, uint32_t* state,
+                                                                int64_t cap, uint32_t* status) {
+  block_scan_u64(pc, (uint32_t)n_pairs);
+  if (threadIdx.x == 0) {
+    const unsigned long long total = pc[n_pairs];
+    state[0] = 0;
+    state[2] = (uint32_t)min(total, 0xFFFFFFFFull);
+    state[3] = 0;
+    if (total > (unsigned long long)cap) {
+      state[1] = 0;
+      *status = DEM_DEV_FRONTIER_OVERFLOW;
+    } else {
+      state[1] = (uint32_t)total;
+      *status = 0;
+    }
+  }
+}
+
+__global__ void k_fr_init_write(const int32_t* __restrict__ pairs, int n_pairs, const int32_t* __restrict__ rbeg,
+                                const int32_t* __restrict__ rcnt, const unsigned long long* __restrict__ pc,
+                                int64_t cap, int4* __restrict__ out) {
+  if (pc[n_pairs] > (unsigned long long)cap) return;
+  for (int k = blockIdx.x; k < n_pairs; k += gridDim.x) {
+    const int pi = pairs[k], pj = pairs[n_pairs + k];
+    const int bi = rbeg[pi], ni = rcnt[pi], bj = rbeg[pj], nj = rcnt[pj];
+    for (int e = threadIdx.x; e < ni * nj; e += blockDim.x) {
+      const int ii = e / nj, jj = e - ii * nj;
+      out[pc[k] + (unsigned long long)e] = make_int4(bi + ii, bj + jj, 0, 0);
+    }
+  }
+}
+
+__global__ void k_fr_mem_clear(unsigned long long* mem, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    mem[k] = kMemEmpty;
+}
+
 // ------------------------------------------------------------------ host
 IterParams make_iter(const dem_params& p) {
   IterParams ip;
@@ -968,10 +1403,10 @@ void launch_flat(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* s
   }
 }
 
-template <typename T>
+template <typename T, bool FR>
 void launch_near_certify(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const NearArgs& na) {
   switch (n_iter) {
-#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_near<T, N, true>), g, b, 0, st, soup, na); break;
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_near<T, N, true, FR>), g, b, 0, st, soup, na); break;
     DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
 #undef DEM_CASE
   }
@@ -1066,7 +1501,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
       mark();
     }
   }
-  NearArgs na;
+  NearArgs na{};
   na.near_ = nearl;
   na.near_tail = ctr->near_tail;
   na.ncap = nseg;
@@ -1083,13 +1518,157 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   na.status = status;
   na.ip = make_iter(p);
   if (p.certify) {
-    launch_near_certify<T>(p.n_iter, dim3(grid), dim3(p.block), st, soup, na);
+    launch_near_certify<T, false>(p.n_iter, dim3(grid), dim3(p.block), st, soup, na);
     mark();
     // the exact comparison-based pass over what the certificate left
     na.near_ = na.fb;
     na.near_tail = na.fb_tail;
   }
-  hipLaunchKernelGGL((k_near<T, 0, false>), dim3(grid), dim3(p.block), 0, st, soup, na);
+  hipLaunchKernelGGL((k_near<T, 0, false, false>), dim3(grid), dim3(p.block), 0, st, soup, na);
+  mark();
+  return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
+
+// ------------------------------------------------------------------ frontier host side
+struct FrLayout {
+  WsLayout w;
+  size_t meta, cm, part, pcount, total;
+};
+
+constexpr int kFrMaxGrid = 8192;
+
+int fr_grid(const dem_params& p) { return std::min(p.grid > 0 ? p.grid : 1024, kFrMaxGrid); }
+
+FrLayout fr_layout(int precision, int64_t n_tris, int64_t ncap, int64_t fcap, int grid, int64_t n_pairs) {
+  FrLayout F;
+  F.w = ws_layout(precision, n_tris, kSeg, ncap);  // level queues unused: minimal
+  size_t o = F.w.total;
+  F.meta = o; o = align_up(o + 4 * (size_t)fcap, 256);
+  F.cm = o; o = align_up(o + (size_t)fcap, 256);
+  F.part = o; o = align_up(o + 8 * (size_t)(grid + 1), 256);
+  F.pcount = o; o = align_up(o + 8 * (size_t)(n_pairs + 1), 256);
+  F.total = o;
+  return F;
+}
+
+bool frontier_ok(const dem_frontier* f) {
+  if (!f || !f->leaves[0] || !f->leaves[1] || !f->state || !f->memory) return false;
+  if (f->capacity < 1 || f->capacity > (int64_t)0xFFFFFFFF) return false;
+  if (f->memory_capacity < 64 || (f->memory_capacity & (f->memory_capacity - 1))) return false;
+  if (reinterpret_cast<uintptr_t>(f->leaves[0]) % 16 || reinterpret_cast<uintptr_t>(f->leaves[1]) % 16) return false;
+  return true;
+}
+
+template <typename T>
+void launch_fr_eval(int n_iter, dim3 g, hipStream_t st, const SoupRec<T>* soup, const FrontierArgs& fa) {
+  switch (n_iter) {
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_fr_eval<T, N, false>), g, dim3(kFrBlock), 0, st, soup, fa); break;
+    DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
+#undef DEM_CASE
+  }
+}
+
+template <typename T>
+dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_frontier* f,
+                             const dem_contacts* out, void* ws, const FrLayout& FL, dem_stats* stats,
+                             uint32_t* status, double* energy, hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  Counters* ctr = reinterpret_cast<Counters*>(base + FL.w.ctr);
+  SoupRec<T>* soup = reinterpret_cast<SoupRec<T>*>(base + FL.w.soup);
+  const int grid = fr_grid(p);
+  int n_launch = 0;
+  auto mark = [&]() {
+    if (p.events && n_launch < p.n_events)
+      (void)hipEventRecord(reinterpret_cast<hipEvent_t>(p.events[n_launch]), st);
+    ++n_launch;
+  };
+  mark();
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctr, stats, status, out->count, energy);
+  mark();
+  FlatArgs<T> fl;
+  fl.verts = static_cast<const T*>(s->verts);
+  fl.n_verts = s->n_verts;
+  fl.tv = s->tri_verts;
+  fl.n_tris = s->n_tris;
+  fl.cbeg = s->child_begin;
+  fl.ccnt = s->child_count;
+  fl.tpart = s->tri_particle;
+  fl.teps = static_cast<const T*>(s->tri_eps);
+  fl.pose = static_cast<const T*>(s->pose);
+  fl.areg_rel = T(p.alpha_reg_rel);
+  fl.root_begin = s->root_begin;
+  fl.root_count = s->root_count;
+  fl.fine_begin = s->fine_begin;
+  fl.soup = soup;
+  fl.mark = reinterpret_cast<uint8_t*>(base + FL.w.mark);
+  fl.lazy = 0;  // leaves may sit at any depth: every record is written
+  fl.status = status;
+  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + 255) / 256), dim3(256), 0, st, fl);
+  mark();
+  const int64_t nseg = p.near_capacity / kSeg;
+  FrontierArgs fa{};
+  fa.buf0 = reinterpret_cast<int4*>(f->leaves[0]);
+  fa.buf1 = reinterpret_cast<int4*>(f->leaves[1]);
+  fa.state = f->state;
+  fa.cap = f->capacity;
+  fa.mem = reinterpret_cast<unsigned long long*>(f->memory);
+  fa.mem_mask = (uint64_t)f->memory_capacity - 1;
+  fa.meta = reinterpret_cast<uint32_t*>(base + FL.meta);
+  fa.cm = reinterpret_cast<uint8_t*>(base + FL.cm);
+  fa.part = reinterpret_cast<unsigned long long*>(base + FL.part);
+  fa.tri_parent = s->tri_parent;
+  fa.tri_depth = s->tri_depth;
+  fa.cbeg = s->child_begin;
+  fa.ccnt = s->child_count;
+  fa.n_tris = s->n_tris;
+  fa.ctr = ctr;
+  fa.near_ = reinterpret_cast<int2*>(base + FL.w.near_);
+  fa.near_tail = ctr->near_tail;
+  fa.ncap = nseg;
+  fa.stats = stats;
+  fa.status = status;
+  fa.ip = make_iter(p);
+  if (p.prune_exact) hipLaunchKernelGGL((k_fr_eval<T, 0, true>), dim3(grid), dim3(kFrBlock), 0, st, soup, fa);
+  else launch_fr_eval<T>(p.n_iter, dim3(grid), st, soup, fa);
+  mark();
+  NearArgs na{};
+  na.near_ = fa.near_;
+  na.near_tail = ctr->near_tail;
+  na.ncap = nseg;
+  na.fb = reinterpret_cast<int2*>(base + FL.w.fb);
+  na.fb_tail = ctr->fb_tail;
+  na.pi = out->pi; na.pj = out->pj; na.ti = out->ti; na.tj = out->tj;
+  na.d = out->d; na.x = out->x; na.n = out->n;
+  na.count = out->count;
+  na.ccap = out->capacity;
+  na.dense = 0;
+  na.k = p.energy_k;
+  na.energy = energy;
+  na.stats = stats;
+  na.status = status;
+  na.ip = make_iter(p);
+  na.fr_buf0 = fa.buf0;
+  na.fr_buf1 = fa.buf1;
+  na.fr_state = f->state;
+  na.fr_meta = reinterpret_cast<uint8_t*>(fa.meta);
+  if (p.certify) {
+    launch_near_certify<T, true>(p.n_iter, dim3(grid), dim3(p.block), st, soup, na);
+    mark();
+    na.near_ = na.fb;
+    na.near_tail = na.fb_tail;
+  }
+  hipLaunchKernelGGL((k_near<T, 0, false, true>), dim3(grid), dim3(p.block), 0, st, soup, na);
+  mark();
+  hipLaunchKernelGGL(k_fr_group, dim3(grid), dim3(kFrBlock), 0, st, fa);
+  mark();
+  hipLaunchKernelGGL(k_fr_count, dim3(grid), dim3(kFrBlock), 0, st, fa);
+  mark();
+  hipLaunchKernelGGL(k_fr_scan, dim3(1), dim3(kScanThreads), 0, st, fa, (uint32_t)grid);
+  mark();
+  hipLaunchKernelGGL(k_fr_emit, dim3(grid), dim3(kFrBlock), 0, st, fa);
+  mark();
+  hipLaunchKernelGGL(k_fr_finish, dim3(1), dim3(64), 0, st, fa);
   mark();
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
@@ -1177,6 +1756,63 @@ dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* c, d
                        static_cast<float*>(grad_verts), energy_out, dev_status);
   }
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
+size_t dem_frontier_workspace_bytes(const dem_scene* scene, int32_t n_pairs, const dem_params* pp,
+                                    int64_t frontier_capacity) {
+  dem_params p;
+  if (pp) p = *pp; else dem_default_params(&p);
+  if (!scene_ok(scene) || !params_ok(p) || n_pairs < 0) return 0;
+  if (frontier_capacity < 1 || frontier_capacity > (int64_t)0xFFFFFFFF) return 0;
+  return fr_layout(scene->precision, scene->n_tris, p.near_capacity, frontier_capacity, fr_grid(p), n_pairs)
+      .total;
+}
+
+dem_status dem_frontier_init(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
+                             const dem_params* pp, const dem_frontier* f, void* workspace,
+                             size_t workspace_bytes, uint32_t* dev_status, dem_stream_t stream) {
+  dem_params p;
+  if (pp) p = *pp; else dem_default_params(&p);
+  if (!scene_ok(scene) || !params_ok(p) || !frontier_ok(f) || !dev_status || !workspace) return DEM_ERR_ARG;
+  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return DEM_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
+  FrLayout FL = fr_layout(scene->precision, scene->n_tris, p.near_capacity, f->capacity, fr_grid(p), n_pairs);
+  if (workspace_bytes < FL.total) return DEM_ERR_CAPACITY;
+  unsigned long long* pc = reinterpret_cast<unsigned long long*>(static_cast<char*>(workspace) + FL.pcount);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_fr_mem_clear, dim3(1024), dim3(256), 0, st,
+                     reinterpret_cast<unsigned long long*>(f->memory), f->memory_capacity);
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_fr_init_count, dim3((n_pairs + 255) / 256), dim3(256), 0, st, pairs, n_pairs,
+                       scene->root_count, pc);
+  hipLaunchKernelGGL(k_fr_init_scan, dim3(1), dim3(kScanThreads), 0, st, pc, n_pairs, f->state, f->capacity,
+                     dev_status);
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_fr_init_write, dim3(std::min(n_pairs, 65535)), dim3(256), 0, st, pairs, n_pairs,
+                       scene->root_begin, scene->root_count, pc, f->capacity,
+                       reinterpret_cast<int4*>(f->leaves[0]));
+  return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
+dem_status dem_frontier_step(const dem_scene* scene, const dem_params* pp, const dem_frontier* f,
+                             const dem_contacts* out, void* workspace, size_t workspace_bytes,
+                             dem_stats* dev_stats, uint32_t* dev_status, double* dev_energy,
+                             dem_stream_t stream) {
+  dem_params p;
+  if (pp) p = *pp; else dem_default_params(&p);
+  if (!scene_ok(scene) || !params_ok(p) || !frontier_ok(f)) return DEM_ERR_ARG;
+  if (!scene->tri_parent || !scene->tri_depth) return DEM_ERR_ARG;
+  if (!out || !out->count || out->capacity < 0 || out->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
+  if (out->capacity > 0 && (!out->pi || !out->pj || !out->ti || !out->tj || !out->d || !out->x || !out->n))
+    return DEM_ERR_ARG;
+  if (!workspace || !dev_status) return DEM_ERR_ARG;
+  FrLayout FL = fr_layout(scene->precision, scene->n_tris, p.near_capacity, f->capacity, fr_grid(p), 0);
+  if (workspace_bytes < FL.total) return DEM_ERR_CAPACITY;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (scene->precision == DEM_F64)
+    return run_frontier_step<double>(scene, p, f, out, workspace, FL, dev_stats, dev_status, dev_energy, st);
+  return run_frontier_step<float>(scene, p, f, out, workspace, FL, dev_stats, dev_status, dev_energy, st);
 }
 
 const char* dem_status_string(dem_status s) {

@@ -32,8 +32,8 @@ def test_header_symbols_exported():
 
 
 def test_struct_sizes_match_header_layout():
-    # dem_stats: 3 arrays of 32 + 4 scalars, 8 bytes each
-    assert C.sizeof(_abi.Stats) == 8 * (3 * 32 + 4)
+    # dem_stats: 3 arrays of 32 + 4 scalars + 3 frontier counters, 8 bytes each
+    assert C.sizeof(_abi.Stats) == 8 * (3 * 32 + 4 + 3)
     p = _abi.default_params()
     assert p.n_iter == 4 and p.mode == _abi.DEM_MODE_HIER and p.omega == 1.0
     assert list(p.level_grid) == [0] * _abi.DEM_MAX_LEVELS and list(p.level_batch) == [0] * _abi.DEM_MAX_LEVELS
@@ -43,7 +43,8 @@ def test_ctypes_layout_matches_c_compiler(tmp_path):
     """Every field offset and struct size of the binding equals what a C
     compiler makes of include/dem.h."""
     structs = {"dem_build_opts": _abi.BuildOpts, "dem_hierarchy": _abi.Hierarchy, "dem_scene": _abi.Scene,
-               "dem_params": _abi.Params, "dem_contacts": _abi.Contacts, "dem_stats": _abi.Stats}
+               "dem_params": _abi.Params, "dem_contacts": _abi.Contacts, "dem_stats": _abi.Stats,
+               "dem_frontier": _abi.Frontier}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dem.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
