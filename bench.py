@@ -63,6 +63,9 @@ WORKLOADS = {
                         "gaps U(0,0.1), full icosphere cascades, FP32", True),
     "big_small": ("bumped sphere R=20 subdivision 7 (327680 tris) + 2000 R=0.5 subdivision-3 spheres "
                   "on its surface, FP32", False),
+    "lattice_frontier": ("1000 bumped spheres on a 10x10x10 lattice, subdivision 3-5, radii logU[0.5,2], "
+                         "gaps U(0,0.1), full icosphere cascades, FP32; persistent active sets "
+                         "(dem_frontier_step, one level of widening / narrowing per step)", True),
 }
 
 
@@ -71,7 +74,8 @@ def workload(name: str):
     if name not in WORKLOADS:
         raise SystemExit(f"unknown workload {name}; one of {sorted(WORKLOADS)}")
     make = {"two_spheres_s3_f64": sg.two_spheres_s3_f64, "two_spheres_s5": sg.two_spheres_s5_hier, "lattice": sg.lattice1000,
-            "lattice_fwd_bwd": sg.lattice1000, "big_small": sg.big_plus_small}[name]
+            "lattice_fwd_bwd": sg.lattice1000, "big_small": sg.big_plus_small,
+            "lattice_frontier": sg.lattice1000}[name]
     desc, backward = WORKLOADS[name]
     return make(), desc, backward
 
@@ -102,6 +106,63 @@ class Step:
         if self.backward:
             self.grad.zero_()
             self.eng.backward(self.grad)
+
+
+class FrontierStep(Step):
+    """One step on persistent active sets: the seeded rigid perturbation,
+    dem_frontier_step (contacts of this step, widening / narrowing for the
+    next) and the backward pass of its contacts."""
+
+    def __call__(self, k: int):
+        self.pose(k)
+        self.eng.step(with_energy=True)
+        if self.backward:
+            self.grad.zero_()
+            self.eng.backward(self.grad)
+
+
+FRONTIER_SLOTS = ("reset", "flatten", "eval", "near", "group", "count", "scan", "emit", "finish")
+
+
+def frontier_kernel_times(torch, step: FrontierStep, K: int):
+    """Per-launch durations (ms) of dem_frontier_step's kernels over K eager
+    steps (HIP events recorded by the library between its launches), the
+    backward call, and the step's counters averaged."""
+    eng = step.eng
+    n_ev = 16
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
+    for e in evs:
+        e.record()
+    torch.cuda.synchronize()
+    handles = (C.c_void_p * n_ev)(*[C.c_void_p(e.cuda_event) for e in evs])
+    eng.p.events = C.cast(handles, C.POINTER(C.c_void_p))
+    eng.p.n_events = n_ev
+    names = list(FRONTIER_SLOTS)
+    if eng.p.certify:
+        names.insert(3, "certify")
+    acc = np.zeros(len(names))
+    bwd = 0.0
+    stats_acc = {}
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    try:
+        for k in range(K):
+            step.pose(k)
+            eng.step(with_energy=True)
+            step.grad.zero_()
+            b0.record()
+            eng.backward(step.grad)
+            b1.record()
+            torch.cuda.synchronize()
+            for i in range(len(names)):
+                acc[i] += evs[i].elapsed_time(evs[i + 1])
+            bwd += b0.elapsed_time(b1)
+            for k2, v in eng.stats_dict().items():
+                v = np.array(v, dtype=np.float64) if isinstance(v, np.ndarray) else float(v)
+                stats_acc[k2] = stats_acc.get(k2, 0) + v
+    finally:
+        eng.p.events = None
+        eng.p.n_events = 0
+    return dict(zip(names, acc / K)), bwd / K, {k2: v / K for k2, v in stats_acc.items()}
 
 
 def time_graph(torch, step: Step, K: int, warmup: int):
@@ -261,6 +322,94 @@ def measured_traffic(workload: str, kernel: str, launch: dict, profiles_dir: str
     return d["read_bytes"] + d["write_bytes"], "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
 
 
+def frontier_launch(p) -> dict:
+    return {k: getattr(p, k) for k in ("grid", "block", "omega", "n_iter", "certify", "prune_exact")}
+
+
+def run_frontier_bench(torch, api, ds, args, params_kw, desc, log):
+    """lattice_frontier: persistent active sets followed through K perturbed
+    steps (captured in one HIP graph) after converging at the start pose."""
+    from paper_2105_12415_amd import autotune
+    K = args.steps
+    p = api.make_params("hier", **params_kw)
+    eng = api.FrontierEngine(ds, p, contact_capacity=args.contact_capacity, energy_k=1e4)
+    tuned = None
+    if not args.no_autotune and not params_kw:
+        # the descent's stored launch shape and damping for this scene
+        rec = autotune.apply_stored(eng)
+        tuned = {"chosen": rec, "source": "stored by the autotuner (descent)"} if rec else None
+    step = FrontierStep(ds, eng, True, K, torch)
+    step.pose(0)
+    eng.init()
+    t0 = time.perf_counter()
+    n_conv = eng.run_to_fixed_point()
+    st0 = eng.stats_dict()
+    n_leaves = int(eng.state_host()[1])
+    log(f"[bench] frontier converged in {n_conv} steps ({time.perf_counter() - t0:.1f} s): {n_leaves} leaves, "
+        f"{eng.count()} contacts")
+    # room for the sets, the near list and the contacts to follow the motion inside the graph
+    eng.reserve(int(1.5 * n_leaves) + 4096)
+    eng.p.near_capacity = max(int(eng.p.near_capacity), 8 * int(st0["near"]) // 2 + 8 * 65536)
+    eng.ws = None
+    eng._alloc_ws()
+    if eng.contacts.capacity < 2 * eng.count():
+        eng.contacts = api.ContactBuffers.alloc(2 * eng.count(), ds.dtype, ds.device)
+    for k in range(K):
+        step(k)
+        status = eng.check()
+        if status:
+            raise RuntimeError(f"device status {status:#x} in eager frontier step {k}")
+    ms, ms_wall, graph = time_graph(torch, step, K, args.warmup)
+    status = eng.check()
+    if status:
+        raise RuntimeError(f"device status {status:#x} after graph replay")
+    del graph
+    kt, bwd_ms, st = frontier_kernel_times(torch, step, K)
+    evals = float(st["frontier_leaves"])
+    log(f"[bench] frontier: {ms:.3f} ms/step (wall {ms_wall:.3f}), {evals:.4g} leaves/step, "
+        f"{st['contacts']:.0f} contacts, unfolded {st['frontier_unfolded']:.1f}, "
+        f"collapsed {st['frontier_collapsed']:.1f}")
+    n_iter = eng.p.n_iter
+    flops = flops_per_eval(n_iter) * evals
+    achieved = flops / (kt["eval"] * 1e-3) / 1e12
+    launch = frontier_launch(eng.p)
+    traffic, traffic_note = measured_traffic(args.workload, "k_fr_eval", launch)
+    roof = {"bound": "alu", "kernel": "k_fr_eval<float>", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
+            "traffic_note": traffic_note, "launches_per_step": 1, "avg_launch_ms": kt["eval"],
+            "flops_per_eval": flops_per_eval(n_iter), "evals_per_step": evals}
+    L = ds.n_levels_max
+    out = {"metric": METRIC, "value": evals / (ms * 1e-3), "unit": "tri-pair evals/s", "n_gpus": 1,
+           "steps": K, "warmup": args.warmup, "ms_per_step": ms, "ms_per_step_wall": ms_wall,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {desc}; forward + backward (k=1e4), per-step rigid "
+                      f"perturbation, {K} steps captured in one HIP graph after converging the active sets "
+                      f"at the start pose ({n_conv} steps)",
+                      "particles": ds.n_particles, "triangles_all_levels": ds.n_tris,
+                      "candidate_pairs": ds.n_pairs, "fine_pairs": ds.n_fine_pairs(), "n_iter": n_iter,
+                      "autotuned": tuned, "launch": launch},
+           "roofline": roof,
+           "kernels": dict({f"{k}_ms": v for k, v in kt.items()}, backward_ms=bwd_ms),
+           "stats": {"leaves": evals, "leaves_by_depth": [int(x) for x in st["evals"][:L]],
+                     "unfolded": st["frontier_unfolded"], "collapsed": st["frontier_collapsed"],
+                     "near": st["near"], "contacts": st["contacts"],
+                     "converged_leaves": n_leaves, "converge_steps": n_conv}}
+    del eng, step
+    torch.cuda.empty_cache()
+    if not args.no_flat:
+        # the full descent on the same perturbed steps, for comparison
+        de, dstep, dms, dwall, dkt, dbwd, dst = run_mode(torch, api, ds, "hier", True, K, args.warmup, params_kw,
+                                                       args.contact_capacity,
+                                                       tune="off" if args.no_autotune else "cache")
+        out["descent"] = {"ms_per_step": dms, "evals_per_step": float(np.sum(dst["evals"])),
+                          "contacts": dst["contacts"]}
+        out["speedup_vs_descent"] = dms / ms
+        log(f"[bench] descent: {dms:.3f} ms/step")
+        del de, dstep
+    return out
+
+
 def cpu_baseline(scene, n_sample: int, backward: bool):
     import oracle
     fs = oracle.fine_scene(scene)
@@ -331,6 +480,14 @@ def main():
     log = lambda m: print(m, file=sys.stderr, flush=True)
     log(f"[bench] {args.workload}: {desc}; {ds.n_particles} particles, {ds.n_tris} triangles, "
         f"{ds.n_pairs} candidate pairs, {ds.n_fine_pairs()} fine pairs")
+
+    if args.workload == "lattice_frontier":
+        out = run_frontier_bench(torch, api, ds, args, params_kw, desc, log)
+        if not args.no_cpu:
+            log("[bench] cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline(scene, args.cpu_pairs, backward)
+        print(json.dumps(out), flush=True)
+        return
 
     eng, step, ms, ms_wall, kt, bwd_ms, st = run_mode(torch, api, ds, "hier", backward, K, args.warmup,
                                                      params_kw, args.contact_capacity,

@@ -549,14 +549,32 @@ class FrontierEngine:
                 need = int(self.state_host()[2])
                 if need <= self.capacity:
                     raise DemError("frontier memory set is full: initialise again with a larger memory_capacity")
-                old = self.leaves()
-                self._alloc_leaves(max(2 * self.capacity, int(1.25 * need) + 1024))
-                self.leaf_bufs[0][:len(old)] = torch.as_tensor(old.astype(np.int64).astype(np.uint32).view(np.int32),
-                                                               device=self.ds.device)
-                self.state.copy_(torch.tensor([0, len(old), len(old), 0], dtype=torch.int32))
+                self.reserve(max(2 * self.capacity, int(1.25 * need) + 1024))
             self.ws = None
             self._alloc_ws()
         raise DemError("capacities kept overflowing")
+
+    def reserve(self, capacity: int):
+        """Grow both leaf buffers to ``capacity`` keeping the current sets
+        (and the memory set); synchronises."""
+        if capacity <= self.capacity:
+            return
+        old = self.leaves()
+        self._alloc_leaves(int(capacity))
+        self.leaf_bufs[0][:len(old)] = torch.as_tensor(old.astype(np.uint32).view(np.int32), device=self.ds.device)
+        self.state.copy_(torch.tensor([0, len(old), len(old), 0], dtype=torch.int32))
+        self.ws = None
+        self._alloc_ws()
+
+    def run_to_fixed_point(self, max_steps: int = 64) -> int:
+        """run_step() at the current positions until a step neither widens
+        nor narrows; returns the number of steps."""
+        for k in range(1, max_steps + 1):
+            self.run_step()
+            s = self.stats_dict()
+            if s["frontier_unfolded"] == 0 and s["frontier_collapsed"] == 0:
+                return k
+        raise DemError("active sets kept changing")
 
     def stats_dict(self) -> dict:
         return _stats_dict(self.stats)

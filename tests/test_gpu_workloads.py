@@ -169,3 +169,61 @@ def test_fwd_bwd_steps_sampled_gradient(step):
     assert err <= (1e-4 if step == 0 else 1e-3), err
     assert len(keep) > 0.6 * len(touched), (len(keep), len(touched), int(bad.sum()), len(bad))
     ds.set_pose(None)
+
+
+def _fine_counts(ds):
+    """Number of fine descendants of every triangle (bottom-up over the
+    child ranges; children have larger ids than their parents)."""
+    cb = ds.child_begin.cpu().numpy().astype(np.int64)
+    cc = ds.child_count.cpu().numpy().astype(np.int64)
+    n = np.where(cc == 0, 1, 0).astype(np.int64)
+    for t in np.nonzero(cc)[0][::-1]:
+        n[t] = n[cb[t]:cb[t] + cc[t]].sum()
+    return n
+
+
+@pytest.mark.parametrize("step", [0, 9])
+def test_lattice_frontier_fixed_point(step):
+    """The persistent active sets in the benchmark's configuration (stored
+    launch parameters), converged at the benchmark's pose of `step`: the
+    leaves cover every fine pair once (count), the contacts of sampled pairs
+    match the oracle, and the whole contact set equals the descent's."""
+    scene, ds = _scene("lattice")
+    P = ds.n_particles
+    Rs, ts = sg.rigid_perturbations(P, 10)
+    centres = np.array([p.centre for p in scene.particles])
+    shift = centres + ts[step] - np.einsum("pij,pj->pi", Rs[step], centres)
+    pose = np.concatenate([Rs[step].reshape(P, 9), shift], 1)
+    ds.set_pose(torch.as_tensor(pose, dtype=ds.dtype, device="cuda:0").contiguous())
+    eng = api.FrontierEngine(ds, api.make_params("hier"), contact_capacity=1 << 23)
+    autotune.apply_stored(eng)
+    eng.init()
+    n_steps = eng.run_to_fixed_point()
+    res = eng.result()
+    L = eng.leaves()
+    say(f"[gpu-test] frontier fixed point after {n_steps} steps: {len(L)} leaves, {len(res['d'])} contacts")
+    assert n_steps <= ds.n_levels_max + 3
+    nf = _fine_counts(ds)
+    F = ds.fine_count_host
+    Pp = ds.pairs_host
+    assert int(np.sum(nf[L[:, 0]] * nf[L[:, 1]])) == int(np.sum(F[Pp[:, 0]] * F[Pp[:, 1]]))
+    moved = [(scene.world(p) - centres[p]) @ Rs[step][p].T + centres[p] + ts[step][p] for p in range(P)]
+    fs = oracle.fine_scene(scene, verts_override=moved)
+    cmax = max(np.abs(m).max() for m in moved)
+    extra = 0.0 if step == 0 else 8 * 2.0 ** -24 * cmax
+    n, _ = _check_pairs(scene, ds, res, fs, _sample(scene, 12, 23), TOL["f32"], extra)
+    assert n > 50
+    ce = _engine(ds)
+    assert ce.run() == 0
+    r2 = ce.result()
+    a = set(zip(res["ti"].tolist(), res["tj"].tolist()))
+    b = set(zip(r2["ti"].tolist(), r2["tj"].tolist()))
+    assert len(a) == len(res["ti"]) and len(a) > 100000
+    # both sides decide the same contacts from the same FP32 soup, up to
+    # pairs within the threshold band that one side settles differently
+    d1 = dict(zip(zip(res["ti"].tolist(), res["tj"].tolist()), res["d"].tolist()))
+    d2 = dict(zip(zip(r2["ti"].tolist(), r2["tj"].tolist()), r2["d"].tolist()))
+    for key in a ^ b:
+        d = d1.get(key, d2.get(key))
+        assert abs(d - 0.1) <= 1e-6, (key, d)
+    ds.set_pose(None)
