@@ -121,7 +121,7 @@ class FrontierStep(Step):
             self.eng.backward(self.grad)
 
 
-FRONTIER_SLOTS = ("reset", "flatten", "eval", "near", "group", "count", "scan", "emit", "finish")
+FRONTIER_SLOTS = ("reset", "flatten", "eval", "near", "group", "scan", "emit", "finish")
 
 
 def frontier_kernel_times(torch, step: FrontierStep, K: int):
@@ -323,7 +323,7 @@ def measured_traffic(workload: str, kernel: str, launch: dict, profiles_dir: str
 
 
 def frontier_launch(p) -> dict:
-    return {k: getattr(p, k) for k in ("grid", "block", "omega", "n_iter", "certify", "prune_exact")}
+    return {k: getattr(p, k) for k in ("grid", "frontier_grid", "block", "omega", "n_iter", "certify", "prune_exact")}
 
 
 def run_frontier_bench(torch, api, ds, args, params_kw, desc, log):

@@ -265,6 +265,7 @@ typedef struct {
   int32_t flat_tile_i;    /* flat mode: i-triangles per tile (multiple of 64, <= 1024) */
   int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..64) */
   int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges (1..16; default 8) */
+  int32_t frontier_grid;  /* dem_frontier_step: blocks of the per-leaf kernels (0 = 4096; <= 8192) */
   /* Per-depth overrides of grid and batch_items for the descent launches
    * (index = tree depth; 0 = use grid / batch_items).  Depths differ in item
    * count and shape (few large root chunks at depth 0, millions of 4 x 4

@@ -917,15 +917,16 @@ __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__
 // leaf record and buffer layout are described with dem_frontier in dem.h).
 //
 // One dem_frontier_step:
-//   k_fr_eval   every leaf: in range or not (lower bound, or exact distance);
-//               fine pairs in range go to the near list; per-leaf outcome
-//               word (meta) = outcome | group index << 8 | n << 16 with n =
-//               the group size at a group's first leaf that may narrow, or
-//               the child-pair count of a leaf that widens
+//   k_fr_eval   every leaf (blocks take contiguous ranges, fr_range): in
+//               range or not (lower bound, or exact distance); fine pairs in
+//               range go to the near list; per-leaf outcome word (meta) =
+//               outcome | group index << 8 | n << 16 with n = the group size
+//               at a group's first leaf that may narrow, or the child-pair
+//               count of a leaf that widens; per-block output leaf counts
 //   k_near<FR>  exact distance of the fine pairs, contacts, outcome byte
 //   k_fr_group  a group's first leaf checks that its n members follow it in
-//               order, all leaves and all "no contact"; marks them (cm)
-//   k_fr_count  output leaves per block of a contiguous leaf range
+//               order, all leaves and all "no contact"; marks them (cm) and
+//               takes the removed members off their blocks' counts
 //   k_fr_scan   block offsets (one block)
 //   k_fr_emit   rewrite in depth-first order into the other buffer: copies,
 //               parents of narrowed groups (inserted into the memory set),
@@ -935,6 +936,7 @@ constexpr unsigned long long kMemEmpty = ~0ull;
 constexpr int kScanThreads = 1024;
 constexpr int kFrBlock = 256;
 constexpr int kMemProbes = 64;
+constexpr int kFrMaxGrid = 8192;  // blocks of the per-leaf kernels (scan partials)
 
 __device__ __forceinline__ uint32_t fr_depth(uint32_t info) { return (info >> 17) & 31u; }
 __device__ __forceinline__ uint32_t fr_gidx(uint32_t info) { return info & 255u; }
@@ -1058,18 +1060,20 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0) a.state[2] = n;
   __syncthreads();
   uint32_t my_unf = 0, my_near = 0;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+  unsigned long long my_out = 0;  // leaves this thread's leaves become if no group narrows
+  uint32_t lo, hi;
+  fr_range(n, lo, hi);
+  for (uint32_t base = lo; base < hi; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     bool near = false;
-    const int4 lf = i < n ? lin[i] : make_int4(0, 0, 0, 0);
+    const int4 lf = i < hi ? lin[i] : make_int4(0, 0, 0, 0);
     const bool valid = (uint32_t)lf.x < (uint32_t)a.n_tris && (uint32_t)lf.y < (uint32_t)a.n_tris;
-    if (i < n && !valid) {
+    if (i < hi && !valid) {
       atomicOr(a.status, DEM_DEV_BAD_TREE);  // not a leaf this library wrote: the sets stay as they are
       a.meta[i] = kOutKeep;
       a.cm[i] = 0;
     }
-    if (i < n && valid) {
+    if (i < hi && valid) {
       int cbi, cci, pi_, cbj, ccj, pj_;
       Tri<T> A = load_tri(soup, lf.x, cbi, cci, pi_);
       Tri<T> B = load_tri(soup, lf.y, cbj, ccj, pj_);
@@ -1098,6 +1102,7 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
       }
       a.meta[i] = out | (g << 8) | (nn << 16);
       a.cm[i] = 0;
+      my_out += out == kOutUnfold ? nn : 1u;
       near = out == kOutNear;
       my_unf += out == kOutUnfold;
       my_near += near;
@@ -1110,14 +1115,23 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
   }
   __syncthreads();
   lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+  __shared__ unsigned long long osum[kFrBlock / kWave];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     my_unf += __shfl_xor(my_unf, o);
     my_near += __shfl_xor(my_near, o);
+    my_out += __shfl_xor(my_out, o);
   }
   if (lane_id() == 0) {
+    osum[threadIdx.x / kWave] = my_out;
     if (my_unf) atomicAdd(&a.ctr->fr_unfold, my_unf);
     if (a.stats && my_near) atomicAdd(&a.stats->near, (unsigned long long)my_near);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += osum[w];
+    a.part[blockIdx.x] = t;  // output leaves of this block's range, before narrowing
   }
   if (a.stats && threadIdx.x < DEM_MAX_LEVELS && hist[threadIdx.x])
     atomicAdd(&a.stats->evals[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
@@ -1127,23 +1141,48 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
 // Narrowing: a group's first leaf checks its n - 1 followers.  In depth-first
 // order a member that is not a leaf is followed by its own first descendant
 // leaf, whose group index is 0, so the check fails exactly when some member
-// is not a leaf or not "no contact".
+// is not a leaf or not "no contact".  A narrowed group leaves one leaf
+// instead of n: the output counts of the blocks holding its other members
+// drop by one each (block ranges as in fr_range).
 __global__ void __launch_bounds__(kFrBlock) k_fr_group(FrontierArgs a) {
   const uint32_t n = fr_count(a);
+  const uint32_t G = gridDim.x, B = blockDim.x;
+  const uint32_t per = ((n + G - 1) / G + B - 1) / B * B;
+  const int lane = lane_id();
   uint32_t my = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint32_t m = a.meta[i];
+  // every wave takes 64 consecutive leaves per round (bounds are wave-uniform)
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const uint32_t m = i < n ? a.meta[i] : 0xFFu;
+    uint32_t prev = __shfl_up(m, 1);
+    if (lane == 0) prev = (i >= 1 && i - 1 < n) ? a.meta[i - 1] : 0xFFu;
+    const bool pr = (m & 255u) == kOutPrune;
+    const uint32_t g = (m >> 8) & 255u;
+    // link: "no contact", and the follower of the previous leaf in its group
+    const bool link = pr && g >= 1 && (prev & 255u) == kOutPrune && ((prev >> 8) & 255u) == g - 1;
+    const unsigned long long lm = __ballot(link);
     const uint32_t gn = m >> 16;
-    if ((m & 255u) != kOutPrune || gn == 0 || ((m >> 8) & 255u) != 0) continue;
-    if ((uint64_t)i + gn > n) continue;
-    bool all = true;
-    for (uint32_t j = 1; j < gn && all; ++j) {
-      const uint32_t mj = a.meta[i + j];
-      all = (mj & 255u) == kOutPrune && ((mj >> 8) & 255u) == j;
+    if (!(i < n && pr && gn > 0 && g == 0 && (uint64_t)i + gn <= n)) continue;
+    // members 1..gn-1 must all link up: lanes lane+1.. of this wave, then
+    // loads for the part past the wave
+    bool all;
+    if ((uint32_t)lane + gn <= 64u) {
+      const unsigned long long need = gn >= 2 ? ((1ull << (gn - 1)) - 1ull) << (lane + 1) : 0ull;
+      all = (lm & need) == need;
+    } else {
+      const unsigned long long need = lane < 63 ? (~0ull << (lane + 1)) : 0ull;
+      all = (lm & need) == need;
+      for (uint32_t j = 64u - (uint32_t)lane; j < gn && all; ++j) {
+        const uint32_t mj = a.meta[i + j];
+        all = (mj & 255u) == kOutPrune && ((mj >> 8) & 255u) == j;
+      }
     }
     if (!all) continue;
     a.cm[i] = 2;
-    for (uint32_t j = 1; j < gn; ++j) a.cm[i + j] = 1;
+    for (uint32_t j = 1; j < gn; ++j) {
+      a.cm[i + j] = 1;
+      atomicAdd(&a.part[(i + j) / per], ~0ull);  // -1
+    }
     ++my;
   }
 #pragma unroll
@@ -1161,24 +1200,6 @@ __device__ __forceinline__ uint32_t fr_out_count(uint32_t m, uint8_t c) {
   if (c == 2) return 1;
   if (c == 1) return 0;
   return (m & 255u) == kOutUnfold ? (m >> 16) : 1u;
-}
-
-__global__ void __launch_bounds__(kFrBlock) k_fr_count(FrontierArgs a) {
-  __shared__ unsigned long long wsum[kFrBlock / kWave];
-  if (fr_skip(a)) return;
-  uint32_t lo, hi;
-  fr_range(fr_count(a), lo, hi);
-  unsigned long long s = 0;
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += fr_out_count(a.meta[i], a.cm[i]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane_id() == 0) wsum[threadIdx.x / kWave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += wsum[w];
-    a.part[blockIdx.x] = t;
-  }
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_fr_scan(FrontierArgs a, uint32_t n_blocks) {
@@ -1221,6 +1242,14 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_emit(FrontierArgs a) {
       m_s[threadIdx.x] = a.meta[i];
       c_s[threadIdx.x] = a.cm[i];
       c = (int)fr_out_count(m_s[threadIdx.x], c_s[threadIdx.x]);
+    }
+    // a tile without widening or narrowing is copied as it is
+    const bool plain = i >= hi || (c_s[threadIdx.x] == 0 && (m_s[threadIdx.x] & 255u) != kOutUnfold);
+    if (__syncthreads_and(plain)) {
+      if (i < hi) lout[obase + (i - t0)] = lf_s[threadIdx.x];
+      obase += min((uint32_t)B, hi - t0);
+      __syncthreads();
+      continue;
     }
     block_scan(c, offs, wsum, B);
     const int total = offs[B];
@@ -1368,6 +1397,7 @@ bool params_ok(const dem_params& p) {
   if (p.queue_capacity < kSeg || p.queue_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.near_capacity < kSeg || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.grid < 0) return false;
+  if (p.frontier_grid < 0 || p.frontier_grid > kFrMaxGrid) return false;
   for (int d = 0; d < DEM_MAX_LEVELS; ++d) {
     if (p.level_grid[d] < 0) return false;
     if (p.level_batch[d] < 0 || p.level_batch[d] > p.block) return false;  // one item per thread
@@ -1536,9 +1566,7 @@ struct FrLayout {
   size_t meta, cm, part, pcount, total;
 };
 
-constexpr int kFrMaxGrid = 8192;
-
-int fr_grid(const dem_params& p) { return std::min(p.grid > 0 ? p.grid : 1024, kFrMaxGrid); }
+int fr_grid(const dem_params& p) { return p.frontier_grid > 0 ? p.frontier_grid : 4096; }
 
 FrLayout fr_layout(int precision, int64_t n_tris, int64_t ncap, int64_t fcap, int grid, int64_t n_pairs) {
   FrLayout F;
@@ -1576,7 +1604,8 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   char* base = static_cast<char*>(ws);
   Counters* ctr = reinterpret_cast<Counters*>(base + FL.w.ctr);
   SoupRec<T>* soup = reinterpret_cast<SoupRec<T>*>(base + FL.w.soup);
-  const int grid = fr_grid(p);
+  const int grid = fr_grid(p);                 // per-leaf kernels
+  const int ngrid = p.grid > 0 ? p.grid : 2048;  // near-pair kernels, as in the descent
   int n_launch = 0;
   auto mark = [&]() {
     if (p.events && n_launch < p.n_events)
@@ -1653,16 +1682,14 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   na.fr_state = f->state;
   na.fr_meta = reinterpret_cast<uint8_t*>(fa.meta);
   if (p.certify) {
-    launch_near_certify<T, true>(p.n_iter, dim3(grid), dim3(p.block), st, soup, na);
+    launch_near_certify<T, true>(p.n_iter, dim3(ngrid), dim3(p.block), st, soup, na);
     mark();
     na.near_ = na.fb;
     na.near_tail = na.fb_tail;
   }
-  hipLaunchKernelGGL((k_near<T, 0, false, true>), dim3(grid), dim3(p.block), 0, st, soup, na);
+  hipLaunchKernelGGL((k_near<T, 0, false, true>), dim3(ngrid), dim3(p.block), 0, st, soup, na);
   mark();
   hipLaunchKernelGGL(k_fr_group, dim3(grid), dim3(kFrBlock), 0, st, fa);
-  mark();
-  hipLaunchKernelGGL(k_fr_count, dim3(grid), dim3(kFrBlock), 0, st, fa);
   mark();
   hipLaunchKernelGGL(k_fr_scan, dim3(1), dim3(kScanThreads), 0, st, fa, (uint32_t)grid);
   mark();
