@@ -63,6 +63,9 @@ WORKLOADS = {
                         "gaps U(0,0.1), full icosphere cascades, FP32", True),
     "big_small": ("bumped sphere R=20 subdivision 7 (327680 tris) + 2000 R=0.5 subdivision-3 spheres "
                   "on its surface, FP32", False),
+    "lattice_forces": ("1000 bumped spheres on a 10x10x10 lattice, subdivision 3-5, radii logU[0.5,2], "
+                       "gaps U(0,0.1), full icosphere cascades, FP32; contact forces: points closer than eps "
+                       "merged, force law K_s = 1000, per-particle force and torque (dem_contact_forces)", False),
     "lattice_frontier": ("1000 bumped spheres on a 10x10x10 lattice, subdivision 3-5, radii logU[0.5,2], "
                          "gaps U(0,0.1), full icosphere cascades, FP32; persistent active sets "
                          "(dem_frontier_step, one level of widening / narrowing per step)", True),
@@ -75,7 +78,7 @@ def workload(name: str):
         raise SystemExit(f"unknown workload {name}; one of {sorted(WORKLOADS)}")
     make = {"two_spheres_s3_f64": sg.two_spheres_s3_f64, "two_spheres_s5": sg.two_spheres_s5_hier, "lattice": sg.lattice1000,
             "lattice_fwd_bwd": sg.lattice1000, "big_small": sg.big_plus_small,
-            "lattice_frontier": sg.lattice1000}[name]
+            "lattice_frontier": sg.lattice1000, "lattice_forces": sg.lattice1000}[name]
     desc, backward = WORKLOADS[name]
     return make(), desc, backward
 
@@ -410,6 +413,93 @@ def run_frontier_bench(torch, api, ds, args, params_kw, desc, log):
     return out
 
 
+FORCE_BYTES_PER_CONTACT = 48  # pi, pj, ti, tj, x, n of a contact (40 B) + its two epsilons (8 B)
+FORCE_BYTES_PER_MERGED = 56   # pi, pj, members, x, n, f of a merged contact (FP32)
+
+
+def run_forces_bench(torch, api, ds, scene, args, params_kw, desc, log):
+    """lattice_forces: contacts (dem_find_contacts) then dem_contact_forces
+    (merging, force law, per-particle force and torque) per perturbed step."""
+    from paper_2105_12415_amd import autotune
+    K = args.steps
+    p = api.make_params("hier", **params_kw)
+    eng = api.ContactEngine(ds, p, contact_capacity=args.contact_capacity, energy_k=1e4)
+    if not args.no_autotune and not params_kw:
+        autotune.apply_stored(eng)
+    step = Step(ds, eng, False, K, torch)
+    step.pose(0)
+    eng.run()
+    mass = torch.as_tensor(np.array([q.radius ** 3 for q in scene.particles]), dtype=ds.dtype, device=ds.device)
+    centre = torch.as_tensor(np.array([q.centre for q in scene.particles]).T.copy(), dtype=ds.dtype,
+                             device=ds.device)
+    fe = api.ForceEngine(ds, eng.contacts.capacity)
+
+    def fstep(k):
+        step(k)
+        fe.run(eng.contacts, mass, centre, with_group=False)
+
+    for k in range(K):
+        fstep(k)
+        if eng.check() or fe.check():
+            raise RuntimeError(f"device status {eng.check():#x} / {fe.check():#x} in eager step {k}")
+    ms_fwd, _, g0 = time_graph(torch, step, K, args.warmup)
+    del g0
+    ms, ms_wall, g1 = time_graph(torch, fstep, K, args.warmup)
+    del g1
+    if fe.check():
+        raise RuntimeError(f"device status {fe.check():#x} after graph replay")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f_ms, n_c, n_m = 0.0, 0, 0
+    for k in range(K):
+        step(k)
+        e0.record()
+        fe.run(eng.contacts, mass, centre, with_group=False)
+        e1.record()
+        torch.cuda.synchronize()
+        f_ms += e0.elapsed_time(e1)
+        n_c += eng.count()
+        n_m += int(fe.merged.count.item())
+    f_ms, n_c, n_m = f_ms / K, n_c / K, n_m / K
+    st = eng.stats_dict()
+    evals = float(np.sum(st["evals"]))
+    log(f"[bench] forces: step {ms:.3f} ms (contacts only {ms_fwd:.3f}); force pass {f_ms:.3f} ms for "
+        f"{n_c:.0f} contacts -> {n_m:.0f} merged")
+    bytes_ = FORCE_BYTES_PER_CONTACT * n_c + FORCE_BYTES_PER_MERGED * n_m
+    achieved = bytes_ / (f_ms * 1e-3) / 1e9
+    return {"metric": METRIC, "value": evals / (ms * 1e-3), "unit": "tri-pair evals/s", "n_gpus": 1, "steps": K,
+            "warmup": args.warmup, "ms_per_step": ms, "ms_per_step_wall": ms_wall, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{args.workload}: {desc}; per-step rigid perturbation, {K} steps captured in "
+                       "one HIP graph (contacts + forces)", "particles": ds.n_particles,
+                       "triangles_all_levels": ds.n_tris, "candidate_pairs": ds.n_pairs, "k_s": 1000.0,
+                       "merge_scale": 1.0, "mass": "radius^3", "centre": "particle centre"},
+            "roofline": {"bound": "hbm", "kernel": "dem_contact_forces (all kernels of the pass)",
+                         "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                         "traffic": None, "traffic_note": "no counter summary for this pass",
+                         "bytes_per_contact": FORCE_BYTES_PER_CONTACT, "bytes_per_merged": FORCE_BYTES_PER_MERGED},
+            "forces": {"ms": f_ms, "contacts": n_c, "merged": n_m, "contacts_per_s": n_c / (f_ms * 1e-3),
+                       "contacts_only_ms_per_step": ms_fwd}}
+
+
+def forces_cpu_baseline(scene, n_sample: int):
+    import oracle
+    from oracle import forces as of
+    fs = oracle.fine_scene(scene)
+    rng = np.random.default_rng(12345)
+    P = np.asarray(scene.pairs)
+    idx = np.sort(rng.choice(len(P), min(n_sample, len(P)), replace=False))
+    c = oracle.find_contacts(fs, pairs=P[idx])
+    mass = np.array([q.radius ** 3 for q in scene.particles])
+    centre = np.array([q.centre for q in scene.particles])
+    t0 = time.perf_counter()
+    r = of.contact_forces(fs, c, mass, centre, pairs=P[idx])
+    dt = time.perf_counter() - t0
+    return {"value": len(c["d"]) / dt, "unit": "contacts/s", "cores": 1, "kind": "oracle",
+            "sample": f"force pass (merging, force law, per-particle sums) over the {len(c['d'])} contacts of "
+                      f"{len(idx)} seeded candidate pairs ({len(r['f'])} merged) in {dt:.2f} s, FP64 numpy/scipy",
+            "seconds": dt}
+
+
 def cpu_baseline(scene, n_sample: int, backward: bool):
     import oracle
     fs = oracle.fine_scene(scene)
@@ -481,6 +571,13 @@ def main():
     log(f"[bench] {args.workload}: {desc}; {ds.n_particles} particles, {ds.n_tris} triangles, "
         f"{ds.n_pairs} candidate pairs, {ds.n_fine_pairs()} fine pairs")
 
+    if args.workload == "lattice_forces":
+        out = run_forces_bench(torch, api, ds, scene, args, params_kw, desc, log)
+        if not args.no_cpu:
+            log("[bench] cpu baseline (oracle force pass) ...")
+            out["cpu_baseline"] = forces_cpu_baseline(scene, args.cpu_pairs)
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "lattice_frontier":
         out = run_frontier_bench(torch, api, ds, args, params_kw, desc, log)
         if not args.no_cpu:

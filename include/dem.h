@@ -472,6 +472,64 @@ dem_status dem_frontier_step(const dem_scene* scene, const dem_params* p, const 
                              dem_stats* dev_stats, uint32_t* dev_status, double* dev_energy,
                              dem_stream_t stream);
 
+/* ------------------------------------------------------------------ forces */
+
+/*
+ * Merged contact points and their forces (Section 2: force of a contact
+ * point; implementation note on redundant contact points).  Device SoA,
+ * caller-owned.  Merged contact m joins particles pi[m] and pj[m]; x is the
+ * mean of its group's contact points, n the mean of their normals n(c), f the
+ * force on pi[m] (pj[m] receives -f).  Order is unspecified.
+ */
+typedef struct {
+  int64_t capacity;
+  int32_t* pi;        /* [capacity] */
+  int32_t* pj;        /* [capacity] */
+  void* x;            /* [3][capacity] */
+  void* n;            /* [3][capacity] */
+  void* f;            /* [3][capacity] */
+  int32_t* members;   /* [capacity] contacts merged into it */
+  uint32_t* count;    /* device scalar: merged contacts (may exceed capacity) */
+} dem_merged;
+
+/* Bytes of device workspace dem_contact_forces needs for contact lists of
+ * up to contact_capacity entries (hash of cells, links, group sums).  0 on
+ * bad input. */
+size_t dem_contact_forces_workspace_bytes(int64_t contact_capacity);
+
+/*
+ * dem_contact_forces -- merge redundant contact points and apply the force
+ * law to every merged point.
+ *
+ * Merging (implementation note of Section 2: points closer than eps become
+ * one average point): two contact points of the same particle pair whose
+ * distance is below merge_scale * (eps_i + eps_j) / 2 are in the same group,
+ * transitively; a group becomes one merged contact at the mean point with
+ * the mean normal.  merge_scale = 1 is the paper's rule; 0 keeps every
+ * contact on its own.
+ * Force (Section 2): F = n/|n| K_s (1 - |n|/eps_i) sqrt(1/(1/M_i + 1/M_j))
+ * on p_i and -F on p_j, with n the merged normal; n = 0 (intersecting
+ * triangles) gives no force.  Torque about the given centres:
+ * (x - centre) x force.
+ *
+ * contacts   the output of dem_find_contacts or dem_frontier_step (its device
+ *            count is read on the device).
+ * mass       device [n_particles], centre device [3][n_particles] (scene
+ *            precision).
+ * out        merged contacts; overflow sets DEM_DEV_CONTACT_OVERFLOW.
+ * group      device [contacts->capacity] or NULL: merged index of every input
+ *            contact.
+ * force, torque  device [3][n_particles] or NULL, ACCUMULATED into (caller
+ *            zeroes them).
+ * dev_status DEM_DEV_* bits are OR-ed in (not cleared); a full cell hash or a
+ *            merge that does not settle within its step bound sets
+ *            DEM_DEV_QUEUE_OVERFLOW.
+ */
+dem_status dem_contact_forces(const dem_scene* scene, const dem_contacts* contacts, const void* mass,
+                              const void* centre, double k_s, double merge_scale, const dem_merged* out,
+                              int32_t* group, void* force, void* torque, void* workspace,
+                              size_t workspace_bytes, uint32_t* dev_status, dem_stream_t stream);
+
 const char* dem_status_string(dem_status s);
 
 /* Library version string ("dem <major>.<minor> gfx950"). */

@@ -29,7 +29,8 @@ DEM_MAX_CHILDREN = 16
 EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "dem_workspace_bytes",
            "dem_find_contacts", "dem_contact_backward", "dem_status_string", "dem_version",
            "dem_default_tree_opts", "dem_build_surrogate_tree", "dem_surrogate_tree_free",
-           "dem_frontier_workspace_bytes", "dem_frontier_init", "dem_frontier_step")
+           "dem_frontier_workspace_bytes", "dem_frontier_init", "dem_frontier_step",
+           "dem_contact_forces_workspace_bytes", "dem_contact_forces")
 
 
 class BuildOpts(C.Structure):
@@ -95,6 +96,11 @@ class Stats(C.Structure):
                 ("frontier_collapsed", C.c_uint64)]
 
 
+class Merged(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("pi", C.c_void_p), ("pj", C.c_void_p), ("x", C.c_void_p),
+                ("n", C.c_void_p), ("f", C.c_void_p), ("members", C.c_void_p), ("count", C.c_void_p)]
+
+
 class Frontier(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("leaves", C.c_void_p * 2), ("state", C.c_void_p),
                 ("memory_capacity", C.c_int64), ("memory", C.c_void_p)]
@@ -148,6 +154,11 @@ def lib():
         L.dem_frontier_step.argtypes = [C.POINTER(Scene), C.POINTER(Params), C.POINTER(Frontier),
                                         C.POINTER(Contacts), vp, C.c_size_t, vp, vp, vp, vp]
         L.dem_frontier_step.restype = C.c_int
+        L.dem_contact_forces_workspace_bytes.argtypes = [C.c_int64]
+        L.dem_contact_forces_workspace_bytes.restype = C.c_size_t
+        L.dem_contact_forces.argtypes = [C.POINTER(Scene), C.POINTER(Contacts), vp, vp, C.c_double, C.c_double,
+                                         C.POINTER(Merged), vp, vp, vp, vp, C.c_size_t, vp, vp]
+        L.dem_contact_forces.restype = C.c_int
         L.dem_status_string.argtypes = [C.c_int]
         L.dem_status_string.restype = C.c_char_p
         L.dem_version.argtypes = []

@@ -587,6 +587,85 @@ class FrontierEngine:
                 "d": c.d[:n].double().cpu().numpy(), "energy": float(self.energy.item())}
 
 
+@dataclass
+class MergedBuffers:
+    capacity: int
+    pi: torch.Tensor
+    pj: torch.Tensor
+    x: torch.Tensor
+    n: torch.Tensor
+    f: torch.Tensor
+    members: torch.Tensor
+    count: torch.Tensor
+
+    @staticmethod
+    def alloc(capacity: int, dtype, device) -> "MergedBuffers":
+        cap = max(1, int(capacity))
+        z = lambda *s, dt=torch.int32: torch.zeros(*s, dtype=dt, device=device)
+        return MergedBuffers(cap, z(cap), z(cap), z(3, cap, dt=dtype), z(3, cap, dt=dtype), z(3, cap, dt=dtype),
+                             z(cap), z(1))
+
+    def c(self) -> _abi.Merged:
+        m = _abi.Merged()
+        m.capacity = self.capacity
+        m.pi, m.pj, m.x, m.n, m.f, m.members, m.count = (
+            t.data_ptr() for t in (self.pi, self.pj, self.x, self.n, self.f, self.members, self.count))
+        return m
+
+
+class ForceEngine:
+    """dem_contact_forces for one scene: merged contact points, their forces
+    and per-particle force and torque, from a contact list of up to
+    ``contact_capacity`` entries (the output of ContactEngine or
+    FrontierEngine)."""
+
+    def __init__(self, ds: DeviceScene, contact_capacity: int, merged_capacity: Optional[int] = None):
+        self.ds = ds
+        dev = ds.device
+        self.contact_capacity = int(contact_capacity)
+        nbytes = lib().dem_contact_forces_workspace_bytes(self.contact_capacity)
+        if nbytes == 0:
+            raise DemError("dem_contact_forces_workspace_bytes rejected the capacity")
+        self.ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=dev)
+        self.ws_ptr = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        self.ws_bytes = int(nbytes)
+        self.merged = MergedBuffers.alloc(merged_capacity or self.contact_capacity, ds.dtype, dev)
+        self.group = torch.zeros(max(1, self.contact_capacity), dtype=torch.int32, device=dev)
+        self.force = torch.zeros(3, ds.n_particles, dtype=ds.dtype, device=dev)
+        self.torque = torch.zeros(3, ds.n_particles, dtype=ds.dtype, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def run(self, contacts: ContactBuffers, mass: torch.Tensor, centre: torch.Tensor, k_s: float = 1000.0,
+            merge_scale: float = 1.0, with_group: bool = True):
+        """Enqueue: force and torque are zeroed, then accumulated."""
+        assert contacts.capacity <= self.contact_capacity
+        assert mass.shape == (self.ds.n_particles,) and mass.dtype == self.ds.dtype and mass.is_contiguous()
+        assert centre.shape == (3, self.ds.n_particles) and centre.dtype == self.ds.dtype and centre.is_contiguous()
+        self.force.zero_()
+        self.torque.zero_()
+        self.status.zero_()
+        cs = contacts.c()
+        mc = self.merged.c()
+        st = lib().dem_contact_forces(C.byref(self.ds.c), C.byref(cs), _ptr(mass), _ptr(centre), float(k_s),
+                                      float(merge_scale), C.byref(mc), _ptr(self.group) if with_group else None,
+                                      _ptr(self.force), _ptr(self.torque), C.c_void_p(self.ws_ptr), self.ws_bytes,
+                                      _ptr(self.status), C.c_void_p(torch.cuda.current_stream(self.ds.device).cuda_stream))
+        check(st, "dem_contact_forces")
+
+    def check(self) -> int:
+        torch.cuda.synchronize(self.ds.device)
+        return int(self.status.item()) & 0xFFFFFFFF
+
+    def result(self, n_contacts: int) -> dict:
+        m = self.merged
+        k = min(int(m.count.item()) & 0xFFFFFFFF, m.capacity)
+        return {"pi": m.pi[:k].cpu().numpy(), "pj": m.pj[:k].cpu().numpy(),
+                "x": m.x[:, :k].double().cpu().numpy().T, "n": m.n[:, :k].double().cpu().numpy().T,
+                "f": m.f[:, :k].double().cpu().numpy().T, "members": m.members[:k].cpu().numpy(),
+                "group": self.group[:n_contacts].cpu().numpy(),
+                "force": self.force.double().cpu().numpy().T, "torque": self.torque.double().cpu().numpy().T}
+
+
 class DemContactEnergy(torch.autograd.Function):
     """E(verts) = k * sum over contacts of max(0, eps_i + eps_j - d)^2.
 

@@ -1355,6 +1355,544 @@ __global__ void k_fr_mem_clear(unsigned long long* mem, int64_t n) {
     mem[k] = kMemEmpty;
 }
 
+// ------------------------------------------------------------------ contact forces
+// dem_contact_forces (Section 2: force of a contact point, merging of
+// redundant points).  Cells are cubes of side r / sqrt(3) (r = the merge
+// radius of the particle pair), shrunk by 1e-5, so two points of one cell are
+// closer than r and a cell's points belong to one group without any test.
+//   k_cf_clear   empty the cell table (hash of (particle pair, cell) keys)
+//   k_cf_insert  every contact's key into the table; points per slot
+//   k_cf_range   every occupied slot a compact cell id and a contiguous range
+//                of the point order (blocks take contiguous slot chunks and
+//                reserve their ids and ranges with one atomic each)
+//   k_cf_place   every contact into its cell's range
+//   k_cf_cells   per cell: smallest contact index m, bounding box; every
+//                point's parent := m (the cells start as stars); a 64-bit key
+//                collision is reported
+//   k_cf_link    per (cell, neighbouring cell) with offsets up to 2 in one
+//                half-space (each cell pair once): if the boxes come closer
+//                than r and some pair of their points is closer than r, the
+//                two cells join (union-find, links from the larger root to
+//                the smaller: a group's root is its smallest contact index)
+//   k_cf_sum     per cell: its points' sums added at the group root (FP64);
+//                the root of every point
+//   k_cf_emit    one merged contact per root: mean point and normal, the
+//                force, per-particle force and torque
+//   k_cf_group   merged index of every input contact (optional output)
+constexpr unsigned long long kCellEmpty = ~0ull;
+constexpr int kCellProbes = 64;
+constexpr int kNbr = 62;                    // neighbouring cells of one half-space
+constexpr uint32_t kLinkBudget = 1u << 16;  // parent reads per thread in one kernel
+constexpr double kCellShrink = 0.57735026918962576 * (1.0 - 1e-5);  // cell side / r
+
+template <typename T>
+struct ForceArgs {
+  const int32_t* pi;
+  const int32_t* pj;
+  const int32_t* ti;
+  const int32_t* tj;
+  const T* x;          // [3][ccap]
+  const T* n;
+  int64_t ccap;
+  const uint32_t* ccount;
+  const T* teps;
+  int n_tris;
+  T scale;
+  // cell table (tmask + 1 slots)
+  unsigned long long* keys;
+  uint32_t* scnt;      // points per slot
+  int32_t* sid;        // compact cell id of an occupied slot
+  uint64_t tmask;
+  uint32_t* n_cells;   // [2]: cells, points placed
+  // cells (compact ids, up to ccap)
+  uint32_t* coff;      // first position of the cell's range
+  uint32_t* ccnt;
+  uint32_t* cfill;
+  int32_t* cmin;       // smallest contact index of the cell
+  T* box;              // [6][ccap]: min xyz, max xyz
+  // per contact
+  int32_t* pcell;      // cell id of the contact (-1: none)
+  int32_t* order;      // contacts ordered by cell
+  int32_t* parent;
+  int32_t* root;
+  int32_t* mslot;
+  double* acc;         // [7][ccap]: point sums, normal sums, members (at group roots)
+  // force law
+  const T* mass;
+  const T* centre;     // [3][n_particles]
+  int n_particles;
+  T k_s;
+  // outputs
+  int32_t* opi;
+  int32_t* opj;
+  T* ox;
+  T* on;
+  T* of;
+  int32_t* omem;
+  uint32_t* ocount;
+  int64_t ocap;
+  int32_t* group;
+  T* force;
+  T* torque;
+  uint32_t* status;
+};
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ unsigned long long cell_key(int pi, int pj, long long cx, long long cy, long long cz) {
+  unsigned long long h = mix64(((unsigned long long)(uint32_t)pi << 32) | (uint32_t)pj);
+  h = mix64(h ^ (unsigned long long)cx);
+  h = mix64(h ^ (unsigned long long)cy);
+  h = mix64(h ^ (unsigned long long)cz);
+  return h == kCellEmpty ? h ^ 1ull : h;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t cf_count(const ForceArgs<T>& a) {
+  return (uint32_t)min((uint64_t)*a.ccount, (uint64_t)a.ccap);
+}
+
+// Whether contact c names triangles and particles this scene has (else it is
+// skipped and flagged).
+template <typename T>
+__device__ __forceinline__ bool cf_valid(const ForceArgs<T>& a, uint32_t c) {
+  return (uint32_t)a.ti[c] < (uint32_t)a.n_tris && (uint32_t)a.tj[c] < (uint32_t)a.n_tris &&
+         (uint32_t)a.pi[c] < (uint32_t)a.n_particles && (uint32_t)a.pj[c] < (uint32_t)a.n_particles;
+}
+
+// Merge radius of the contact's particle pair: scale * (eps_i + eps_j) / 2.
+template <typename T>
+__device__ __forceinline__ T cf_radius(const ForceArgs<T>& a, uint32_t c) {
+  return a.scale * T(0.5) * (a.teps[a.ti[c]] + a.teps[a.tj[c]]);
+}
+
+template <typename T>
+__device__ __forceinline__ void cf_cell(const ForceArgs<T>& a, uint32_t c, T r, long long& cx, long long& cy,
+                                        long long& cz) {
+  const T inv = T(1) / (r * T(kCellShrink));
+  cx = (long long)floor(a.x[c] * inv);
+  cy = (long long)floor(a.x[a.ccap + c] * inv);
+  cz = (long long)floor(a.x[2 * a.ccap + c] * inv);
+}
+
+// Slot of a key in the cell table, -1 if absent.
+template <typename T>
+__device__ __forceinline__ int cf_find(const ForceArgs<T>& a, unsigned long long key) {
+  uint64_t slot = mix64(key) & a.tmask;
+  for (int k = 0; k < kCellProbes; ++k) {
+    const unsigned long long kk = a.keys[slot];
+    if (kk == key) return (int)slot;
+    if (kk == kCellEmpty) return -1;
+    slot = (slot + 1) & a.tmask;
+  }
+  return -1;
+}
+
+// Root of x (device-coherent reads: parents change under other lanes'
+// links); path halving stores ancestors only.  Parents have smaller indices
+// than their children, so there are no cycles.  -1 when the budget runs out.
+__device__ int uf_root(int32_t* parent, int x, uint32_t& budget) {
+  while (budget) {
+    --budget;
+    const int p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p == x) return x;
+    const int g = __hip_atomic_load(parent + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (g != p) __hip_atomic_store(parent + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = g;
+  }
+  return -1;
+}
+
+// Root estimate from plain (possibly stale) reads: equal estimates for two
+// points prove they are already in one group (groups only ever join).
+__device__ __forceinline__ int uf_root_plain(const int32_t* parent, int x) {
+  for (int k = 0; k < 64; ++k) {
+    const int p = parent[x];
+    if (p == x) return x;
+    x = p;
+  }
+  return -1;
+}
+
+__device__ void uf_union(int32_t* parent, int a, int b, uint32_t& budget, uint32_t* status) {
+  while (budget) {
+    a = uf_root(parent, a, budget);
+    b = uf_root(parent, b, budget);
+    if (a < 0 || b < 0) break;
+    if (a == b) return;
+    const int hi = max(a, b), lo = min(a, b);
+    if (atomicCAS(parent + hi, hi, lo) == hi) return;
+  }
+  atomicOr(status, DEM_DEV_QUEUE_OVERFLOW);
+}
+
+template <typename T>
+__global__ void k_cf_clear(ForceArgs<T> a, uint64_t n) {
+  for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < n; k += (uint64_t)gridDim.x * blockDim.x) {
+    a.keys[k] = kCellEmpty;
+    a.scnt[k] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 2) a.n_cells[threadIdx.x] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_insert(ForceArgs<T> a) {
+  const uint32_t cnt = cf_count(a);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
+    a.parent[c] = (int32_t)c;
+    a.pcell[c] = -1;
+    a.cfill[c] = 0;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) a.acc[(size_t)k * a.ccap + c] = 0.0;
+    if (!cf_valid(a, c)) {
+      atomicOr(a.status, DEM_DEV_BAD_TREE);
+      continue;
+    }
+    if (!(a.scale > T(0))) continue;
+    const T r = cf_radius(a, c);
+    if (!(r > T(0))) continue;
+    long long cx, cy, cz;
+    cf_cell(a, c, r, cx, cy, cz);
+    const unsigned long long key = cell_key(a.pi[c], a.pj[c], cx, cy, cz);
+    uint64_t slot = mix64(key) & a.tmask;
+    int k = 0;
+    for (; k < kCellProbes; ++k) {
+      const unsigned long long old = atomicCAS(a.keys + slot, kCellEmpty, key);
+      if (old == kCellEmpty || old == key) break;
+      slot = (slot + 1) & a.tmask;
+    }
+    if (k == kCellProbes) {
+      atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+      continue;
+    }
+    a.pcell[c] = (int32_t)slot;  // a slot for now; k_cf_place turns it into a cell id
+    atomicAdd(a.scnt + slot, 1u);
+  }
+}
+
+// Block sum of v over the whole block (every thread gets it).
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_range(ForceArgs<T> a, uint64_t n) {
+  __shared__ unsigned long long red[256 / kWave];
+  __shared__ int woff[256 / kWave][2];
+  __shared__ uint32_t base_c, base_p;
+  const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = min(blockIdx.x * per, n), hi = min(lo + per, n);
+  // pass 1: cells and points of this block's chunk
+  unsigned long long mc = 0, mp = 0;
+  for (uint64_t s = lo + threadIdx.x; s < hi; s += blockDim.x) {
+    const uint32_t m = a.scnt[s];
+    mc += m ? 1u : 0u;
+    mp += m;
+  }
+  const unsigned long long tc = block_sum_u64(mc, red);
+  const unsigned long long tp = block_sum_u64(mp, red);
+  if (threadIdx.x == 0) {
+    base_c = tc ? atomicAdd(a.n_cells, (uint32_t)tc) : 0u;
+    base_p = tp ? atomicAdd(a.n_cells + 1, (uint32_t)tp) : 0u;
+  }
+  __syncthreads();
+  // pass 2: hand out ids and ranges in slot order, a block-wide round at a time
+  uint32_t run_c = base_c, run_p = base_p;
+  for (uint64_t t0 = lo; t0 < hi; t0 += blockDim.x) {
+    const uint64_t s = t0 + threadIdx.x;
+    const uint32_t m = s < hi ? a.scnt[s] : 0u;
+    uint32_t vc = m ? 1u : 0u, vp = m;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t yc = __shfl_up(vc, o), yp = __shfl_up(vp, o);
+      if (lane_id() >= o) { vc += yc; vp += yp; }
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) { woff[w][0] = (int)vc; woff[w][1] = (int)vp; }
+    __syncthreads();
+    uint32_t pc = 0, pp = 0, tcr = 0, tpr = 0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
+      if (k < w) { pc += (uint32_t)woff[k][0]; pp += (uint32_t)woff[k][1]; }
+      tcr += (uint32_t)woff[k][0];
+      tpr += (uint32_t)woff[k][1];
+    }
+    if (m) {
+      const uint32_t id = run_c + pc + vc - 1u;
+      a.sid[s] = (int32_t)id;
+      a.coff[id] = run_p + pp + vp - m;
+      a.ccnt[id] = m;
+    }
+    run_c += tcr;
+    run_p += tpr;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
+  const uint32_t cnt = cf_count(a);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
+    const int slot = a.pcell[c];
+    if (slot < 0) continue;
+    const int id = a.sid[slot];
+    a.pcell[c] = id;
+    a.order[a.coff[id] + atomicAdd(a.cfill + id, 1u)] = (int32_t)c;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
+  const uint32_t nc = a.n_cells[0];
+  for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < nc; id += gridDim.x * blockDim.x) {
+    const uint32_t m = a.ccnt[id];
+    const int32_t* pts = a.order + a.coff[id];
+    int mn = pts[0];
+    T lo[3], hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = a.x[(size_t)k * a.ccap + pts[0]];
+    for (uint32_t k = 1; k < m; ++k) {
+      const int c = pts[k];
+      mn = min(mn, c);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const T v = a.x[(size_t)d * a.ccap + c];
+        lo[d] = min(lo[d], v);
+        hi[d] = max(hi[d], v);
+      }
+    }
+    // one (pair, cell) per cell, else the 64-bit keys of two cells collided
+    const T r = cf_radius(a, (uint32_t)mn);
+    const int pi = a.pi[mn], pj = a.pj[mn];
+    long long cx, cy, cz;
+    cf_cell(a, (uint32_t)mn, r, cx, cy, cz);
+    bool same = true;
+    for (uint32_t k = 0; k < m; ++k) {
+      const int c = pts[k];
+      long long qx, qy, qz;
+      cf_cell(a, (uint32_t)c, r, qx, qy, qz);
+      same &= a.pi[c] == pi && a.pj[c] == pj && qx == cx && qy == cy && qz == cz;
+      a.parent[c] = mn;
+    }
+    if (!same) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+    a.cmin[id] = mn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a.box[(size_t)k * a.ccap + id] = lo[k];
+      a.box[(size_t)(3 + k) * a.ccap + id] = hi[k];
+    }
+  }
+}
+
+// Neighbour offsets (dx, dy, dz) of one half-space ((dz, dy, dx)
+// lexicographically after zero), |d| <= 2 per axis: the 13 adjacent ones
+// (largest |d| = 1) first, then the 49 others.
+constexpr int kNbrAdjacent = 13;
+__constant__ signed char kCfOff[kNbr][3] = {
+    {1, 0, 0}, {-1, 1, 0}, {0, 1, 0}, {1, 1, 0}, {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {-1, 0, 1},
+    {0, 0, 1}, {1, 0, 1}, {-1, 1, 1}, {0, 1, 1}, {1, 1, 1}, {2, 0, 0}, {-2, 1, 0}, {2, 1, 0},
+    {-2, 2, 0}, {-1, 2, 0}, {0, 2, 0}, {1, 2, 0}, {2, 2, 0}, {-2, -2, 1}, {-1, -2, 1}, {0, -2, 1},
+    {1, -2, 1}, {2, -2, 1}, {-2, -1, 1}, {2, -1, 1}, {-2, 0, 1}, {2, 0, 1}, {-2, 1, 1}, {2, 1, 1},
+    {-2, 2, 1}, {-1, 2, 1}, {0, 2, 1}, {1, 2, 1}, {2, 2, 1}, {-2, -2, 2}, {-1, -2, 2}, {0, -2, 2},
+    {1, -2, 2}, {2, -2, 2}, {-2, -1, 2}, {-1, -1, 2}, {0, -1, 2}, {1, -1, 2}, {2, -1, 2}, {-2, 0, 2},
+    {-1, 0, 2}, {0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {-2, 1, 2}, {-1, 1, 2}, {0, 1, 2}, {1, 1, 2},
+    {2, 1, 2}, {-2, 2, 2}, {-1, 2, 2}, {0, 2, 2}, {1, 2, 2}, {2, 2, 2}};
+
+// One thread per (cell, neighbour offset): if the neighbouring cell exists,
+// its box comes closer than r to the cell's box and the two are not yet one
+// group, the cell's points within r of that box look for a point of the
+// neighbour closer than r; one is enough to join the two cells.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1) {
+  const uint64_t nc = a.n_cells[0];
+  const uint64_t total = nc * (uint64_t)(k1 - k0);
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t A = (uint32_t)(t % nc);
+    const int k = k0 + (int)(t / nc);
+    const int dx = kCfOff[k][0], dy = kCfOff[k][1], dz = kCfOff[k][2];
+    const int ma = a.cmin[A];
+    const T r = cf_radius(a, (uint32_t)ma);
+    const T r2 = r * r;
+    const int pi = a.pi[ma], pj = a.pj[ma];
+    long long cx, cy, cz;
+    cf_cell(a, (uint32_t)ma, r, cx, cy, cz);
+    const int slot = cf_find(a, cell_key(pi, pj, cx + dx, cy + dy, cz + dz));
+    if (slot < 0) continue;
+    const int B = a.sid[slot];
+    const int mb = a.cmin[B];
+    if (a.pi[mb] != pi || a.pj[mb] != pj) continue;  // a colliding key (reported by k_cf_cells)
+    T bl[3], bh[3], gap2 = T(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      bl[k] = a.box[(size_t)k * a.ccap + B];
+      bh[k] = a.box[(size_t)(3 + k) * a.ccap + B];
+      const T g = max(max(bl[k] - a.box[(size_t)(3 + k) * a.ccap + A], a.box[(size_t)k * a.ccap + A] - bh[k]), T(0));
+      gap2 += g * g;
+    }
+    if (!(gap2 < r2)) continue;
+    const int ra = uf_root_plain(a.parent, ma), rb = uf_root_plain(a.parent, mb);
+    if (ra >= 0 && ra == rb) continue;  // already one group
+    const int32_t* pa = a.order + a.coff[A];
+    const int32_t* pb = a.order + a.coff[B];
+    const uint32_t na = a.ccnt[A], nb = a.ccnt[B];
+    bool close = false;
+    for (uint32_t i = 0; i < na && !close; ++i) {
+      const int p = pa[i];
+      const T xp = a.x[p], yp = a.x[a.ccap + p], zp = a.x[2 * a.ccap + p];
+      const T gx = max(max(bl[0] - xp, xp - bh[0]), T(0));
+      const T gy = max(max(bl[1] - yp, yp - bh[1]), T(0));
+      const T gz = max(max(bl[2] - zp, zp - bh[2]), T(0));
+      if (!(gx * gx + gy * gy + gz * gz < r2)) continue;
+      for (uint32_t j = 0; j < nb; ++j) {
+        const int q = pb[j];
+        const T ex = a.x[q] - xp, ey = a.x[a.ccap + q] - yp, ez = a.x[2 * a.ccap + q] - zp;
+        if (ex * ex + ey * ey + ez * ez < r2) {
+          close = true;
+          break;
+        }
+      }
+    }
+    if (close) {
+      uint32_t budget = kLinkBudget;
+      uf_union(a.parent, ma, mb, budget, a.status);
+    }
+  }
+}
+
+// Merging: per cell, its points' sums go to the group root in one set of
+// atomics.  Without merging (or for points in no cell): per point.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_sum(ForceArgs<T> a) {
+  const uint32_t cnt = cf_count(a);
+  const uint32_t nc = (a.scale > T(0)) ? a.n_cells[0] : 0u;
+  const uint32_t total = nc + cnt;
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < total; w += gridDim.x * blockDim.x) {
+    uint32_t budget = kLinkBudget;
+    if (w < nc) {
+      const uint32_t id = w;
+      int r = uf_root(a.parent, a.cmin[id], budget);
+      if (r < 0) {
+        atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+        r = a.cmin[id];
+      }
+      const int32_t* pts = a.order + a.coff[id];
+      double s[7] = {0, 0, 0, 0, 0, 0, 0};
+      for (uint32_t k = 0; k < a.ccnt[id]; ++k) {
+        const int c = pts[k];
+        a.root[c] = r;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          s[d] += (double)a.x[(size_t)d * a.ccap + c];
+          s[3 + d] += (double)a.n[(size_t)d * a.ccap + c];
+        }
+        s[6] += 1.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 7; ++k) unsafeAtomicAdd(a.acc + (size_t)k * a.ccap + r, s[k]);
+    } else {
+      const uint32_t c = w - nc;
+      if (a.pcell[c] >= 0) continue;  // summed with its cell
+      a.root[c] = (int32_t)c;
+      if (!cf_valid(a, c)) continue;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a.acc[(size_t)d * a.ccap + c] = (double)a.x[(size_t)d * a.ccap + c];
+        a.acc[(size_t)(3 + d) * a.ccap + c] = (double)a.n[(size_t)d * a.ccap + c];
+      }
+      a.acc[(size_t)6 * a.ccap + c] = 1.0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_emit(ForceArgs<T> a) {
+  const uint32_t cnt = cf_count(a);
+  for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    const bool is_root = c < cnt && a.root[c] == (int32_t)c && cf_valid(a, c);
+    uint32_t ok;
+    const uint32_t slot = wave_append(is_root, a.ocount, ok);
+    if (!is_root) continue;
+    a.mslot[c] = (int32_t)slot;
+    if (!ok || slot >= (uint64_t)a.ocap) {
+      atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
+      continue;
+    }
+    const double m = a.acc[(size_t)6 * a.ccap + c];
+    double xm[3], nm[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xm[k] = a.acc[(size_t)k * a.ccap + c] / m;
+      nm[k] = a.acc[(size_t)(3 + k) * a.ccap + c] / m;
+    }
+    const int pi = a.pi[c], pj = a.pj[c];
+    const double ln = sqrt(nm[0] * nm[0] + nm[1] * nm[1] + nm[2] * nm[2]);
+    const double ei = (double)a.teps[a.ti[c]];
+    const double mi = (double)a.mass[pi], mj = (double)a.mass[pj];
+    // F = n/|n| K_s (1 - |n|/eps_i) sqrt(1 / (1/M_i + 1/M_j)); no direction for n = 0
+    const double mag = ln > 0.0 ? (double)a.k_s * (1.0 - ln / ei) * sqrt(1.0 / (1.0 / mi + 1.0 / mj)) / ln : 0.0;
+    double f[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] = mag * nm[k];
+    a.opi[slot] = pi;
+    a.opj[slot] = pj;
+    a.omem[slot] = (int32_t)m;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a.ox[(size_t)k * a.ocap + slot] = (T)xm[k];
+      a.on[(size_t)k * a.ocap + slot] = (T)nm[k];
+      a.of[(size_t)k * a.ocap + slot] = (T)f[k];
+    }
+    const size_t P = (size_t)a.n_particles;
+    if (a.force) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        atomic_add_t(a.force + k * P + pi, (T)f[k]);
+        atomic_add_t(a.force + k * P + pj, (T)(-f[k]));
+      }
+    }
+    if (a.torque) {
+      // (x - centre) x force, for both particles
+      double ri[3], rj[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ri[k] = xm[k] - (double)a.centre[k * P + pi];
+        rj[k] = xm[k] - (double)a.centre[k * P + pj];
+      }
+      const double ti[3] = {ri[1] * f[2] - ri[2] * f[1], ri[2] * f[0] - ri[0] * f[2], ri[0] * f[1] - ri[1] * f[0]};
+      const double tj[3] = {-(rj[1] * f[2] - rj[2] * f[1]), -(rj[2] * f[0] - rj[0] * f[2]),
+                            -(rj[0] * f[1] - rj[1] * f[0])};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        atomic_add_t(a.torque + k * P + pi, (T)ti[k]);
+        atomic_add_t(a.torque + k * P + pj, (T)tj[k]);
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_group(ForceArgs<T> a) {
+  const uint32_t cnt = cf_count(a);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x)
+    a.group[c] = cf_valid(a, c) ? a.mslot[a.root[c]] : -1;
+}
+
+__global__ void k_cf_reset(uint32_t* ocount) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ocount = 0;
+}
+
 // ------------------------------------------------------------------ host
 IterParams make_iter(const dem_params& p) {
   IterParams ip;
@@ -1700,6 +2238,106 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
 
+
+// ------------------------------------------------------------------ contact forces host side
+struct CfLayout {
+  uint64_t table;
+  size_t keys, scnt, sid, counters, coff, ccnt, cfill, cmin, box, pcell, order, parent, root, mslot, acc, total;
+};
+
+CfLayout cf_layout(int64_t cap) {
+  CfLayout L;
+  const uint64_t want = std::max<uint64_t>(1024, 2 * (uint64_t)cap);
+  L.table = 1;
+  while (L.table < want) L.table <<= 1;
+  const size_t T = L.table, C = (size_t)cap;
+  size_t o = 0;
+  L.keys = o; o = align_up(o + 8 * T, 256);
+  L.scnt = o; o = align_up(o + 4 * T, 256);
+  L.sid = o; o = align_up(o + 4 * T, 256);
+  L.counters = o; o = align_up(o + 8, 256);
+  L.coff = o; o = align_up(o + 4 * C, 256);
+  L.ccnt = o; o = align_up(o + 4 * C, 256);
+  L.cfill = o; o = align_up(o + 4 * C, 256);
+  L.cmin = o; o = align_up(o + 4 * C, 256);
+  L.box = o; o = align_up(o + 8 * 6 * C, 256);  // room for FP64 boxes
+  L.pcell = o; o = align_up(o + 4 * C, 256);
+  L.order = o; o = align_up(o + 4 * C, 256);
+  L.parent = o; o = align_up(o + 4 * C, 256);
+  L.root = o; o = align_up(o + 4 * C, 256);
+  L.mslot = o; o = align_up(o + 4 * C, 256);
+  L.acc = o; o = align_up(o + 8 * 7 * C, 256);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+dem_status run_forces(const dem_scene* s, const dem_contacts* c, const void* mass, const void* centre, double k_s,
+                      double scale, const dem_merged* out, int32_t* group, void* force, void* torque, void* ws,
+                      const CfLayout& L, uint32_t* status, hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  ForceArgs<T> a;
+  a.pi = c->pi; a.pj = c->pj; a.ti = c->ti; a.tj = c->tj;
+  a.x = static_cast<const T*>(c->x);
+  a.n = static_cast<const T*>(c->n);
+  a.ccap = c->capacity;
+  a.ccount = c->count;
+  a.teps = static_cast<const T*>(s->tri_eps);
+  a.n_tris = s->n_tris;
+  a.scale = (T)scale;
+  a.keys = reinterpret_cast<unsigned long long*>(base + L.keys);
+  a.scnt = reinterpret_cast<uint32_t*>(base + L.scnt);
+  a.sid = reinterpret_cast<int32_t*>(base + L.sid);
+  a.tmask = L.table - 1;
+  a.n_cells = reinterpret_cast<uint32_t*>(base + L.counters);
+  a.coff = reinterpret_cast<uint32_t*>(base + L.coff);
+  a.ccnt = reinterpret_cast<uint32_t*>(base + L.ccnt);
+  a.cfill = reinterpret_cast<uint32_t*>(base + L.cfill);
+  a.cmin = reinterpret_cast<int32_t*>(base + L.cmin);
+  a.box = reinterpret_cast<T*>(base + L.box);
+  a.pcell = reinterpret_cast<int32_t*>(base + L.pcell);
+  a.order = reinterpret_cast<int32_t*>(base + L.order);
+  a.parent = reinterpret_cast<int32_t*>(base + L.parent);
+  a.root = reinterpret_cast<int32_t*>(base + L.root);
+  a.mslot = reinterpret_cast<int32_t*>(base + L.mslot);
+  a.acc = reinterpret_cast<double*>(base + L.acc);
+  a.mass = static_cast<const T*>(mass);
+  a.centre = static_cast<const T*>(centre);
+  a.n_particles = s->n_particles;
+  a.k_s = (T)k_s;
+  a.opi = out->pi; a.opj = out->pj;
+  a.ox = static_cast<T*>(out->x);
+  a.on = static_cast<T*>(out->n);
+  a.of = static_cast<T*>(out->f);
+  a.omem = out->members;
+  a.ocount = out->count;
+  a.ocap = out->capacity;
+  a.group = group;
+  a.force = static_cast<T*>(force);
+  a.torque = static_cast<T*>(torque);
+  a.status = status;
+  const dim3 g(2048), b(256), gt(4096);
+  hipLaunchKernelGGL(k_cf_reset, dim3(1), dim3(64), 0, st, out->count);
+  if (c->capacity > 0) {
+    const bool merge = scale > 0.0;
+    hipLaunchKernelGGL(k_cf_clear<T>, gt, b, 0, st, a, merge ? (uint64_t)L.table : (uint64_t)0);
+    hipLaunchKernelGGL(k_cf_insert<T>, g, b, 0, st, a);
+    if (merge) {
+      hipLaunchKernelGGL(k_cf_range<T>, gt, b, 0, st, a, (uint64_t)L.table);
+      hipLaunchKernelGGL(k_cf_place<T>, g, b, 0, st, a);
+      hipLaunchKernelGGL(k_cf_cells<T>, g, b, 0, st, a);
+      // adjacent cells first: they join most of a patch, so that the distant
+      // offsets mostly find both cells in one group already
+      hipLaunchKernelGGL(k_cf_link<T>, g, b, 0, st, a, 0, kNbrAdjacent);
+      hipLaunchKernelGGL(k_cf_link<T>, g, b, 0, st, a, kNbrAdjacent, kNbr);
+    }
+    hipLaunchKernelGGL(k_cf_sum<T>, g, b, 0, st, a);
+    hipLaunchKernelGGL(k_cf_emit<T>, g, b, 0, st, a);
+    if (group) hipLaunchKernelGGL(k_cf_group<T>, g, b, 0, st, a);
+  }
+  return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1840,6 +2478,34 @@ dem_status dem_frontier_step(const dem_scene* scene, const dem_params* pp, const
   if (scene->precision == DEM_F64)
     return run_frontier_step<double>(scene, p, f, out, workspace, FL, dev_stats, dev_status, dev_energy, st);
   return run_frontier_step<float>(scene, p, f, out, workspace, FL, dev_stats, dev_status, dev_energy, st);
+}
+
+size_t dem_contact_forces_workspace_bytes(int64_t contact_capacity) {
+  if (contact_capacity < 0 || contact_capacity > (int64_t)0x7FFFFFFF) return 0;
+  return cf_layout(std::max<int64_t>(contact_capacity, 1)).total;
+}
+
+dem_status dem_contact_forces(const dem_scene* scene, const dem_contacts* c, const void* mass,
+                              const void* centre, double k_s, double merge_scale, const dem_merged* out,
+                              int32_t* group, void* force, void* torque, void* workspace,
+                              size_t workspace_bytes, uint32_t* dev_status, dem_stream_t stream) {
+  if (!scene_ok(scene) || !c || !c->count || !out || !out->count || !mass || !centre || !dev_status || !workspace)
+    return DEM_ERR_ARG;
+  if (c->capacity < 0 || c->capacity > (int64_t)0x7FFFFFFF) return DEM_ERR_ARG;
+  if (c->capacity > 0 && (!c->pi || !c->pj || !c->ti || !c->tj || !c->x || !c->n)) return DEM_ERR_ARG;
+  if (out->capacity < 0 || out->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
+  if (out->capacity > 0 && (!out->pi || !out->pj || !out->x || !out->n || !out->f || !out->members))
+    return DEM_ERR_ARG;
+  if (!(k_s >= 0.0) || !(k_s < INFINITY) || !(merge_scale >= 0.0) || !(merge_scale < INFINITY)) return DEM_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
+  CfLayout L = cf_layout(std::max<int64_t>(c->capacity, 1));
+  if (workspace_bytes < L.total) return DEM_ERR_CAPACITY;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (scene->precision == DEM_F64)
+    return run_forces<double>(scene, c, mass, centre, k_s, merge_scale, out, group, force, torque, workspace, L,
+                              dev_status, st);
+  return run_forces<float>(scene, c, mass, centre, k_s, merge_scale, out, group, force, torque, workspace, L,
+                           dev_status, st);
 }
 
 const char* dem_status_string(dem_status s) {

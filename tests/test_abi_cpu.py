@@ -44,7 +44,7 @@ def test_ctypes_layout_matches_c_compiler(tmp_path):
     compiler makes of include/dem.h."""
     structs = {"dem_build_opts": _abi.BuildOpts, "dem_hierarchy": _abi.Hierarchy, "dem_scene": _abi.Scene,
                "dem_params": _abi.Params, "dem_contacts": _abi.Contacts, "dem_stats": _abi.Stats,
-               "dem_frontier": _abi.Frontier}
+               "dem_frontier": _abi.Frontier, "dem_merged": _abi.Merged}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dem.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')

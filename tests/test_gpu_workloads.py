@@ -227,3 +227,85 @@ def test_lattice_frontier_fixed_point(step):
         d = d1.get(key, d2.get(key))
         assert abs(d - 0.1) <= 1e-6, (key, d)
     ds.set_pose(None)
+
+
+def test_lattice_forces_sampled_pairs():
+    """dem_contact_forces on the full lattice contact list (6.5 M contacts):
+    Newton's third law and the balance of angular momentum over the whole
+    scene, and for sampled candidate pairs the merged groups and forces
+    against the oracle's (partition compared with a band of 1e-4 of the merge
+    radius around the threshold, values on groups with the same members)."""
+    from scipy.spatial import cKDTree
+
+    from oracle import forces as of
+    scene, ds = _scene("lattice")
+    ds.set_pose(None)
+    eng = _engine(ds)
+    assert eng.run() == 0
+    res = eng.result()
+    mass = np.array([p.radius ** 3 for p in scene.particles])
+    centre = np.array([p.centre for p in scene.particles])
+    fe = api.ForceEngine(ds, eng.contacts.capacity)
+    fe.run(eng.contacts, torch.as_tensor(mass, dtype=ds.dtype, device="cuda:0"),
+           torch.as_tensor(centre.T.copy(), dtype=ds.dtype, device="cuda:0"))
+    assert fe.check() == 0
+    g = fe.result(len(res["d"]))
+    say(f"[gpu-test] {len(res['d'])} contacts merged into {len(g['f'])}")
+    assert 0 < len(g["f"]) < len(res["d"])
+    fmax = np.abs(g["f"]).max()
+    assert np.abs(g["force"].sum(0)).max() <= 1e-5 * fmax * np.sqrt(len(g["f"]))
+    L = g["torque"] + np.cross(centre, g["force"])
+    assert np.abs(L.sum(0)).max() <= 1e-4 * fmax * np.sqrt(len(g["f"]))
+    # sampled pairs against the oracle
+    fs = oracle.fine_scene(scene)
+    P = np.asarray(scene.pairs)
+    idx = _sample(scene, 10, 31)
+    ref = oracle.find_contacts(fs, pairs=P[idx])
+    o = of.contact_forces(fs, ref, mass, centre, pairs=P[idx])
+    sel = {(int(P[k, 0]), int(P[k, 1])) for k in idx}
+    lti = res["ti"] - ds.fine_begin_host[res["pi"]]
+    ltj = res["tj"] - ds.fine_begin_host[res["pj"]]
+    gk = {(int(a), int(b), int(c), int(d)): k for k, (a, b, c, d) in enumerate(zip(res["pi"], res["pj"], lti, ltj))
+          if (int(a), int(b)) in sel}
+    ok = {(int(P[idx[p], 0]), int(P[idx[p], 1]), int(a), int(b)): k
+          for k, (p, a, b) in enumerate(zip(ref["pair"], ref["ti"], ref["tj"]))}
+    common = sorted(set(gk) & set(ok))
+    for key in set(gk) ^ set(ok):  # contact-set differences only inside the threshold band
+        k = ok.get(key)
+        assert k is not None and abs(ref["d"][k] - 0.1) <= 1e-6 or k is None, key
+    x, *_ = of.contact_points(fs, ref, pairs=P[idx])
+    band, r = 1e-4, 0.05
+    n_same = 0
+    for pk in sel:
+        keys = [k for k in common if k[:2] == pk]
+        if not keys:
+            continue
+        xo = x[[ok[k] for k in keys]]
+        gl = np.array([g["group"][gk[k]] for k in keys])
+        n = len(keys)
+        e = cKDTree(xo).query_pairs(r * (1 + band), output_type="ndarray").reshape(-1, 2)
+        de = np.linalg.norm(xo[e[:, 0]] - xo[e[:, 1]], axis=1)
+        strict = _cc(n, e[de < r * (1 - band)])
+        loose = _cc(n, e[de < r * (1 + band)])
+        for comp in np.unique(strict):
+            assert len(np.unique(gl[strict == comp])) == 1
+        for grp in np.unique(gl):
+            assert len(np.unique(loose[gl == grp])) == 1
+        ol = np.array([o["labels"][ok[k]] for k in keys])
+        o_row = {lab: i for i, lab in enumerate(np.unique(o["labels"]))}
+        for lab in np.unique(ol):
+            mem = np.nonzero(ol == lab)[0]
+            gg = np.unique(gl[mem])
+            if len(gg) == 1 and np.sum(gl == gg[0]) == len(mem) and g["members"][gg[0]] == len(mem):
+                assert np.allclose(g["f"][gg[0]], o["f"][o_row[lab]], atol=2e-4 * of.K_S)
+                assert np.allclose(g["x"][gg[0]], o["x"][o_row[lab]], atol=4e-5 * max(1.0, np.abs(o["x"][o_row[lab]]).max()))
+                n_same += 1
+    assert n_same > 10
+
+
+def _cc(n, edges):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    _, lab = connected_components(coo_matrix((np.ones(len(edges)), (edges[:, 0], edges[:, 1])), shape=(n, n)),
+                                  directed=False)
+    return lab
