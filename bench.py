@@ -251,7 +251,7 @@ from paper_2105_12415_amd.autotune import STORED as TUNE_CACHE  # noqa: E402
 
 
 def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capacity, tune="cache",
-             tune_out=None):
+             tune_out=None, half_depths=0):
     """tune: "cache" (parameters the autotuner stored for this scene, else
     time them now), "live" (time them now) or "off" (library defaults)."""
     from paper_2105_12415_amd import autotune
@@ -280,6 +280,10 @@ def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capac
             autotune.store(tune_out, autotune.signature(eng), best)
         step.pose(0)
         eng.run()
+    if half_depths and mode == "hier":
+        eng.p.half_depths = half_depths
+        step.pose(0)
+        eng.run()
     ms_graph, ms_wall, graph = time_graph(torch, step, K, warmup)
     status = eng.check()
     if status:
@@ -292,7 +296,10 @@ def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capac
 def launch_knobs(eng) -> dict:
     """Every tunable launch/tile knob of the engine's parameters."""
     from paper_2105_12415_amd import autotune
-    return {k: autotune.get_knob(eng.p, k) for k in autotune.hier_space(eng.ds.n_levels_max)}
+    knobs = {k: autotune.get_knob(eng.p, k) for k in autotune.hier_space(eng.ds.n_levels_max)}
+    if eng.p.half_depths:
+        knobs["half_depths"] = eng.p.half_depths
+    return knobs
 
 
 def kernel_sources_sha256() -> str:
@@ -538,6 +545,9 @@ def main():
     ap.add_argument("--retune", action="store_true",
                     help="time the autotuner's candidates now instead of using the stored result")
     ap.add_argument("--tune-out", default=None, help="write a result timed now to this JSON file")
+    ap.add_argument("--half-depths", type=int, default=0,
+                    help="run the descent's Newton iteration in half precision at tree depths below this "
+                         "(applied on top of the stored launch parameters)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -590,7 +600,7 @@ def main():
                                                      params_kw, args.contact_capacity,
                                                      tune="off" if args.no_autotune else
                                                      ("live" if args.retune else "cache"),
-                                                     tune_out=args.tune_out)
+                                                     tune_out=args.tune_out, half_depths=args.half_depths)
     evals = float(np.sum(st["evals"]))
     log(f"[bench] hier: {ms:.3f} ms/step (wall {ms_wall:.3f}), {evals:.4g} evals/step, "
         f"{st['contacts']:.0f} contacts, near {st['near']:.0f}")

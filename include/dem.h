@@ -266,6 +266,11 @@ typedef struct {
   int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..64) */
   int32_t seed_chunk;     /* root-pair items are seed_chunk x seed_chunk triangle ranges (1..16; default 8) */
   int32_t frontier_grid;  /* dem_frontier_step: blocks of the per-leaf kernels (0 = 4096; <= 8192) */
+  int32_t half_depths;    /* FP32 scenes, HIER mode: the descent at tree depths d < half_depths runs
+                             the Newton iteration in half precision (reduced precision on coarse
+                             surrogate levels, an extension named in the conclusion, Section 7).
+                             The bound along its direction stays FP32 with its rounding slack, so the
+                             contact set is unchanged.  0 (default) = off */
   /* Per-depth overrides of grid and batch_items for the descent launches
    * (index = tree depth; 0 = use grid / batch_items).  Depths differ in item
    * count and shape (few large root chunks at depth 0, millions of 4 x 4

@@ -76,7 +76,7 @@ class Params(C.Structure):
                 ("init_centroid", C.c_int32), ("dense_distance", C.c_int32), ("certify", C.c_int32),
                 ("prune_exact", C.c_int32), ("energy_k", C.c_double), ("block", C.c_int32), ("grid", C.c_int32),
                 ("batch_items", C.c_int32), ("flat_tile_i", C.c_int32), ("flat_tile_j", C.c_int32),
-                ("seed_chunk", C.c_int32), ("frontier_grid", C.c_int32),
+                ("seed_chunk", C.c_int32), ("frontier_grid", C.c_int32), ("half_depths", C.c_int32),
                 ("level_grid", C.c_int32 * DEM_MAX_LEVELS), ("level_batch", C.c_int32 * DEM_MAX_LEVELS),
                 ("queue_capacity", C.c_int64), ("near_capacity", C.c_int64),
                 ("events", C.POINTER(C.c_void_p)), ("n_events", C.c_int32)]

@@ -45,6 +45,14 @@ DEM_HD float ab_(float a) { return fabsf(a); }
 DEM_HD double ab_(double a) { return fabs(a); }
 DEM_HD float sq_(float a) { return sqrtf(a); }
 DEM_HD double sq_(double a) { return sqrt(a); }
+// Half precision (the reduced-precision iteration): plain arithmetic in
+// _Float16, fused multiply-add in one rounding.  NaN and infinity only ever
+// reach the search direction, whose bound is formed in FP32 (see
+// iterate_bound_mixed).
+DEM_HD _Float16 fm_(_Float16 a, _Float16 b, _Float16 c) { return __builtin_fmaf16(a, b, c); }
+DEM_HD _Float16 mn_(_Float16 a, _Float16 b) { return a < b ? a : b; }
+DEM_HD _Float16 mx_(_Float16 a, _Float16 b) { return a > b ? a : b; }
+DEM_HD _Float16 ab_(_Float16 a) { return a < _Float16(0) ? -a : a; }
 
 template <typename T>
 struct V3 {
@@ -106,6 +114,7 @@ DEM_HD float rcp_fast(float x) {
 #endif
 }
 DEM_HD double rcp_fast(double x) { return 1.0 / x; }
+DEM_HD _Float16 rcp_fast(_Float16 x) { return _Float16(1) / x; }
 DEM_HD float rsq_fast(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rsqf(x);
@@ -201,10 +210,10 @@ DEM_HD void iterate_theta(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const Iter
 // direction u between the two iterate points:
 //     d(A, B) >= min_k u.b_k - max_k u.a_k.
 // Returns the bound (-inf if the two points coincide: nothing is pruned).
-template <typename T, int N>
-DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip) {
-  T a1, b1, a2, b2;
-  iterate_theta<T, N>(A, B, D0, ip, a1, b1, a2, b2);
+// Lower bound along the unit direction between the points of parameters
+// (a1, b1) on A and (a2, b2) on B.
+template <typename T>
+DEM_HD T bound_along(const Tri<T>& A, const Tri<T>& B, V3<T> D0, T a1, T b1, T a2, T b2) {
   // w = p2 - p1 between the two (feasible) iterate points
   V3<T> w = fma3(a2, B.e1, fma3(b2, B.e2, fma3(-a1, A.e1, fma3(-b1, A.e2, -D0))));
   T ww = dot(w, w);
@@ -213,6 +222,31 @@ DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterPar
   T hA = mx_(T(0), mx_(dot(u, A.e1), dot(u, A.e2)));
   T hB = mn_(T(0), mn_(dot(u, B.e1), dot(u, B.e2))) - dot(u, D0);
   return ww > T(0) ? hB - hA : -T(INFINITY);
+}
+
+template <typename T, int N>
+DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip) {
+  T a1, b1, a2, b2;
+  iterate_theta<T, N>(A, B, D0, ip, a1, b1, a2, b2);
+  return bound_along(A, B, D0, a1, b1, a2, b2);
+}
+
+// Reduced-precision variant for FP32 scenes: the Newton iteration runs in
+// half precision on the pair-local edges, offsets and Hessian diagonals; the
+// bound along the resulting direction is formed in FP32.  The bound holds for
+// any direction, so the half-precision rounding only changes how much is
+// pruned, and the FP32 rounding slack (bound_slack) still covers the bound.
+template <int N>
+DEM_HD float iterate_bound_mixed(const Tri<float>& A, const Tri<float>& B, V3<float> D0, const IterParams& ip) {
+  auto h3 = [](V3<float> v) { return V3<_Float16>{(_Float16)v.x, (_Float16)v.y, (_Float16)v.z}; };
+  Tri<_Float16> Ah, Bh;
+  Ah.e1 = h3(A.e1); Ah.e2 = h3(A.e2); Ah.ia = (_Float16)A.ia; Ah.ib = (_Float16)A.ib;
+  Bh.e1 = h3(B.e1); Bh.e2 = h3(B.e2); Bh.ia = (_Float16)B.ia; Bh.ib = (_Float16)B.ib;
+  _Float16 a1, b1, a2, b2;
+  iterate_theta<_Float16, N>(Ah, Bh, h3(D0), ip, a1, b1, a2, b2);
+  // back in FP32: a non-finite parameter becomes a vertex (still a valid direction)
+  auto f = [](_Float16 v) { float x = (float)v; return (x >= 0.0f && x <= 1.0f) ? x : 0.0f; };
+  return bound_along(A, B, D0, f(a1), f(b1), f(a2), f(b2));
 }
 
 // Rounding slack of the bound above: the computed bound of a pair at true

@@ -351,6 +351,7 @@ struct LevelArgs {
   int dense;
   int batch;
   uint8_t* mark;             // lazy flattening: survival flags of surrogates (else null)
+  int half;                  // this depth runs the Newton iteration in half precision
   IterParams ip;
 };
 
@@ -437,7 +438,7 @@ constexpr uint32_t kOutPrune = 0, kOutKeep = 1, kOutUnfold = 2, kOutNear = 3;
 // produced at the previous depth (hardware dispatches workgroups
 // round-robin over the 8 XCDs, so block b runs on XCD b % 8): a subtree of
 // the descent stays on one XCD, whose L2 already holds its triangles.
-template <typename T, int N, int BLOCK>
+template <typename T, int N, int BLOCK, bool HALF>
 __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
   // LDS sized to the block: one item per thread, stages of two rounds;
   // under 20 KB at BLOCK = 256 so that eight blocks fit in a CU's 160 KB
@@ -511,7 +512,12 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
         Tri<T> A = load_tri(soup, ci, cbi, cci, pi_, kfi);
         Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_, kfj);
         V3<T> D0 = A.v0 - B.v0;
-        T L = iterate_bound<T, N>(A, B, D0, a.ip);
+        T L;
+        if constexpr (HALF && sizeof(T) == 4) {
+          L = iterate_bound_mixed<N>(A, B, D0, a.ip);
+        } else {
+          L = iterate_bound<T, N>(A, B, D0, a.ip);
+        }
         T delta = A.eps + B.eps;
         bool fine = (cci == 0) && (ccj == 0);
         bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
@@ -1936,6 +1942,7 @@ bool params_ok(const dem_params& p) {
   if (p.near_capacity < kSeg || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.grid < 0) return false;
   if (p.frontier_grid < 0 || p.frontier_grid > kFrMaxGrid) return false;
+  if (p.half_depths < 0 || p.half_depths > DEM_MAX_LEVELS) return false;
   for (int d = 0; d < DEM_MAX_LEVELS; ++d) {
     if (p.level_grid[d] < 0) return false;
     if (p.level_batch[d] < 0 || p.level_batch[d] > p.block) return false;  // one item per thread
@@ -1946,13 +1953,26 @@ bool params_ok(const dem_params& p) {
 
 // The Newton iteration count is a template parameter so the iteration is
 // fully unrolled; counts 0..8 are instantiated.
-template <typename T, int BLOCK>
-void launch_level_b(int n_iter, dim3 g, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
+template <typename T, int BLOCK, bool HALF>
+void launch_level_h(int n_iter, dim3 g, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
   switch (n_iter) {
-#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_level<T, N, BLOCK>), g, dim3(BLOCK), 0, st, soup, la); break;
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_level<T, N, BLOCK, HALF>), g, dim3(BLOCK), 0, st, soup, la); break;
     DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
 #undef DEM_CASE
   }
+}
+
+// The half-precision iteration is a separate instantiation (FP32 only), so
+// that the FP32 kernel keeps its own register allocation.
+template <typename T, int BLOCK>
+void launch_level_b(int n_iter, dim3 g, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
+  if constexpr (sizeof(T) == 4) {
+    if (la.half) {
+      launch_level_h<T, BLOCK, true>(n_iter, g, st, soup, la);
+      return;
+    }
+  }
+  launch_level_h<T, BLOCK, false>(n_iter, g, st, soup, la);
 }
 
 template <typename T>
@@ -2021,7 +2041,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   mark();
   // per-segment capacities
   const int64_t qseg = p.queue_capacity / kSeg, nseg = p.near_capacity / kSeg;
-  LevelArgs la;
+  LevelArgs la{};
   la.qcap = qseg;
   la.near_ = nearl;
   la.near_tail = ctr->near_tail;
@@ -2045,6 +2065,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         la.depth = lev;
         la.batch = p.level_batch[lev] > 0 ? p.level_batch[lev] : p.batch_items;
         la.mark = fa.lazy ? fa.mark : nullptr;
+        la.half = s->precision == DEM_F32 && lev < p.half_depths;
         const int g = p.level_grid[lev] > 0 ? p.level_grid[lev] : grid;
         launch_level<T>(p.n_iter, dim3(g), dim3(p.block), st, soup, la);
         mark();

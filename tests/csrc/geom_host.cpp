@@ -44,6 +44,20 @@ static void bound_one(const double* P, const float* prm, double* out) {
   ip.init_centroid = (int)prm[4];
   V3<T> D0 = A.v0 - B.v0;
   T L;
+  if constexpr (sizeof(T) == 4) {
+    if (prm[5] > 0.5f) {  // the reduced-precision iteration
+      switch (ip.n_iter) {
+        case 0: L = iterate_bound_mixed<0>(A, B, D0, ip); break;
+        case 4: L = iterate_bound_mixed<4>(A, B, D0, ip); break;
+        case 8: L = iterate_bound_mixed<8>(A, B, D0, ip); break;
+        default: L = -INFINITY;
+      }
+      out[0] = L;
+      out[1] = bound_slack(A, B, D0, T(0));
+      for (int k = 2; k < 7; ++k) out[k] = 0;
+      return;
+    }
+  }
   switch (ip.n_iter) {
     case 0: L = iterate_bound<T, 0>(A, B, D0, ip); break;
     case 1: L = iterate_bound<T, 1>(A, B, D0, ip); break;

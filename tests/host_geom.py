@@ -40,9 +40,10 @@ def exact(pairs, double=True):
             "w2": out[:, 10:13], "feature": out[:, 13].astype(int)}
 
 
-def bound(pairs, double=True, n_iter=4, omega=1.0, areg=1e-4, rho=1e3, centroid=0):
+def bound(pairs, double=True, n_iter=4, omega=1.0, areg=1e-4, rho=1e3, centroid=0, half=False):
+    """half: the reduced-precision iteration (FP32 only)."""
     P = np.ascontiguousarray(np.asarray(pairs, np.float64).reshape(-1, 18))
-    prm = np.array([n_iter, omega, areg, rho, centroid], np.float32)
+    prm = np.array([n_iter, omega, areg, rho, centroid, 1.0 if half else 0.0], np.float32)
     out = np.zeros((len(P), 7))
     lib().geom_bound(P.ctypes.data_as(C.POINTER(C.c_double)), len(P), int(double),
                      prm.ctypes.data_as(C.POINTER(C.c_float)), out.ctypes.data_as(C.POINTER(C.c_double)))
@@ -51,7 +52,7 @@ def bound(pairs, double=True, n_iter=4, omega=1.0, areg=1e-4, rho=1e3, centroid=
 
 def certify(pairs, double=True, omega=1.0, areg=1e-4, rho=1e3, centroid=0):
     P = np.ascontiguousarray(np.asarray(pairs, np.float64).reshape(-1, 18))
-    prm = np.array([4, omega, areg, rho, centroid], np.float32)
+    prm = np.array([4, omega, areg, rho, centroid, 0.0], np.float32)
     out = np.zeros((len(P), 2))
     lib().geom_certify(P.ctypes.data_as(C.POINTER(C.c_double)), len(P), int(double),
                        prm.ctypes.data_as(C.POINTER(C.c_float)), out.ctypes.data_as(C.POINTER(C.c_double)))

@@ -111,3 +111,27 @@ def test_certified_distances_are_exact(double, r, a):
         err = np.abs(c["d"][ok] - ref["d"][ok]) - (r * ref["d"][ok] + a * _h(P)[ok])
         assert np.all(err <= 0), np.max(err)
         assert ok.mean() > 0.3  # it settles a good share of pairs
+
+
+@pytest.mark.parametrize("n_iter,omega", [(4, 1.0), (4, 0.5), (8, 0.7)])
+def test_reduced_precision_iteration_bound_is_safe(n_iter, omega):
+    """The reduced-precision iteration (Newton steps in FP16, bound in FP32)
+    keeps the pruning test safe on every case, including edges and offsets
+    beyond the half-precision range, and prunes nearly as well as the FP32
+    iteration on separated pairs."""
+    P = _cases()
+    big = sg.random_triangle_pairs(2000, seed=25, scale=3e3, spread=2e4)  # offsets beyond 65504
+    tiny = sg.random_triangle_pairs(2000, seed=26, scale=1e-4, spread=3e-4)  # diagonals beyond the range
+    P = np.concatenate([P, big, tiny])
+    ref = oracle.tri_tri_batch(P)
+    b = host_geom.bound(P, False, n_iter=n_iter, omega=omega, half=True)
+    assert np.all(b["L"] - b["slack"] <= ref["d"])
+    f = host_geom.bound(P, False, n_iter=n_iter, omega=omega)
+    far = ref["d"] > _h(P)
+    assert np.mean(b["L"][far] > 0.5 * ref["d"][far]) > 0.9
+    # at the descent's thresholds (delta = 0.1 on unit-size pairs) it keeps few more pairs than FP32
+    sel = ref["d"] < 3.0
+    delta = 0.1 * _h(P)[sel]
+    pruned32 = f["L"][sel] > delta + f["slack"][sel]
+    pruned16 = b["L"][sel] > delta + b["slack"][sel]
+    assert pruned16.sum() >= 0.97 * pruned32.sum()

@@ -468,3 +468,23 @@ def test_certified_hybrid_matches_exact_fallback():
     ref = oracle.find_contacts(oracle.fine_scene(scene))
     compare_sets(scene, ds, r1, ref, TOL["f32"])
     compare_sets(scene, ds, r0, ref, TOL["f32"])
+
+
+@pytest.mark.parametrize("half_depths", [2, 32])
+def test_reduced_precision_iteration_keeps_the_contacts(half_depths):
+    """Newton iterations in half precision on the coarse depths (or all of
+    them): the bound stays FP32, so the contact set and its exact distances
+    are those of the FP32 iteration; pruning changes little."""
+    scene = sg.two_spheres_s5_hier()
+    ds = api.DeviceScene(scene, device="cuda:0")
+    e32 = api.ContactEngine(ds, api.make_params("hier"))
+    assert e32.run() == 0
+    r32, s32 = e32.result(), e32.stats_dict()
+    e16 = api.ContactEngine(ds, api.make_params("hier", half_depths=half_depths))
+    assert e16.run() == 0
+    r16, s16 = e16.result(), e16.stats_dict()
+    k32 = sorted(zip(r32["ti"].tolist(), r32["tj"].tolist(), r32["d"].tolist()))
+    k16 = sorted(zip(r16["ti"].tolist(), r16["tj"].tolist(), r16["d"].tolist()))
+    assert len(k32) > 100 and k32 == k16
+    say(f"evals fp32 {s32['evals'][:3].tolist()} half {s16['evals'][:3].tolist()}")
+    assert s16["evals"].sum() <= 1.05 * s32["evals"].sum()
