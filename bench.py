@@ -538,7 +538,7 @@ def main():
     ap.add_argument("--flat-steps", type=int, default=1)
     ap.add_argument("--no-flat", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=60)
+    ap.add_argument("--cpu-pairs", type=int, default=180)
     ap.add_argument("--contact-capacity", type=int, default=1 << 23)
     ap.add_argument("--param", action="append", default=[], help="dem_params override, e.g. omega=0.5")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
