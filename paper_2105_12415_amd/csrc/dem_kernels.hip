@@ -1419,6 +1419,8 @@ struct ForceArgs {
   // per contact
   int32_t* pcell;      // cell id of the contact (-1: none)
   int32_t* order;      // contacts ordered by cell
+  T* xs;               // [3][ccap] points in cell order
+  T* ns;               // [3][ccap] normals in cell order
   int32_t* parent;
   int32_t* root;
   int32_t* mslot;
@@ -1550,11 +1552,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_cf_insert(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
-    a.parent[c] = (int32_t)c;
     a.pcell[c] = -1;
-    a.cfill[c] = 0;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) a.acc[(size_t)k * a.ccap + c] = 0.0;
     if (!cf_valid(a, c)) {
       atomicOr(a.status, DEM_DEV_BAD_TREE);
       continue;
@@ -1639,6 +1637,7 @@ __global__ void __launch_bounds__(256) k_cf_range(ForceArgs<T> a, uint64_t n) {
       a.sid[s] = (int32_t)id;
       a.coff[id] = run_p + pp + vp - m;
       a.ccnt[id] = m;
+      a.cfill[id] = 0;
     }
     run_c += tcr;
     run_p += tpr;
@@ -1654,7 +1653,13 @@ __global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
     if (slot < 0) continue;
     const int id = a.sid[slot];
     a.pcell[c] = id;
-    a.order[a.coff[id] + atomicAdd(a.cfill + id, 1u)] = (int32_t)c;
+    const uint32_t pos = a.coff[id] + atomicAdd(a.cfill + id, 1u);
+    a.order[pos] = (int32_t)c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a.xs[(size_t)k * a.ccap + pos] = a.x[(size_t)k * a.ccap + c];
+      a.ns[(size_t)k * a.ccap + pos] = a.n[(size_t)k * a.ccap + c];
+    }
   }
 }
 
@@ -1662,37 +1667,38 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
   const uint32_t nc = a.n_cells[0];
   for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < nc; id += gridDim.x * blockDim.x) {
-    const uint32_t m = a.ccnt[id];
-    const int32_t* pts = a.order + a.coff[id];
+    const uint32_t m = a.ccnt[id], o = a.coff[id];
+    const int32_t* pts = a.order + o;
     int mn = pts[0];
     T lo[3], hi[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = a.x[(size_t)k * a.ccap + pts[0]];
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = a.xs[(size_t)k * a.ccap + o];
     for (uint32_t k = 1; k < m; ++k) {
-      const int c = pts[k];
-      mn = min(mn, c);
+      mn = min(mn, pts[k]);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const T v = a.x[(size_t)d * a.ccap + c];
+        const T v = a.xs[(size_t)d * a.ccap + o + k];
         lo[d] = min(lo[d], v);
         hi[d] = max(hi[d], v);
       }
     }
     // one (pair, cell) per cell, else the 64-bit keys of two cells collided
     const T r = cf_radius(a, (uint32_t)mn);
+    const T inv = T(1) / (r * T(kCellShrink));
     const int pi = a.pi[mn], pj = a.pj[mn];
-    long long cx, cy, cz;
-    cf_cell(a, (uint32_t)mn, r, cx, cy, cz);
+    const long long cx = (long long)floor(a.x[mn] * inv), cy = (long long)floor(a.x[a.ccap + mn] * inv),
+                    cz = (long long)floor(a.x[2 * a.ccap + mn] * inv);
     bool same = true;
     for (uint32_t k = 0; k < m; ++k) {
       const int c = pts[k];
-      long long qx, qy, qz;
-      cf_cell(a, (uint32_t)c, r, qx, qy, qz);
-      same &= a.pi[c] == pi && a.pj[c] == pj && qx == cx && qy == cy && qz == cz;
-      a.parent[c] = mn;
+      same &= a.pi[c] == pi && a.pj[c] == pj && (long long)floor(a.xs[o + k] * inv) == cx &&
+              (long long)floor(a.xs[a.ccap + o + k] * inv) == cy && (long long)floor(a.xs[2 * a.ccap + o + k] * inv) == cz;
     }
     if (!same) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
     a.cmin[id] = mn;
+    a.parent[mn] = mn;  // union-find runs over the cells' smallest contacts only
+#pragma unroll
+    for (int k = 0; k < 7; ++k) a.acc[(size_t)k * a.ccap + mn] = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       a.box[(size_t)k * a.ccap + id] = lo[k];
@@ -1749,20 +1755,19 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
     if (!(gap2 < r2)) continue;
     const int ra = uf_root_plain(a.parent, ma), rb = uf_root_plain(a.parent, mb);
     if (ra >= 0 && ra == rb) continue;  // already one group
-    const int32_t* pa = a.order + a.coff[A];
-    const int32_t* pb = a.order + a.coff[B];
+    const T* xa = a.xs + a.coff[A];
+    const T* xb = a.xs + a.coff[B];
+    const size_t C = (size_t)a.ccap;
     const uint32_t na = a.ccnt[A], nb = a.ccnt[B];
     bool close = false;
     for (uint32_t i = 0; i < na && !close; ++i) {
-      const int p = pa[i];
-      const T xp = a.x[p], yp = a.x[a.ccap + p], zp = a.x[2 * a.ccap + p];
+      const T xp = xa[i], yp = xa[C + i], zp = xa[2 * C + i];
       const T gx = max(max(bl[0] - xp, xp - bh[0]), T(0));
       const T gy = max(max(bl[1] - yp, yp - bh[1]), T(0));
       const T gz = max(max(bl[2] - zp, zp - bh[2]), T(0));
       if (!(gx * gx + gy * gy + gz * gz < r2)) continue;
       for (uint32_t j = 0; j < nb; ++j) {
-        const int q = pb[j];
-        const T ex = a.x[q] - xp, ey = a.x[a.ccap + q] - yp, ez = a.x[2 * a.ccap + q] - zp;
+        const T ex = xb[j] - xp, ey = xb[C + j] - yp, ez = xb[2 * C + j] - zp;
         if (ex * ex + ey * ey + ez * ez < r2) {
           close = true;
           break;
@@ -1792,15 +1797,15 @@ __global__ void __launch_bounds__(256) k_cf_sum(ForceArgs<T> a) {
         atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
         r = a.cmin[id];
       }
-      const int32_t* pts = a.order + a.coff[id];
+      const uint32_t o = a.coff[id];
+      const int32_t* pts = a.order + o;
       double s[7] = {0, 0, 0, 0, 0, 0, 0};
       for (uint32_t k = 0; k < a.ccnt[id]; ++k) {
-        const int c = pts[k];
-        a.root[c] = r;
+        a.root[pts[k]] = r;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          s[d] += (double)a.x[(size_t)d * a.ccap + c];
-          s[3 + d] += (double)a.n[(size_t)d * a.ccap + c];
+          s[d] += (double)a.xs[(size_t)d * a.ccap + o + k];
+          s[3 + d] += (double)a.ns[(size_t)d * a.ccap + o + k];
         }
         s[6] += 1.0;
       }
@@ -2263,7 +2268,8 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
 // ------------------------------------------------------------------ contact forces host side
 struct CfLayout {
   uint64_t table;
-  size_t keys, scnt, sid, counters, coff, ccnt, cfill, cmin, box, pcell, order, parent, root, mslot, acc, total;
+  size_t keys, scnt, sid, counters, coff, ccnt, cfill, cmin, box, pcell, order, xs, ns, parent, root, mslot, acc,
+      total;
 };
 
 CfLayout cf_layout(int64_t cap) {
@@ -2284,6 +2290,8 @@ CfLayout cf_layout(int64_t cap) {
   L.box = o; o = align_up(o + 8 * 6 * C, 256);  // room for FP64 boxes
   L.pcell = o; o = align_up(o + 4 * C, 256);
   L.order = o; o = align_up(o + 4 * C, 256);
+  L.xs = o; o = align_up(o + 8 * 3 * C, 256);  // room for FP64
+  L.ns = o; o = align_up(o + 8 * 3 * C, 256);
   L.parent = o; o = align_up(o + 4 * C, 256);
   L.root = o; o = align_up(o + 4 * C, 256);
   L.mslot = o; o = align_up(o + 4 * C, 256);
@@ -2318,6 +2326,8 @@ dem_status run_forces(const dem_scene* s, const dem_contacts* c, const void* mas
   a.box = reinterpret_cast<T*>(base + L.box);
   a.pcell = reinterpret_cast<int32_t*>(base + L.pcell);
   a.order = reinterpret_cast<int32_t*>(base + L.order);
+  a.xs = reinterpret_cast<T*>(base + L.xs);
+  a.ns = reinterpret_cast<T*>(base + L.ns);
   a.parent = reinterpret_cast<int32_t*>(base + L.parent);
   a.root = reinterpret_cast<int32_t*>(base + L.root);
   a.mslot = reinterpret_cast<int32_t*>(base + L.mslot);
