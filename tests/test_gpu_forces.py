@@ -166,3 +166,39 @@ def test_forces_without_contacts():
     ds, res, g, fs, ref, o = run_both(scene)
     assert len(res["d"]) == 0 and len(g["f"]) == 0
     assert np.all(g["force"] == 0) and np.all(g["torque"] == 0)
+
+
+def test_force_pass_in_a_graph_matches_eager():
+    """Contacts + force pass captured in one HIP graph, replayed twice with
+    eager work in between, against the eager pass (sums in different atomic
+    order: force and torque within 1e-5 of their largest entry)."""
+    scene = sg.two_spheres(4, [2, 3, 4], "f32", 2.02, 4, "two_spheres_s4_f32")
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds)
+    assert eng.run() == 0
+    mass, centre = _mass_centre(scene)
+    m = torch.as_tensor(mass, dtype=ds.dtype, device=ds.device)
+    c = torch.as_tensor(centre.T.copy(), dtype=ds.dtype, device=ds.device)
+    fe = api.ForceEngine(ds, eng.contacts.capacity)
+    fe.run(eng.contacts, m, c, with_group=False)
+    assert fe.check() == 0
+    ref = fe.result(0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            eng.forward()
+            fe.run(eng.contacts, m, c, with_group=False)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(2):
+        eng.forward()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert fe.check() == 0 and eng.check() == 0
+        got = fe.result(0)
+        assert len(got["f"]) == len(ref["f"]) and sorted(got["members"].tolist()) == sorted(ref["members"].tolist())
+        fmax = np.abs(ref["force"]).max()
+        assert np.allclose(got["force"], ref["force"], atol=1e-5 * fmax)
+        assert np.allclose(got["torque"], ref["torque"], atol=1e-5 * np.abs(ref["torque"]).max())
