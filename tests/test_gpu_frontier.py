@@ -300,3 +300,30 @@ def test_frontier_steps_in_a_graph_match_eager_steps():
         ra, rb = a.result(), b.result()
         assert sorted(zip(ra["ti"].tolist(), ra["tj"].tolist())) == sorted(zip(rb["ti"].tolist(), rb["tj"].tolist()))
     say(f"{len(a.leaves())} leaves, {len(ra['ti'])} contacts")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_frontier_certified_settling_matches_exact(prec):
+    """certify = 1 settles the frontier's fine pairs from the iterate where the
+    separation bound certifies the distance (the rest by the exact distance):
+    same fixed-point leaves and contact set as exact settling."""
+    sc = _spheres(prec)
+    out = []
+    for cert in (0, 1):
+        ds = api.DeviceScene(sc, device="cuda:0")
+        eng = api.FrontierEngine(ds, api.make_params("hier", certify=cert))
+        eng.init()
+        eng.run_to_fixed_point()
+        r = eng.result()
+        out.append((eng.leaves(), dict(zip(zip(r["ti"].tolist(), r["tj"].tolist()), r["d"].tolist())), eng.stats_dict()))
+    (l0, c0, s0), (l1, c1, s1) = out
+    assert np.array_equal(l0, l1)
+    band = TOL[prec]["band"]
+    for key in set(c0) ^ set(c1):
+        d = c0.get(key, c1.get(key))
+        assert abs(d - 0.1) <= band, key
+    common = set(c0) & set(c1)
+    assert len(common) > 20
+    r_, a_ = TOL[prec]["r"], TOL[prec]["a"]
+    assert all(abs(c0[k] - c1[k]) <= 4 * (r_ * c0[k] + a_ * 0.2) for k in common)
+    assert s1["certified"] > 0
