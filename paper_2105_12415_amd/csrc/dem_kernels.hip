@@ -823,9 +823,13 @@ __device__ __forceinline__ void atomic_add_t(T* p, T v) {
 // atomic per (vertex, component) leaves the block.  Contacts arrive grouped
 // by the surrogate pair they descend from, so a chunk touches few distinct
 // vertices; scattered device-scope float atomics are the costly part.
+// A thread takes kBwdPerThread consecutive contacts.  The child pairs of a
+// surrogate pair are listed with the triangle of particle i varying slowest,
+// so consecutive contacts often share t_i: the contributions of such a run
+// to the vertices of t_i are summed in registers and enter the table once.
 constexpr int kHashSlots = 2048;     // power of two
 constexpr int kHashBits = 11;
-constexpr int kBwdPerThread = 4;     // contacts per thread per chunk
+constexpr int kBwdPerThread = 4;     // consecutive contacts per thread per chunk
 
 template <typename T>
 struct GradHash {
@@ -853,6 +857,33 @@ __device__ __forceinline__ void hash_add(GradHash<T>& H, int vid, T gx, T gy, T 
   unsafeAtomicAdd(grad + 2 * (size_t)n_verts + vid, gz);
 }
 
+// The three vertex contributions of triangle t (gv[v] for vertex v): index
+// loads and first probes are issued together so their latencies overlap.
+template <typename T>
+__device__ __forceinline__ void hash_add_tri(GradHash<T>& H, const int32_t* __restrict__ tv, int n_tris,
+                                             int t, const V3<T>* gv, T* grad, int n_verts) {
+  int vid[3], slot[3], cur[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) vid[v] = tv[(size_t)v * n_tris + t];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const bool nz = gv[v].x != T(0) || gv[v].y != T(0) || gv[v].z != T(0);
+    slot[v] = (int)(((uint32_t)vid[v] * 2654435761u) >> (32 - kHashBits));
+    cur[v] = nz ? atomicCAS(&H.key[slot[v]], -1, vid[v]) : -2;
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    if (cur[v] == -2) continue;
+    if (cur[v] == -1 || cur[v] == vid[v]) {
+      atomicAdd(&H.val[0][slot[v]], gv[v].x);
+      atomicAdd(&H.val[1][slot[v]], gv[v].y);
+      atomicAdd(&H.val[2][slot[v]], gv[v].z);
+    } else {
+      hash_add(H, vid[v], gv[v].x, gv[v].y, gv[v].z, grad, n_verts);  // probe on
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__ soup,
                                                   const int32_t* __restrict__ tv, int n_tris,
@@ -874,9 +905,12 @@ __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__
   __syncthreads();
   double e_acc = 0.0;
   for (uint32_t c0 = blockIdx.x * chunk; c0 < cnt; c0 += gridDim.x * chunk) {
+    const uint32_t cb = c0 + threadIdx.x * kBwdPerThread;
+    int run = -1;      // t_i of the current run
+    V3<T> rg[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // its vertex contributions so far
     for (int j = 0; j < kBwdPerThread; ++j) {
-      const uint32_t c = c0 + j * bdim + threadIdx.x;
-      if (c >= cnt) continue;
+      const uint32_t c = cb + j;
+      if (c >= cnt) break;
       const int ti = cti[c], tj = ctj[c];
       int cbi, cci, pi_, cbj, ccj, pj_;
       Tri<T> A = load_tri(soup, ti, cbi, cci, pi_);
@@ -892,13 +926,21 @@ __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__
       if (!(d > T(0)) || grad == nullptr) continue;
       T g = T(2.0 * k * pen * gE);
       V3<T> u = (T(1) / d) * (cl.q - cl.p);
+      if (ti != run) {
+        if (run >= 0) hash_add_tri(H, tv, n_tris, run, rg, grad, n_verts);
+        run = ti;
+#pragma unroll
+        for (int v = 0; v < 3; ++v) rg[v] = V3<T>{0, 0, 0};
+      }
+      V3<T> gq[3];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        T gi = g * cl.wp[v], gj = -g * cl.wq[v];
-        if (gi != T(0)) hash_add(H, tv[(size_t)v * n_tris + ti], gi * u.x, gi * u.y, gi * u.z, grad, n_verts);
-        if (gj != T(0)) hash_add(H, tv[(size_t)v * n_tris + tj], gj * u.x, gj * u.y, gj * u.z, grad, n_verts);
+        rg[v] = rg[v] + (g * cl.wp[v]) * u;
+        gq[v] = (-g * cl.wq[v]) * u;
       }
+      hash_add_tri(H, tv, n_tris, tj, gq, grad, n_verts);
     }
+    if (run >= 0) hash_add_tri(H, tv, n_tris, run, rg, grad, n_verts);
     __syncthreads();
     for (int s2 = threadIdx.x; s2 < kHashSlots; s2 += bdim) {
       int vid = H.key[s2];
