@@ -311,7 +311,7 @@ def _grad_compare(scene, prec):
     oracle.set_ambiguity_tol(tol["amb"])
     ref = oracle.find_contacts(fs)
     E_ref, g_ref = oracle.energy_grad(fs, ref, 1e4)
-    assert abs(float(E) - E_ref) <= (1e-5 if prec == "f32" else 1e-10) * E_ref
+    assert abs(float(E.detach()) - E_ref) <= (1e-5 if prec == "f32" else 1e-10) * E_ref
     # exclude vertices of pairs with non-unique closest points at this
     # resolution, and of pairs within the threshold band (in or out)
     P = np.asarray(scene.pairs)
@@ -333,6 +333,61 @@ def test_gradient_fp64():
 
 def test_gradient_fp32():
     _grad_compare(sg.two_spheres(4, [2, 3, 4], "f32", sep=2.03, stream_id=44, name="g32"), "f32")
+
+
+def _sub_contacts(cb, ti, tj):
+    """A contact list made of the given (ti, tj) device tensors (the adjoint
+    reads the triangle pair and the count only; other buffers are the
+    originals, unread)."""
+    n = int(ti.numel())
+    return api.ContactBuffers(max(1, n), cb.pi, cb.pj, ti.contiguous(), tj.contiguous(), cb.d, cb.x, cb.n,
+                              torch.tensor([n], dtype=torch.int32, device=ti.device))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_backward_depends_on_the_contact_set_only(prec):
+    """dE/dv is a sum over contacts: a shuffled contact list gives the same
+    gradient and energy up to rounding, and a list split into a short head
+    (1, 2, 3 or 5 contacts: a thread's group of consecutive contacts cut
+    short) and the rest gives two parts that add up to the whole."""
+    if prec == "f32":
+        scene = sg.two_spheres(4, [2, 3, 4], "f32", sep=2.03, stream_id=44, name="g32")
+        rtol = 1e-5
+    else:
+        scene = sg.two_spheres(3, [1, 2, 3], "f64", sep=2.03, stream_id=43, name="g64")
+        rtol = 1e-12
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params("hier"), energy_k=1e4)
+    assert eng.run() == 0
+    n = eng.count()
+    assert n > 100
+    full = eng.contacts
+
+    def grad_of(cb):
+        g = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device="cuda:0")
+        eng.contacts = cb
+        try:
+            eng.backward(g, energy=True)
+            torch.cuda.synchronize()
+        finally:
+            eng.contacts = full
+        assert eng.check() == 0
+        return g.double().cpu().numpy(), float(eng.energy_bwd.item())
+
+    g0, e0 = grad_of(full)
+    gmax = np.abs(g0).max()
+    assert gmax > 0 and e0 > 0
+    ti, tj = full.ti[:n], full.tj[:n]
+    perm = torch.as_tensor(np.random.default_rng(7).permutation(n), device="cuda:0")
+    g1, e1 = grad_of(_sub_contacts(full, ti[perm], tj[perm]))
+    assert np.abs(g1 - g0).max() <= rtol * gmax
+    assert abs(e1 - e0) <= rtol * e0
+    for m in (1, 2, 3, 5):
+        gh, eh = grad_of(_sub_contacts(full, ti[:m], tj[:m]))
+        gr, er = grad_of(_sub_contacts(full, ti[m:], tj[m:]))
+        assert np.abs(gh).max() > 0
+        assert np.abs(gh + gr - g0).max() <= rtol * gmax, m
+        assert abs(eh + er - e0) <= rtol * e0, m
 
 
 # ------------------------------------------------------------------ failure handling
