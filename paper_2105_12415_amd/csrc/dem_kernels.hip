@@ -1753,6 +1753,7 @@ __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
 // lexicographically after zero), |d| <= 2 per axis: the 13 adjacent ones
 // (largest |d| = 1) first, then the 49 others.
 constexpr int kNbrAdjacent = 13;
+static_assert(kNbrAdjacent <= 64 && kNbr - kNbrAdjacent <= 64, "one lane per offset in k_cf_link");
 __constant__ signed char kCfOff[kNbr][3] = {
     {1, 0, 0}, {-1, 1, 0}, {0, 1, 0}, {1, 1, 0}, {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {-1, 0, 1},
     {0, 0, 1}, {1, 0, 1}, {-1, 1, 1}, {0, 1, 1}, {1, 1, 1}, {2, 0, 0}, {-2, 1, 0}, {2, 1, 0},
@@ -1763,62 +1764,101 @@ __constant__ signed char kCfOff[kNbr][3] = {
     {-1, 0, 2}, {0, 0, 2}, {1, 0, 2}, {2, 0, 2}, {-2, 1, 2}, {-1, 1, 2}, {0, 1, 2}, {1, 1, 2},
     {2, 1, 2}, {-2, 2, 2}, {-1, 2, 2}, {0, 2, 2}, {1, 2, 2}, {2, 2, 2}};
 
-// One thread per (cell, neighbour offset): if the neighbouring cell exists,
-// its box comes closer than r to the cell's box and the two are not yet one
-// group, the cell's points within r of that box look for a point of the
-// neighbour closer than r; one is enough to join the two cells.
+// One wave per cell A.  Lane l takes neighbour offset k0 + l (k1 - k0 <= 64)
+// for the cheap tests: the neighbouring cell exists, its box comes closer
+// than r to A's box, and the two are not yet one group.  The neighbours that
+// pass are then taken one at a time by the whole wave: lanes hold A's points
+// (those within r of the neighbour's box) and scan the neighbour's points
+// until some lane finds one closer than r; one is enough to join the cells.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1) {
-  const uint64_t nc = a.n_cells[0];
-  const uint64_t total = nc * (uint64_t)(k1 - k0);
-  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t A = (uint32_t)(t % nc);
-    const int k = k0 + (int)(t / nc);
-    const int dx = kCfOff[k][0], dy = kCfOff[k][1], dz = kCfOff[k][2];
+  const uint32_t nc = a.n_cells[0];
+  const int lane = lane_id();
+  const uint32_t wpb = blockDim.x / kWave;
+  const uint32_t nw = gridDim.x * wpb;
+  const size_t C = (size_t)a.ccap;
+  for (uint32_t A = blockIdx.x * wpb + threadIdx.x / kWave; A < nc; A += nw) {
     const int ma = a.cmin[A];
     const T r = cf_radius(a, (uint32_t)ma);
     const T r2 = r * r;
     const int pi = a.pi[ma], pj = a.pj[ma];
     long long cx, cy, cz;
     cf_cell(a, (uint32_t)ma, r, cx, cy, cz);
-    const int slot = cf_find(a, cell_key(pi, pj, cx + dx, cy + dy, cz + dz));
-    if (slot < 0) continue;
-    const int B = a.sid[slot];
-    const int mb = a.cmin[B];
-    if (a.pi[mb] != pi || a.pj[mb] != pj) continue;  // a colliding key (reported by k_cf_cells)
-    T bl[3], bh[3], gap2 = T(0);
+    T al[3], ah[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      bl[k] = a.box[(size_t)k * a.ccap + B];
-      bh[k] = a.box[(size_t)(3 + k) * a.ccap + B];
-      const T g = max(max(bl[k] - a.box[(size_t)(3 + k) * a.ccap + A], a.box[(size_t)k * a.ccap + A] - bh[k]), T(0));
-      gap2 += g * g;
+    for (int d = 0; d < 3; ++d) {
+      al[d] = a.box[(size_t)d * C + A];
+      ah[d] = a.box[(size_t)(3 + d) * C + A];
     }
-    if (!(gap2 < r2)) continue;
-    const int ra = uf_root_plain(a.parent, ma), rb = uf_root_plain(a.parent, mb);
-    if (ra >= 0 && ra == rb) continue;  // already one group
-    const T* xa = a.xs + a.coff[A];
-    const T* xb = a.xs + a.coff[B];
-    const size_t C = (size_t)a.ccap;
-    const uint32_t na = a.ccnt[A], nb = a.ccnt[B];
-    bool close = false;
-    for (uint32_t i = 0; i < na && !close; ++i) {
-      const T xp = xa[i], yp = xa[C + i], zp = xa[2 * C + i];
-      const T gx = max(max(bl[0] - xp, xp - bh[0]), T(0));
-      const T gy = max(max(bl[1] - yp, yp - bh[1]), T(0));
-      const T gz = max(max(bl[2] - zp, zp - bh[2]), T(0));
-      if (!(gx * gx + gy * gy + gz * gz < r2)) continue;
-      for (uint32_t j = 0; j < nb; ++j) {
-        const T ex = xb[j] - xp, ey = xb[C + j] - yp, ez = xb[2 * C + j] - zp;
-        if (ex * ex + ey * ey + ez * ez < r2) {
-          close = true;
-          break;
+    const int k = k0 + lane;
+    int B = -1, mb = -1;
+    if (k < k1) {
+      const int slot = cf_find(a, cell_key(pi, pj, cx + kCfOff[k][0], cy + kCfOff[k][1], cz + kCfOff[k][2]));
+      if (slot >= 0) {
+        const int b = a.sid[slot];
+        const int m = a.cmin[b];
+        if (a.pi[m] == pi && a.pj[m] == pj) {  // else a colliding key (reported by k_cf_cells)
+          T gap2 = T(0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const T g = max(max(a.box[(size_t)d * C + b] - ah[d], al[d] - a.box[(size_t)(3 + d) * C + b]), T(0));
+            gap2 += g * g;
+          }
+          if (gap2 < r2) {
+            const int ra = uf_root_plain(a.parent, ma), rb = uf_root_plain(a.parent, m);
+            if (!(ra >= 0 && ra == rb)) {
+              B = b;
+              mb = m;
+            }
+          }
         }
       }
     }
-    if (close) {
-      uint32_t budget = kLinkBudget;
-      uf_union(a.parent, ma, mb, budget, a.status);
+    unsigned long long todo = __ballot(B >= 0);
+    const T* xa = a.xs + a.coff[A];
+    const uint32_t na = a.ccnt[A];
+    while (todo) {
+      const int src = __ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      const int Bw = __builtin_amdgcn_readfirstlane(__shfl(B, src));
+      const int mbw = __builtin_amdgcn_readfirstlane(__shfl(mb, src));
+      // an earlier neighbour of this wave may have joined them already
+      const int ra = uf_root_plain(a.parent, ma), rb = uf_root_plain(a.parent, mbw);
+      if (ra >= 0 && ra == rb) continue;
+      T bl[3], bh[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        bl[d] = a.box[(size_t)d * C + Bw];
+        bh[d] = a.box[(size_t)(3 + d) * C + Bw];
+      }
+      const T* xb = a.xs + a.coff[Bw];
+      const uint32_t nb = a.ccnt[Bw];
+      bool close = false;
+      for (uint32_t i0 = 0; i0 < na; i0 += kWave) {
+        const uint32_t i = i0 + (uint32_t)lane;
+        T xp = T(0), yp = T(0), zp = T(0);
+        bool act = i < na;
+        if (act) {
+          xp = xa[i];
+          yp = xa[C + i];
+          zp = xa[2 * C + i];
+          const T gx = max(max(bl[0] - xp, xp - bh[0]), T(0));
+          const T gy = max(max(bl[1] - yp, yp - bh[1]), T(0));
+          const T gz = max(max(bl[2] - zp, zp - bh[2]), T(0));
+          act = gx * gx + gy * gy + gz * gz < r2;
+        }
+        if (__ballot(act) == 0ull) continue;
+        for (uint32_t j = 0; j < nb; ++j) {
+          const T ex = xb[j] - xp, ey = xb[C + j] - yp, ez = xb[2 * C + j] - zp;
+          close = close || (act && ex * ex + ey * ey + ez * ez < r2);
+          if ((j & 7u) == 7u && __ballot(close) != 0ull) break;
+        }
+        if (__ballot(close) != 0ull) break;
+      }
+      if (__ballot(close) != 0ull && lane == 0) {
+        uint32_t budget = kLinkBudget;
+        uf_union(a.parent, ma, mbw, budget, a.status);
+      }
     }
   }
 }
