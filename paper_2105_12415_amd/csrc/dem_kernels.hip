@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <cstring>
 
@@ -141,6 +142,20 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* tail, uint3
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename V>
+__device__ __forceinline__ V wave_min(V v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <typename V>
+__device__ __forceinline__ V wave_max(V v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
   return v;
 }
 
@@ -1705,46 +1720,57 @@ __global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
   }
 }
 
+// One wave per cell, lanes over its points.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
   const uint32_t nc = a.n_cells[0];
-  for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < nc; id += gridDim.x * blockDim.x) {
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t wpb = blockDim.x / kWave, nw = gridDim.x * wpb;
+  const size_t C = (size_t)a.ccap;
+  for (uint32_t id = blockIdx.x * wpb + threadIdx.x / kWave; id < nc; id += nw) {
     const uint32_t m = a.ccnt[id], o = a.coff[id];
     const int32_t* pts = a.order + o;
-    int mn = pts[0];
-    T lo[3], hi[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = a.xs[(size_t)k * a.ccap + o];
-    for (uint32_t k = 1; k < m; ++k) {
+    int mn = INT_MAX;
+    T lo[3] = {T(INFINITY), T(INFINITY), T(INFINITY)}, hi[3] = {-T(INFINITY), -T(INFINITY), -T(INFINITY)};
+    for (uint32_t k = lane; k < m; k += kWave) {
       mn = min(mn, pts[k]);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const T v = a.xs[(size_t)d * a.ccap + o + k];
+        const T v = a.xs[(size_t)d * C + o + k];
         lo[d] = min(lo[d], v);
         hi[d] = max(hi[d], v);
       }
+    }
+    mn = wave_min(mn);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = wave_min(lo[d]);
+      hi[d] = wave_max(hi[d]);
     }
     // one (pair, cell) per cell, else the 64-bit keys of two cells collided
     const T r = cf_radius(a, (uint32_t)mn);
     const T inv = T(1) / (r * T(kCellShrink));
     const int pi = a.pi[mn], pj = a.pj[mn];
-    const long long cx = (long long)floor(a.x[mn] * inv), cy = (long long)floor(a.x[a.ccap + mn] * inv),
-                    cz = (long long)floor(a.x[2 * a.ccap + mn] * inv);
+    const long long cx = (long long)floor(a.x[mn] * inv), cy = (long long)floor(a.x[C + mn] * inv),
+                    cz = (long long)floor(a.x[2 * C + mn] * inv);
     bool same = true;
-    for (uint32_t k = 0; k < m; ++k) {
+    for (uint32_t k = lane; k < m; k += kWave) {
       const int c = pts[k];
       same &= a.pi[c] == pi && a.pj[c] == pj && (long long)floor(a.xs[o + k] * inv) == cx &&
-              (long long)floor(a.xs[a.ccap + o + k] * inv) == cy && (long long)floor(a.xs[2 * a.ccap + o + k] * inv) == cz;
+              (long long)floor(a.xs[C + o + k] * inv) == cy && (long long)floor(a.xs[2 * C + o + k] * inv) == cz;
     }
-    if (!same) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
-    a.cmin[id] = mn;
-    a.parent[mn] = mn;  // union-find runs over the cells' smallest contacts only
-#pragma unroll
-    for (int k = 0; k < 7; ++k) a.acc[(size_t)k * a.ccap + mn] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      a.box[(size_t)k * a.ccap + id] = lo[k];
-      a.box[(size_t)(3 + k) * a.ccap + id] = hi[k];
+    const bool all_same = __ballot(!same) == 0ull;
+    if (lane == 0) {
+      if (!all_same) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+      a.cmin[id] = mn;
+      a.parent[mn] = mn;  // union-find runs over the cells' smallest contacts only
+    }
+    if (lane < 7) a.acc[(size_t)lane * C + mn] = 0.0;
+    if (lane < 3) {
+      const T l = lane == 0 ? lo[0] : (lane == 1 ? lo[1] : lo[2]);
+      const T h = lane == 0 ? hi[0] : (lane == 1 ? hi[1] : hi[2]);
+      a.box[(size_t)lane * C + id] = l;
+      a.box[(size_t)(3 + lane) * C + id] = h;
     }
   }
 }
@@ -1869,42 +1895,51 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_cf_sum(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
   const uint32_t nc = (a.scale > T(0)) ? a.n_cells[0] : 0u;
-  const uint32_t total = nc + cnt;
-  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < total; w += gridDim.x * blockDim.x) {
-    uint32_t budget = kLinkBudget;
-    if (w < nc) {
-      const uint32_t id = w;
-      int r = uf_root(a.parent, a.cmin[id], budget);
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t wpb = blockDim.x / kWave, nw = gridDim.x * wpb;
+  const size_t C = (size_t)a.ccap;
+  // cells: one wave each, lanes over the points
+  for (uint32_t id = blockIdx.x * wpb + threadIdx.x / kWave; id < nc; id += nw) {
+    int r = 0;
+    if (lane == 0) {
+      uint32_t budget = kLinkBudget;
+      r = uf_root(a.parent, a.cmin[id], budget);
       if (r < 0) {
         atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
         r = a.cmin[id];
       }
-      const uint32_t o = a.coff[id];
-      const int32_t* pts = a.order + o;
-      double s[7] = {0, 0, 0, 0, 0, 0, 0};
-      for (uint32_t k = 0; k < a.ccnt[id]; ++k) {
-        a.root[pts[k]] = r;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          s[d] += (double)a.xs[(size_t)d * a.ccap + o + k];
-          s[3 + d] += (double)a.ns[(size_t)d * a.ccap + o + k];
-        }
-        s[6] += 1.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 7; ++k) unsafeAtomicAdd(a.acc + (size_t)k * a.ccap + r, s[k]);
-    } else {
-      const uint32_t c = w - nc;
-      if (a.pcell[c] >= 0) continue;  // summed with its cell
-      a.root[c] = (int32_t)c;
-      if (!cf_valid(a, c)) continue;
+    }
+    r = __shfl(r, 0);
+    const uint32_t o = a.coff[id], m = a.ccnt[id];
+    const int32_t* pts = a.order + o;
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t k = lane; k < m; k += kWave) {
+      a.root[pts[k]] = r;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        a.acc[(size_t)d * a.ccap + c] = (double)a.x[(size_t)d * a.ccap + c];
-        a.acc[(size_t)(3 + d) * a.ccap + c] = (double)a.n[(size_t)d * a.ccap + c];
+        s[d] += (double)a.xs[(size_t)d * C + o + k];
+        s[3 + d] += (double)a.ns[(size_t)d * C + o + k];
       }
-      a.acc[(size_t)6 * a.ccap + c] = 1.0;
+      s[6] += 1.0;
     }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) s[k] = wave_sum(s[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) unsafeAtomicAdd(a.acc + (size_t)k * C + r, s[k]);
+    }
+  }
+  // points in no cell (no merging, or skipped): their own groups
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
+    if (a.pcell[c] >= 0) continue;  // summed with its cell
+    a.root[c] = (int32_t)c;
+    if (!cf_valid(a, c)) continue;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      a.acc[(size_t)d * C + c] = (double)a.x[(size_t)d * C + c];
+      a.acc[(size_t)(3 + d) * C + c] = (double)a.n[(size_t)d * C + c];
+    }
+    a.acc[(size_t)6 * C + c] = 1.0;
   }
 }
 
