@@ -1605,34 +1605,56 @@ __global__ void k_cf_clear(ForceArgs<T> a, uint64_t n) {
   if (blockIdx.x == 0 && threadIdx.x < 2) a.n_cells[threadIdx.x] = 0;
 }
 
+// Contacts next to each other in the list mostly share a cell: the lanes of
+// a wave holding one key are served by one leader (one probe sequence, one
+// count update) instead of one atomic each on the same slot.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_insert(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
-    a.pcell[c] = -1;
-    if (!cf_valid(a, c)) {
-      atomicOr(a.status, DEM_DEV_BAD_TREE);
-      continue;
+  const int lane = lane_id();
+  for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    bool has = false;
+    unsigned long long key = 0;
+    if (c < cnt) {
+      a.pcell[c] = -1;
+      if (!cf_valid(a, c)) {
+        atomicOr(a.status, DEM_DEV_BAD_TREE);
+      } else if (a.scale > T(0)) {
+        const T r = cf_radius(a, c);
+        if (r > T(0)) {
+          long long cx, cy, cz;
+          cf_cell(a, c, r, cx, cy, cz);
+          key = cell_key(a.pi[c], a.pj[c], cx, cy, cz);
+          has = true;
+        }
+      }
     }
-    if (!(a.scale > T(0))) continue;
-    const T r = cf_radius(a, c);
-    if (!(r > T(0))) continue;
-    long long cx, cy, cz;
-    cf_cell(a, c, r, cx, cy, cz);
-    const unsigned long long key = cell_key(a.pi[c], a.pj[c], cx, cy, cz);
-    uint64_t slot = mix64(key) & a.tmask;
-    int k = 0;
-    for (; k < kCellProbes; ++k) {
-      const unsigned long long old = atomicCAS(a.keys + slot, kCellEmpty, key);
-      if (old == kCellEmpty || old == key) break;
-      slot = (slot + 1) & a.tmask;
+    int my_slot = -1;
+    unsigned long long pending = __ballot(has);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const unsigned long long lk = __shfl(key, leader);
+      const unsigned long long same = __ballot(has && key == lk) & pending;
+      int slot = -1;
+      if (lane == leader) {
+        uint64_t sl = mix64(lk) & a.tmask;
+        for (int k = 0; k < kCellProbes; ++k) {
+          const unsigned long long old = atomicCAS(a.keys + sl, kCellEmpty, lk);
+          if (old == kCellEmpty || old == lk) {
+            slot = (int)sl;
+            break;
+          }
+          sl = (sl + 1) & a.tmask;
+        }
+        if (slot < 0) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+        else atomicAdd(a.scnt + slot, (uint32_t)__popcll(same));
+      }
+      slot = __shfl(slot, leader);
+      if ((same >> lane) & 1ull) my_slot = slot;
+      pending &= ~same;
     }
-    if (k == kCellProbes) {
-      atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
-      continue;
-    }
-    a.pcell[c] = (int32_t)slot;  // a slot for now; k_cf_place turns it into a cell id
-    atomicAdd(a.scnt + slot, 1u);
+    if (has && my_slot >= 0) a.pcell[c] = my_slot;  // a slot for now; k_cf_place turns it into a cell id
   }
 }
 
@@ -1702,15 +1724,35 @@ __global__ void __launch_bounds__(256) k_cf_range(ForceArgs<T> a, uint64_t n) {
   }
 }
 
+// Positions within a cell's range: one count update per cell present in a
+// wave (its leader's), the lanes ranked by lane order.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
-    const int slot = a.pcell[c];
-    if (slot < 0) continue;
-    const int id = a.sid[slot];
+  const int lane = lane_id();
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    int id = -1;
+    if (c < cnt) {
+      const int slot = a.pcell[c];
+      if (slot >= 0) id = a.sid[slot];
+    }
+    const bool act = id >= 0;
+    uint32_t pos = 0;
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int lid = __shfl(id, leader);
+      const unsigned long long same = __ballot(act && id == lid) & pending;
+      uint32_t b = 0;
+      if (lane == leader) b = a.coff[lid] + atomicAdd(a.cfill + lid, (uint32_t)__popcll(same));
+      b = __shfl(b, leader);
+      if ((same >> lane) & 1ull) pos = b + (uint32_t)__popcll(same & lt);
+      pending &= ~same;
+    }
+    if (!act) continue;
     a.pcell[c] = id;
-    const uint32_t pos = a.coff[id] + atomicAdd(a.cfill + id, 1u);
     a.order[pos] = (int32_t)c;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -1886,6 +1928,20 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
         uf_union(a.parent, ma, mbw, budget, a.status);
       }
     }
+  }
+}
+
+// Between the two linking launches: every cell's smallest contact points
+// straight at its current root, so the second launch's root checks read one
+// or two parents (no union runs concurrently here).
+template <typename T>
+__global__ void __launch_bounds__(256) k_cf_compress(ForceArgs<T> a) {
+  const uint32_t nc = a.n_cells[0];
+  for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < nc; id += gridDim.x * blockDim.x) {
+    uint32_t budget = kLinkBudget;
+    const int m = a.cmin[id];
+    const int r = uf_root(a.parent, m, budget);
+    if (r >= 0 && r != m) __hip_atomic_store(a.parent + m, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -2477,6 +2533,7 @@ dem_status run_forces(const dem_scene* s, const dem_contacts* c, const void* mas
       // adjacent cells first: they join most of a patch, so that the distant
       // offsets mostly find both cells in one group already
       hipLaunchKernelGGL(k_cf_link<T>, g, b, 0, st, a, 0, kNbrAdjacent);
+      hipLaunchKernelGGL(k_cf_compress<T>, g, b, 0, st, a);
       hipLaunchKernelGGL(k_cf_link<T>, g, b, 0, st, a, kNbrAdjacent, kNbr);
     }
     hipLaunchKernelGGL(k_cf_sum<T>, g, b, 0, st, a);
