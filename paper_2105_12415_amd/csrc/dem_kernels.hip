@@ -1821,6 +1821,8 @@ __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
 // lexicographically after zero), |d| <= 2 per axis: the 13 adjacent ones
 // (largest |d| = 1) first, then the 49 others.
 constexpr int kNbrAdjacent = 13;
+constexpr int kLinkLanes = 16;                 // lanes per neighbour in k_cf_link's point tests
+constexpr int kLinkGroups = kWave / kLinkLanes;
 static_assert(kNbrAdjacent <= 64 && kNbr - kNbrAdjacent <= 64, "one lane per offset in k_cf_link");
 __constant__ signed char kCfOff[kNbr][3] = {
     {1, 0, 0}, {-1, 1, 0}, {0, 1, 0}, {1, 1, 0}, {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {-1, 0, 1},
@@ -1835,9 +1837,10 @@ __constant__ signed char kCfOff[kNbr][3] = {
 // One wave per cell A.  Lane l takes neighbour offset k0 + l (k1 - k0 <= 64)
 // for the cheap tests: the neighbouring cell exists, its box comes closer
 // than r to A's box, and the two are not yet one group.  The neighbours that
-// pass are then taken one at a time by the whole wave: lanes hold A's points
-// (those within r of the neighbour's box) and scan the neighbour's points
-// until some lane finds one closer than r; one is enough to join the cells.
+// pass are then taken kLinkGroups at a time, kLinkLanes lanes each: the
+// lanes hold A's points (those within r of the neighbour's box) and scan the
+// neighbour's points until one of them finds a point closer than r; one is
+// enough to join the cells.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1) {
   const uint32_t nc = a.n_cells[0];
@@ -1882,28 +1885,42 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
         }
       }
     }
+    // the remaining neighbours, kLinkGroups at a time: group g (kLinkLanes
+    // lanes) takes the g-th lowest of them
     unsigned long long todo = __ballot(B >= 0);
     const T* xa = a.xs + a.coff[A];
     const uint32_t na = a.ccnt[A];
+    const int grp = lane / kLinkLanes, gl = lane % kLinkLanes;
+    const unsigned long long gmask = (kLinkLanes == 64 ? ~0ull : ((1ull << kLinkLanes) - 1ull)) << (grp * kLinkLanes);
     while (todo) {
-      const int src = __ffsll((long long)todo) - 1;
-      todo &= todo - 1;
-      const int Bw = __builtin_amdgcn_readfirstlane(__shfl(B, src));
-      const int mbw = __builtin_amdgcn_readfirstlane(__shfl(mb, src));
-      // an earlier neighbour of this wave may have joined them already
-      const int ra = uf_root_plain(a.parent, ma), rb = uf_root_plain(a.parent, mbw);
-      if (ra >= 0 && ra == rb) continue;
-      T bl[3], bh[3];
+      unsigned long long t = todo;
+      for (int q = 0; q < grp && t; ++q) t &= t - 1;
+      const int src = t ? __ffsll((long long)t) - 1 : 0;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        bl[d] = a.box[(size_t)d * C + Bw];
-        bh[d] = a.box[(size_t)(3 + d) * C + Bw];
+      for (int q = 0; q < kLinkGroups; ++q) todo &= todo ? todo - 1 : 0ull;
+      const int Bg = __shfl(B, src), mbg = __shfl(mb, src);
+      bool live = t != 0ull;
+      // an earlier neighbour may have joined them already
+      if (live) {
+        const int ra = uf_root_plain(a.parent, ma), rb = uf_root_plain(a.parent, mbg);
+        live = !(ra >= 0 && ra == rb);
       }
-      const T* xb = a.xs + a.coff[Bw];
-      const uint32_t nb = a.ccnt[Bw];
+      T bl[3] = {T(0), T(0), T(0)}, bh[3] = {T(0), T(0), T(0)};
+      const T* xb = a.xs;
+      uint32_t nb = 0;
+      if (live) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          bl[d] = a.box[(size_t)d * C + Bg];
+          bh[d] = a.box[(size_t)(3 + d) * C + Bg];
+        }
+        xb = a.xs + a.coff[Bg];
+        nb = a.ccnt[Bg];
+      }
       bool close = false;
-      for (uint32_t i0 = 0; i0 < na; i0 += kWave) {
-        const uint32_t i = i0 + (uint32_t)lane;
+      // group-uniform loops: lanes gl, gl + kLinkLanes, ... over A's points
+      for (uint32_t i0 = 0; live && i0 < na; i0 += kLinkLanes) {
+        const uint32_t i = i0 + (uint32_t)gl;
         T xp = T(0), yp = T(0), zp = T(0);
         bool act = i < na;
         if (act) {
@@ -1915,21 +1932,23 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
           const T gz = max(max(bl[2] - zp, zp - bh[2]), T(0));
           act = gx * gx + gy * gy + gz * gz < r2;
         }
-        if (__ballot(act) == 0ull) continue;
+        if ((__ballot(act) & gmask) == 0ull) continue;
         for (uint32_t j = 0; j < nb; ++j) {
           const T ex = xb[j] - xp, ey = xb[C + j] - yp, ez = xb[2 * C + j] - zp;
           close = close || (act && ex * ex + ey * ey + ez * ez < r2);
-          if ((j & 7u) == 7u && __ballot(close) != 0ull) break;
+          if ((j & 7u) == 7u && (__ballot(close) & gmask) != 0ull) break;
         }
-        if (__ballot(close) != 0ull) break;
+        if ((__ballot(close) & gmask) != 0ull) break;
       }
-      if (__ballot(close) != 0ull && lane == 0) {
+      const bool joined = (__ballot(close) & gmask) != 0ull;
+      if (joined && gl == 0) {
         uint32_t budget = kLinkBudget;
-        uf_union(a.parent, ma, mbw, budget, a.status);
+        uf_union(a.parent, ma, mbg, budget, a.status);
       }
     }
   }
 }
+
 
 // Between the two linking launches: every cell's smallest contact points
 // straight at its current root, so the second launch's root checks read one
