@@ -1476,8 +1476,7 @@ struct ForceArgs {
   // per contact
   int32_t* pcell;      // cell id of the contact (-1: none)
   int32_t* order;      // contacts ordered by cell
-  T* xs;               // [3][ccap] points in cell order
-  T* ns;               // [3][ccap] normals in cell order
+  T* pts;              // [ccap][8] in cell order: point x, y, z, 0, normal x, y, z, 0
   int32_t* parent;
   int32_t* root;
   int32_t* mslot;
@@ -1501,6 +1500,22 @@ struct ForceArgs {
   T* torque;
   uint32_t* status;
 };
+
+// One half of a cell-ordered point record (16 B in FP32, 32 B in FP64).
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+  T x, y, z, w;
+};
+
+template <typename T>
+__device__ __forceinline__ Q4<T> cf_pt(const ForceArgs<T>& a, size_t pos) {
+  return reinterpret_cast<const Q4<T>*>(a.pts)[2 * pos];
+}
+
+template <typename T>
+__device__ __forceinline__ Q4<T> cf_nr(const ForceArgs<T>& a, size_t pos) {
+  return reinterpret_cast<const Q4<T>*>(a.pts)[2 * pos + 1];
+}
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
   z += 0x9E3779B97F4A7C15ull;
@@ -1754,11 +1769,10 @@ __global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
     if (!act) continue;
     a.pcell[c] = id;
     a.order[pos] = (int32_t)c;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      a.xs[(size_t)k * a.ccap + pos] = a.x[(size_t)k * a.ccap + c];
-      a.ns[(size_t)k * a.ccap + pos] = a.n[(size_t)k * a.ccap + c];
-    }
+    const size_t C = (size_t)a.ccap;
+    Q4<T>* q = reinterpret_cast<Q4<T>*>(a.pts) + 2 * (size_t)pos;
+    q[0] = Q4<T>{a.x[c], a.x[C + c], a.x[2 * C + c], T(0)};
+    q[1] = Q4<T>{a.n[c], a.n[C + c], a.n[2 * C + c], T(0)};
   }
 }
 
@@ -1776,12 +1790,9 @@ __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
     T lo[3] = {T(INFINITY), T(INFINITY), T(INFINITY)}, hi[3] = {-T(INFINITY), -T(INFINITY), -T(INFINITY)};
     for (uint32_t k = lane; k < m; k += kWave) {
       mn = min(mn, pts[k]);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const T v = a.xs[(size_t)d * C + o + k];
-        lo[d] = min(lo[d], v);
-        hi[d] = max(hi[d], v);
-      }
+      const Q4<T> q = cf_pt(a, o + k);
+      lo[0] = min(lo[0], q.x); lo[1] = min(lo[1], q.y); lo[2] = min(lo[2], q.z);
+      hi[0] = max(hi[0], q.x); hi[1] = max(hi[1], q.y); hi[2] = max(hi[2], q.z);
     }
     mn = wave_min(mn);
 #pragma unroll
@@ -1798,8 +1809,9 @@ __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
     bool same = true;
     for (uint32_t k = lane; k < m; k += kWave) {
       const int c = pts[k];
-      same &= a.pi[c] == pi && a.pj[c] == pj && (long long)floor(a.xs[o + k] * inv) == cx &&
-              (long long)floor(a.xs[C + o + k] * inv) == cy && (long long)floor(a.xs[2 * C + o + k] * inv) == cz;
+      const Q4<T> q = cf_pt(a, o + k);
+      same &= a.pi[c] == pi && a.pj[c] == pj && (long long)floor(q.x * inv) == cx &&
+              (long long)floor(q.y * inv) == cy && (long long)floor(q.z * inv) == cz;
     }
     const bool all_same = __ballot(!same) == 0ull;
     if (lane == 0) {
@@ -1888,7 +1900,7 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
     // the remaining neighbours, kLinkGroups at a time: group g (kLinkLanes
     // lanes) takes the g-th lowest of them
     unsigned long long todo = __ballot(B >= 0);
-    const T* xa = a.xs + a.coff[A];
+    const size_t oa = a.coff[A];
     const uint32_t na = a.ccnt[A];
     const int grp = lane / kLinkLanes, gl = lane % kLinkLanes;
     const unsigned long long gmask = (kLinkLanes == 64 ? ~0ull : ((1ull << kLinkLanes) - 1ull)) << (grp * kLinkLanes);
@@ -1906,7 +1918,7 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
         live = !(ra >= 0 && ra == rb);
       }
       T bl[3] = {T(0), T(0), T(0)}, bh[3] = {T(0), T(0), T(0)};
-      const T* xb = a.xs;
+      size_t ob = 0;
       uint32_t nb = 0;
       if (live) {
 #pragma unroll
@@ -1914,7 +1926,7 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
           bl[d] = a.box[(size_t)d * C + Bg];
           bh[d] = a.box[(size_t)(3 + d) * C + Bg];
         }
-        xb = a.xs + a.coff[Bg];
+        ob = a.coff[Bg];
         nb = a.ccnt[Bg];
       }
       bool close = false;
@@ -1924,9 +1936,10 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
         T xp = T(0), yp = T(0), zp = T(0);
         bool act = i < na;
         if (act) {
-          xp = xa[i];
-          yp = xa[C + i];
-          zp = xa[2 * C + i];
+          const Q4<T> q = cf_pt(a, oa + i);
+          xp = q.x;
+          yp = q.y;
+          zp = q.z;
           const T gx = max(max(bl[0] - xp, xp - bh[0]), T(0));
           const T gy = max(max(bl[1] - yp, yp - bh[1]), T(0));
           const T gz = max(max(bl[2] - zp, zp - bh[2]), T(0));
@@ -1934,7 +1947,8 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
         }
         if ((__ballot(act) & gmask) == 0ull) continue;
         for (uint32_t j = 0; j < nb; ++j) {
-          const T ex = xb[j] - xp, ey = xb[C + j] - yp, ez = xb[2 * C + j] - zp;
+          const Q4<T> q = cf_pt(a, ob + j);
+          const T ex = q.x - xp, ey = q.y - yp, ez = q.z - zp;
           close = close || (act && ex * ex + ey * ey + ez * ez < r2);
           if ((j & 7u) == 7u && (__ballot(close) & gmask) != 0ull) break;
         }
@@ -1990,11 +2004,9 @@ __global__ void __launch_bounds__(256) k_cf_sum(ForceArgs<T> a) {
     double s[7] = {0, 0, 0, 0, 0, 0, 0};
     for (uint32_t k = lane; k < m; k += kWave) {
       a.root[pts[k]] = r;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        s[d] += (double)a.xs[(size_t)d * C + o + k];
-        s[3 + d] += (double)a.ns[(size_t)d * C + o + k];
-      }
+      const Q4<T> q = cf_pt(a, o + k), w = cf_nr(a, o + k);
+      s[0] += (double)q.x; s[1] += (double)q.y; s[2] += (double)q.z;
+      s[3] += (double)w.x; s[4] += (double)w.y; s[5] += (double)w.z;
       s[6] += 1.0;
     }
 #pragma unroll
@@ -2460,7 +2472,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
 // ------------------------------------------------------------------ contact forces host side
 struct CfLayout {
   uint64_t table;
-  size_t keys, scnt, sid, counters, coff, ccnt, cfill, cmin, box, pcell, order, xs, ns, parent, root, mslot, acc,
+  size_t keys, scnt, sid, counters, coff, ccnt, cfill, cmin, box, pcell, order, pts, parent, root, mslot, acc,
       total;
 };
 
@@ -2482,8 +2494,7 @@ CfLayout cf_layout(int64_t cap) {
   L.box = o; o = align_up(o + 8 * 6 * C, 256);  // room for FP64 boxes
   L.pcell = o; o = align_up(o + 4 * C, 256);
   L.order = o; o = align_up(o + 4 * C, 256);
-  L.xs = o; o = align_up(o + 8 * 3 * C, 256);  // room for FP64
-  L.ns = o; o = align_up(o + 8 * 3 * C, 256);
+  L.pts = o; o = align_up(o + 8 * 8 * C, 256);  // room for FP64
   L.parent = o; o = align_up(o + 4 * C, 256);
   L.root = o; o = align_up(o + 4 * C, 256);
   L.mslot = o; o = align_up(o + 4 * C, 256);
@@ -2518,8 +2529,7 @@ dem_status run_forces(const dem_scene* s, const dem_contacts* c, const void* mas
   a.box = reinterpret_cast<T*>(base + L.box);
   a.pcell = reinterpret_cast<int32_t*>(base + L.pcell);
   a.order = reinterpret_cast<int32_t*>(base + L.order);
-  a.xs = reinterpret_cast<T*>(base + L.xs);
-  a.ns = reinterpret_cast<T*>(base + L.ns);
+  a.pts = reinterpret_cast<T*>(base + L.pts);
   a.parent = reinterpret_cast<int32_t*>(base + L.parent);
   a.root = reinterpret_cast<int32_t*>(base + L.root);
   a.mslot = reinterpret_cast<int32_t*>(base + L.mslot);
