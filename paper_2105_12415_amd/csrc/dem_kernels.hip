@@ -1448,6 +1448,17 @@ constexpr int kNbr = 62;                    // neighbouring cells of one half-sp
 constexpr uint32_t kLinkBudget = 1u << 16;  // parent reads per thread in one kernel
 constexpr double kCellShrink = 0.57735026918962576 * (1.0 - 1e-5);  // cell side / r
 
+// Per-cell record (k_cf_cells writes it, k_cf_link reads it): cell
+// coordinates, bounding box of the points, merge radius, smallest contact and
+// particle pair.  64 B in FP32, 96 B in FP64.
+template <typename T>
+struct alignas(16) CellRec {
+  long long cx, cy, cz;
+  T lo[3], hi[3];
+  T r;
+  int32_t cmin, pi, pj;
+};
+
 template <typename T>
 struct ForceArgs {
   const int32_t* pi;
@@ -1472,7 +1483,7 @@ struct ForceArgs {
   uint32_t* ccnt;
   uint32_t* cfill;
   int32_t* cmin;       // smallest contact index of the cell
-  T* box;              // [6][ccap]: min xyz, max xyz
+  CellRec<T>* crec;    // [ccap]
   // per contact
   int32_t* pcell;      // cell id of the contact (-1: none)
   int32_t* order;      // contacts ordered by cell
@@ -1560,13 +1571,15 @@ __device__ __forceinline__ void cf_cell(const ForceArgs<T>& a, uint32_t c, T r, 
   cz = (long long)floor(a.x[2 * a.ccap + c] * inv);
 }
 
-// Slot of a key in the cell table, -1 if absent.
+// Cell id of a key, -1 if absent.  A probe loads the slot's key and cell id
+// together (the id is used only if the key matches).
 template <typename T>
-__device__ __forceinline__ int cf_find(const ForceArgs<T>& a, unsigned long long key) {
+__device__ __forceinline__ int cf_find_id(const ForceArgs<T>& a, unsigned long long key) {
   uint64_t slot = mix64(key) & a.tmask;
   for (int k = 0; k < kCellProbes; ++k) {
     const unsigned long long kk = a.keys[slot];
-    if (kk == key) return (int)slot;
+    const int id = a.sid[slot];
+    if (kk == key) return id;
     if (kk == kCellEmpty) return -1;
     slot = (slot + 1) & a.tmask;
   }
@@ -1820,11 +1833,17 @@ __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
       a.parent[mn] = mn;  // union-find runs over the cells' smallest contacts only
     }
     if (lane < 7) a.acc[(size_t)lane * C + mn] = 0.0;
-    if (lane < 3) {
-      const T l = lane == 0 ? lo[0] : (lane == 1 ? lo[1] : lo[2]);
-      const T h = lane == 0 ? hi[0] : (lane == 1 ? hi[1] : hi[2]);
-      a.box[(size_t)lane * C + id] = l;
-      a.box[(size_t)(3 + lane) * C + id] = h;
+    if (lane == 1) {
+      CellRec<T> cr;
+      cr.cx = cx; cr.cy = cy; cr.cz = cz;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        cr.lo[d] = lo[d];
+        cr.hi[d] = hi[d];
+      }
+      cr.r = r;
+      cr.cmin = mn; cr.pi = pi; cr.pj = pj;
+      a.crec[id] = cr;
     }
   }
 }
@@ -1859,32 +1878,23 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
   const int lane = lane_id();
   const uint32_t wpb = blockDim.x / kWave;
   const uint32_t nw = gridDim.x * wpb;
-  const size_t C = (size_t)a.ccap;
   for (uint32_t A = blockIdx.x * wpb + threadIdx.x / kWave; A < nc; A += nw) {
-    const int ma = a.cmin[A];
-    const T r = cf_radius(a, (uint32_t)ma);
-    const T r2 = r * r;
-    const int pi = a.pi[ma], pj = a.pj[ma];
-    long long cx, cy, cz;
-    cf_cell(a, (uint32_t)ma, r, cx, cy, cz);
-    T al[3], ah[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      al[d] = a.box[(size_t)d * C + A];
-      ah[d] = a.box[(size_t)(3 + d) * C + A];
-    }
+    const CellRec<T> ca = a.crec[A];
+    const int ma = ca.cmin;
+    const T r2 = ca.r * ca.r;
+    const int pi = ca.pi, pj = ca.pj;
     const int k = k0 + lane;
     int B = -1, mb = -1;
     if (k < k1) {
-      const int slot = cf_find(a, cell_key(pi, pj, cx + kCfOff[k][0], cy + kCfOff[k][1], cz + kCfOff[k][2]));
-      if (slot >= 0) {
-        const int b = a.sid[slot];
-        const int m = a.cmin[b];
-        if (a.pi[m] == pi && a.pj[m] == pj) {  // else a colliding key (reported by k_cf_cells)
+      const int b = cf_find_id(a, cell_key(pi, pj, ca.cx + kCfOff[k][0], ca.cy + kCfOff[k][1], ca.cz + kCfOff[k][2]));
+      if (b >= 0) {
+        const CellRec<T> cb = a.crec[b];
+        const int m = cb.cmin;
+        if (cb.pi == pi && cb.pj == pj) {  // else a colliding key (reported by k_cf_cells)
           T gap2 = T(0);
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const T g = max(max(a.box[(size_t)d * C + b] - ah[d], al[d] - a.box[(size_t)(3 + d) * C + b]), T(0));
+            const T g = max(max(cb.lo[d] - ca.hi[d], ca.lo[d] - cb.hi[d]), T(0));
             gap2 += g * g;
           }
           if (gap2 < r2) {
@@ -1921,10 +1931,11 @@ __global__ void __launch_bounds__(256) k_cf_link(ForceArgs<T> a, int k0, int k1)
       size_t ob = 0;
       uint32_t nb = 0;
       if (live) {
+        const CellRec<T> cb = a.crec[Bg];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          bl[d] = a.box[(size_t)d * C + Bg];
-          bh[d] = a.box[(size_t)(3 + d) * C + Bg];
+          bl[d] = cb.lo[d];
+          bh[d] = cb.hi[d];
         }
         ob = a.coff[Bg];
         nb = a.ccnt[Bg];
@@ -2472,7 +2483,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
 // ------------------------------------------------------------------ contact forces host side
 struct CfLayout {
   uint64_t table;
-  size_t keys, scnt, sid, counters, coff, ccnt, cfill, cmin, box, pcell, order, pts, parent, root, mslot, acc,
+  size_t keys, scnt, sid, counters, coff, ccnt, cfill, cmin, crec, pcell, order, pts, parent, root, mslot, acc,
       total;
 };
 
@@ -2491,7 +2502,7 @@ CfLayout cf_layout(int64_t cap) {
   L.ccnt = o; o = align_up(o + 4 * C, 256);
   L.cfill = o; o = align_up(o + 4 * C, 256);
   L.cmin = o; o = align_up(o + 4 * C, 256);
-  L.box = o; o = align_up(o + 8 * 6 * C, 256);  // room for FP64 boxes
+  L.crec = o; o = align_up(o + sizeof(CellRec<double>) * C, 256);
   L.pcell = o; o = align_up(o + 4 * C, 256);
   L.order = o; o = align_up(o + 4 * C, 256);
   L.pts = o; o = align_up(o + 8 * 8 * C, 256);  // room for FP64
@@ -2526,7 +2537,7 @@ dem_status run_forces(const dem_scene* s, const dem_contacts* c, const void* mas
   a.ccnt = reinterpret_cast<uint32_t*>(base + L.ccnt);
   a.cfill = reinterpret_cast<uint32_t*>(base + L.cfill);
   a.cmin = reinterpret_cast<int32_t*>(base + L.cmin);
-  a.box = reinterpret_cast<T*>(base + L.box);
+  a.crec = reinterpret_cast<CellRec<T>*>(base + L.crec);
   a.pcell = reinterpret_cast<int32_t*>(base + L.pcell);
   a.order = reinterpret_cast<int32_t*>(base + L.order);
   a.pts = reinterpret_cast<T*>(base + L.pts);
