@@ -1487,7 +1487,7 @@ struct ForceArgs {
   // per contact
   int32_t* pcell;      // cell id of the contact (-1: none)
   int32_t* order;      // contacts ordered by cell
-  T* pts;              // [ccap][8] in cell order: point x, y, z, 0, normal x, y, z, 0
+  T* pts;              // [ccap][8] in cell order: point x, y, z, pi, normal x, y, z, pj
   int32_t* parent;
   int32_t* root;
   int32_t* mslot;
@@ -1517,6 +1517,13 @@ template <typename T>
 struct alignas(4 * sizeof(T)) Q4 {
   T x, y, z, w;
 };
+
+// The records' fourth words carry the contact's particles (pi in the point
+// half, pj in the normal half), as integer bits.
+__device__ __forceinline__ float int_bits(int v, float) { return __int_as_float(v); }
+__device__ __forceinline__ double int_bits(int v, double) { return __longlong_as_double((long long)v); }
+__device__ __forceinline__ int bits_int(float v) { return __float_as_int(v); }
+__device__ __forceinline__ int bits_int(double v) { return (int)__double_as_longlong(v); }
 
 template <typename T>
 __device__ __forceinline__ Q4<T> cf_pt(const ForceArgs<T>& a, size_t pos) {
@@ -1633,9 +1640,9 @@ __global__ void k_cf_clear(ForceArgs<T> a, uint64_t n) {
   if (blockIdx.x == 0 && threadIdx.x < 2) a.n_cells[threadIdx.x] = 0;
 }
 
-// Contacts next to each other in the list mostly share a cell: the lanes of
-// a wave holding one key are served by one leader (one probe sequence, one
-// count update) instead of one atomic each on the same slot.
+// Contacts next to each other in the list mostly share a cell: a run of
+// lanes with one key is served by its first lane (one probe sequence, one
+// count update for the run); the runs' leaders work in parallel.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_insert(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
@@ -1658,31 +1665,33 @@ __global__ void __launch_bounds__(256) k_cf_insert(ForceArgs<T> a) {
         }
       }
     }
-    int my_slot = -1;
-    unsigned long long pending = __ballot(has);
-    while (pending) {
-      const int leader = __ffsll((long long)pending) - 1;
-      const unsigned long long lk = __shfl(key, leader);
-      const unsigned long long same = __ballot(has && key == lk) & pending;
-      int slot = -1;
-      if (lane == leader) {
-        uint64_t sl = mix64(lk) & a.tmask;
-        for (int k = 0; k < kCellProbes; ++k) {
-          const unsigned long long old = atomicCAS(a.keys + sl, kCellEmpty, lk);
-          if (old == kCellEmpty || old == lk) {
-            slot = (int)sl;
-            break;
-          }
-          sl = (sl + 1) & a.tmask;
+    const unsigned long long prev_key = __shfl_up(key, 1);
+    const bool prev_has = __shfl_up((int)has, 1) != 0;
+    const bool lead = has && (lane == 0 || !prev_has || prev_key != key);
+    const unsigned long long leaders = __ballot(lead), members = __ballot(has);
+    // a leader's run: it and the following lanes up to the next leader or gap
+    const unsigned long long after = lane == 63 ? 0ull : (~0ull << (lane + 1));
+    const unsigned long long stops = (leaders | ~members) & after;
+    const int end = stops ? __ffsll((long long)stops) - 1 : 64;
+    int slot = -1;
+    if (lead) {
+      uint64_t sl = mix64(key) & a.tmask;
+      for (int k = 0; k < kCellProbes; ++k) {
+        const unsigned long long old = atomicCAS(a.keys + sl, kCellEmpty, key);
+        if (old == kCellEmpty || old == key) {
+          slot = (int)sl;
+          break;
         }
-        if (slot < 0) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
-        else atomicAdd(a.scnt + slot, (uint32_t)__popcll(same));
+        sl = (sl + 1) & a.tmask;
       }
-      slot = __shfl(slot, leader);
-      if ((same >> lane) & 1ull) my_slot = slot;
-      pending &= ~same;
+      if (slot < 0) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+      else atomicAdd(a.scnt + slot, (uint32_t)(end - lane));
     }
-    if (has && my_slot >= 0) a.pcell[c] = my_slot;  // a slot for now; k_cf_place turns it into a cell id
+    // every member takes its run leader's slot
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int my_lead = 63 - __clzll((long long)(leaders & upto));
+    slot = __shfl(slot, has ? my_lead : lane);
+    if (has && slot >= 0) a.pcell[c] = slot;  // a slot for now; k_cf_place turns it into a cell id
   }
 }
 
@@ -1752,13 +1761,12 @@ __global__ void __launch_bounds__(256) k_cf_range(ForceArgs<T> a, uint64_t n) {
   }
 }
 
-// Positions within a cell's range: one count update per cell present in a
-// wave (its leader's), the lanes ranked by lane order.
+// Positions within a cell's range: one count update per run of lanes with
+// one cell (its first lane's, all runs in parallel), lanes ranked in the run.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
   const int lane = lane_id();
-  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
     const uint32_t c = base + threadIdx.x;
     int id = -1;
@@ -1767,25 +1775,25 @@ __global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
       if (slot >= 0) id = a.sid[slot];
     }
     const bool act = id >= 0;
-    uint32_t pos = 0;
-    unsigned long long pending = __ballot(act);
-    while (pending) {
-      const int leader = __ffsll((long long)pending) - 1;
-      const int lid = __shfl(id, leader);
-      const unsigned long long same = __ballot(act && id == lid) & pending;
-      uint32_t b = 0;
-      if (lane == leader) b = a.coff[lid] + atomicAdd(a.cfill + lid, (uint32_t)__popcll(same));
-      b = __shfl(b, leader);
-      if ((same >> lane) & 1ull) pos = b + (uint32_t)__popcll(same & lt);
-      pending &= ~same;
-    }
+    const int prev_id = __shfl_up(id, 1);
+    const bool lead = act && (lane == 0 || prev_id != id);
+    const unsigned long long leaders = __ballot(lead), members = __ballot(act);
+    const unsigned long long after = lane == 63 ? 0ull : (~0ull << (lane + 1));
+    const unsigned long long stops = (leaders | ~members) & after;
+    const int end = stops ? __ffsll((long long)stops) - 1 : 64;
+    uint32_t b = 0;
+    if (lead) b = a.coff[id] + atomicAdd(a.cfill + id, (uint32_t)(end - lane));
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int my_lead = 63 - __clzll((long long)(leaders & upto));
+    b = __shfl(b, act ? my_lead : lane);
     if (!act) continue;
+    const uint32_t pos = b + (uint32_t)(lane - my_lead);
     a.pcell[c] = id;
     a.order[pos] = (int32_t)c;
     const size_t C = (size_t)a.ccap;
     Q4<T>* q = reinterpret_cast<Q4<T>*>(a.pts) + 2 * (size_t)pos;
-    q[0] = Q4<T>{a.x[c], a.x[C + c], a.x[2 * C + c], T(0)};
-    q[1] = Q4<T>{a.n[c], a.n[C + c], a.n[2 * C + c], T(0)};
+    q[0] = Q4<T>{a.x[c], a.x[C + c], a.x[2 * C + c], int_bits(a.pi[c], T(0))};
+    q[1] = Q4<T>{a.n[c], a.n[C + c], a.n[2 * C + c], int_bits(a.pj[c], T(0))};
   }
 }
 
@@ -1821,9 +1829,8 @@ __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
                     cz = (long long)floor(a.x[2 * C + mn] * inv);
     bool same = true;
     for (uint32_t k = lane; k < m; k += kWave) {
-      const int c = pts[k];
-      const Q4<T> q = cf_pt(a, o + k);
-      same &= a.pi[c] == pi && a.pj[c] == pj && (long long)floor(q.x * inv) == cx &&
+      const Q4<T> q = cf_pt(a, o + k), w = cf_nr(a, o + k);
+      same &= bits_int(q.w) == pi && bits_int(w.w) == pj && (long long)floor(q.x * inv) == cx &&
               (long long)floor(q.y * inv) == cy && (long long)floor(q.z * inv) == cz;
     }
     const bool all_same = __ballot(!same) == 0ull;
