@@ -1429,16 +1429,18 @@ __global__ void k_fr_mem_clear(unsigned long long* mem, int64_t n) {
 //                of the point order (blocks take contiguous slot chunks and
 //                reserve their ids and ranges with one atomic each)
 //   k_cf_place   every contact into its cell's range
-//   k_cf_cells   per cell: smallest contact index m, bounding box; every
-//                point's parent := m (the cells start as stars); a 64-bit key
-//                collision is reported
+//   k_cf_cells   per cell (one wave, lanes over the points): smallest
+//                contact index m, the cell record (coordinates, bounding box,
+//                radius, pair), its point and normal sums (FP64) kept at m;
+//                the union-find runs over the m's (the cells start as stars);
+//                a 64-bit key collision is reported
 //   k_cf_link    per (cell, neighbouring cell) with offsets up to 2 in one
 //                half-space (each cell pair once): if the boxes come closer
 //                than r and some pair of their points is closer than r, the
 //                two cells join (union-find, links from the larger root to
-//                the smaller: a group's root is its smallest contact index)
-//   k_cf_sum     per cell: its points' sums added at the group root (FP64);
-//                the root of every point
+//                the smaller: a group's root is its smallest contact index);
+//                adjacent offsets first, then k_cf_compress, then the others
+//   k_cf_sum     per cell: its group root, and its sums added at the root
 //   k_cf_emit    one merged contact per root: mean point and normal, the
 //                force, per-particle force and torque
 //   k_cf_group   merged index of every input contact (optional output)
@@ -1489,7 +1491,7 @@ struct ForceArgs {
   int32_t* order;      // contacts ordered by cell
   T* pts;              // [ccap][8] in cell order: point x, y, z, pi, normal x, y, z, pj
   int32_t* parent;
-  int32_t* root;
+  int32_t* root;       // group root of every cell (by cell id)
   int32_t* mslot;
   double* acc;         // [7][ccap]: point sums, normal sums, members (at group roots)
   // force law
@@ -1797,29 +1799,80 @@ __global__ void __launch_bounds__(256) k_cf_place(ForceArgs<T> a) {
   }
 }
 
-// One wave per cell, lanes over its points.
+// Reductions over the 16 lanes of a DPP row, every lane getting the result:
+// lanes i ^ 1 and i ^ 2 (quad permutations), then i and 7 - i within each
+// half row, then i and 15 - i within the row.  All 16 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_row(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+  return __int_as_float(dpp_row<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_row<CTRL>((int)b), hi = dpp_row<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+struct OpMin {
+  template <typename V>
+  __device__ V operator()(V x, V y) const { return min(x, y); }
+};
+struct OpMax {
+  template <typename V>
+  __device__ V operator()(V x, V y) const { return max(x, y); }
+};
+struct OpAdd {
+  template <typename V>
+  __device__ V operator()(V x, V y) const { return x + y; }
+};
+template <typename V, typename Op>
+__device__ __forceinline__ V row_reduce(V v, Op op) {
+  v = op(v, dpp_row<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = op(v, dpp_row<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = op(v, dpp_row<0x141>(v));  // row_half_mirror
+  v = op(v, dpp_row<0x140>(v));  // row_mirror
+  return v;
+}
+
+// One DPP row (16 lanes) per cell, lanes over its points.
+constexpr uint32_t kCellLanes = 16;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
   const uint32_t nc = a.n_cells[0];
-  const uint32_t lane = (uint32_t)lane_id();
-  const uint32_t wpb = blockDim.x / kWave, nw = gridDim.x * wpb;
+  const uint32_t cnt = cf_count(a);
+  const uint32_t sl = (uint32_t)lane_id() % kCellLanes;
+  const uint32_t gpb = blockDim.x / kCellLanes, ng = gridDim.x * gpb;
   const size_t C = (size_t)a.ccap;
-  for (uint32_t id = blockIdx.x * wpb + threadIdx.x / kWave; id < nc; id += nw) {
+  for (uint32_t id = blockIdx.x * gpb + threadIdx.x / kCellLanes; id < nc; id += ng) {
     const uint32_t m = a.ccnt[id], o = a.coff[id];
     const int32_t* pts = a.order + o;
     int mn = INT_MAX;
     T lo[3] = {T(INFINITY), T(INFINITY), T(INFINITY)}, hi[3] = {-T(INFINITY), -T(INFINITY), -T(INFINITY)};
-    for (uint32_t k = lane; k < m; k += kWave) {
+    double sm[7] = {0, 0, 0, 0, 0, 0, 0};  // the cell's point and normal sums, count
+    for (uint32_t k = sl; k < m; k += kCellLanes) {
       mn = min(mn, pts[k]);
-      const Q4<T> q = cf_pt(a, o + k);
+      const Q4<T> q = cf_pt(a, o + k), w = cf_nr(a, o + k);
       lo[0] = min(lo[0], q.x); lo[1] = min(lo[1], q.y); lo[2] = min(lo[2], q.z);
       hi[0] = max(hi[0], q.x); hi[1] = max(hi[1], q.y); hi[2] = max(hi[2], q.z);
+      sm[0] += (double)q.x; sm[1] += (double)q.y; sm[2] += (double)q.z;
+      sm[3] += (double)w.x; sm[4] += (double)w.y; sm[5] += (double)w.z;
+      sm[6] += 1.0;
     }
-    mn = wave_min(mn);
+    mn = row_reduce(mn, OpMin());
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      lo[d] = wave_min(lo[d]);
-      hi[d] = wave_max(hi[d]);
+      lo[d] = row_reduce(lo[d], OpMin());
+      hi[d] = row_reduce(hi[d], OpMax());
+    }
+#pragma unroll
+    for (int d = 0; d < 7; ++d) sm[d] = row_reduce(sm[d], OpAdd());
+    if ((uint32_t)mn >= cnt) {  // never expected: keep the indices below valid
+      if (sl == 0) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+      mn = pts[0];
     }
     // one (pair, cell) per cell, else the 64-bit keys of two cells collided
     const T r = cf_radius(a, (uint32_t)mn);
@@ -1827,20 +1880,26 @@ __global__ void __launch_bounds__(256) k_cf_cells(ForceArgs<T> a) {
     const int pi = a.pi[mn], pj = a.pj[mn];
     const long long cx = (long long)floor(a.x[mn] * inv), cy = (long long)floor(a.x[C + mn] * inv),
                     cz = (long long)floor(a.x[2 * C + mn] * inv);
-    bool same = true;
-    for (uint32_t k = lane; k < m; k += kWave) {
+    int same = 1;
+    for (uint32_t k = sl; k < m; k += kCellLanes) {
       const Q4<T> q = cf_pt(a, o + k), w = cf_nr(a, o + k);
       same &= bits_int(q.w) == pi && bits_int(w.w) == pj && (long long)floor(q.x * inv) == cx &&
               (long long)floor(q.y * inv) == cy && (long long)floor(q.z * inv) == cz;
     }
-    const bool all_same = __ballot(!same) == 0ull;
-    if (lane == 0) {
-      if (!all_same) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+    same = row_reduce(same, OpMin());
+    if (sl == 0) {
+      if (!same) atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
       a.cmin[id] = mn;
       a.parent[mn] = mn;  // union-find runs over the cells' smallest contacts only
     }
-    if (lane < 7) a.acc[(size_t)lane * C + mn] = 0.0;
-    if (lane == 1) {
+    // the cell's sums at its smallest contact; k_cf_sum moves them to the group root
+    if (sl < 7) {
+      double v = sm[0];
+#pragma unroll
+      for (int d = 1; d < 7; ++d) v = sl == (uint32_t)d ? sm[d] : v;
+      a.acc[(size_t)sl * C + mn] = v;
+    }
+    if (sl == 7) {
       CellRec<T> cr;
       cr.cx = cx; cr.cy = cy; cr.cz = cz;
 #pragma unroll
@@ -2002,43 +2061,26 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_cf_sum(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
   const uint32_t nc = (a.scale > T(0)) ? a.n_cells[0] : 0u;
-  const uint32_t lane = (uint32_t)lane_id();
-  const uint32_t wpb = blockDim.x / kWave, nw = gridDim.x * wpb;
   const size_t C = (size_t)a.ccap;
-  // cells: one wave each, lanes over the points
-  for (uint32_t id = blockIdx.x * wpb + threadIdx.x / kWave; id < nc; id += nw) {
-    int r = 0;
-    if (lane == 0) {
-      uint32_t budget = kLinkBudget;
-      r = uf_root(a.parent, a.cmin[id], budget);
-      if (r < 0) {
-        atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
-        r = a.cmin[id];
-      }
+  // cells: the group root, and the cell's sums (at its smallest contact,
+  // which no other cell adds to unless it is the root) added there
+  for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < nc; id += gridDim.x * blockDim.x) {
+    uint32_t budget = kLinkBudget;
+    const int mn = a.cmin[id];
+    int r = uf_root(a.parent, mn, budget);
+    if (r < 0) {
+      atomicOr(a.status, DEM_DEV_QUEUE_OVERFLOW);
+      r = mn;
     }
-    r = __shfl(r, 0);
-    const uint32_t o = a.coff[id], m = a.ccnt[id];
-    const int32_t* pts = a.order + o;
-    double s[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (uint32_t k = lane; k < m; k += kWave) {
-      a.root[pts[k]] = r;
-      const Q4<T> q = cf_pt(a, o + k), w = cf_nr(a, o + k);
-      s[0] += (double)q.x; s[1] += (double)q.y; s[2] += (double)q.z;
-      s[3] += (double)w.x; s[4] += (double)w.y; s[5] += (double)w.z;
-      s[6] += 1.0;
-    }
+    a.root[id] = r;
+    if (r != mn) {
 #pragma unroll
-    for (int k = 0; k < 7; ++k) s[k] = wave_sum(s[k]);
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < 7; ++k) unsafeAtomicAdd(a.acc + (size_t)k * C + r, s[k]);
+      for (int k = 0; k < 7; ++k) unsafeAtomicAdd(a.acc + (size_t)k * C + r, a.acc[(size_t)k * C + mn]);
     }
   }
   // points in no cell (no merging, or skipped): their own groups
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
-    if (a.pcell[c] >= 0) continue;  // summed with its cell
-    a.root[c] = (int32_t)c;
-    if (!cf_valid(a, c)) continue;
+    if (a.pcell[c] >= 0 || !cf_valid(a, c)) continue;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       a.acc[(size_t)d * C + c] = (double)a.x[(size_t)d * C + c];
@@ -2048,12 +2090,19 @@ __global__ void __launch_bounds__(256) k_cf_sum(ForceArgs<T> a) {
   }
 }
 
+// Group root of contact c: its cell's, or itself outside any cell.
+template <typename T>
+__device__ __forceinline__ int cf_root_of(const ForceArgs<T>& a, uint32_t c) {
+  const int id = a.pcell[c];
+  return id >= 0 ? a.root[id] : (int)c;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_cf_emit(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
   for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
     const uint32_t c = base + threadIdx.x;
-    const bool is_root = c < cnt && a.root[c] == (int32_t)c && cf_valid(a, c);
+    const bool is_root = c < cnt && cf_valid(a, c) && cf_root_of(a, c) == (int)c;
     uint32_t ok;
     const uint32_t slot = wave_append(is_root, a.ocount, ok);
     if (!is_root) continue;
@@ -2119,7 +2168,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_cf_group(ForceArgs<T> a) {
   const uint32_t cnt = cf_count(a);
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x)
-    a.group[c] = cf_valid(a, c) ? a.mslot[a.root[c]] : -1;
+    a.group[c] = cf_valid(a, c) ? a.mslot[cf_root_of(a, c)] : -1;
 }
 
 __global__ void k_cf_reset(uint32_t* ocount) {
