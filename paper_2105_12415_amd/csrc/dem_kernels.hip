@@ -209,7 +209,7 @@ struct FlatArgs {
 // Soup record of triangle t: world vertices (pose applied), edges, the
 // regularised Newton diagonal and the topology word.
 template <typename T>
-__device__ __forceinline__ void flatten_one(const FlatArgs<T>& a, int t, int cb, int cc, int part) {
+__device__ __forceinline__ SoupRec<T> flatten_rec(const FlatArgs<T>& a, int t, int cb, int cc, int part) {
   const T* X = a.verts;
   const T* Y = a.verts + a.n_verts;
   const T* Z = a.verts + 2 * (size_t)a.n_verts;
@@ -240,29 +240,49 @@ __device__ __forceinline__ void flatten_one(const FlatArgs<T>& a, int t, int cb,
   const bool kids_fine = cc > 0 && cb >= a.fine_begin[part];
   r.topo[0] = cb; r.topo[1] = cc | (kids_fine ? kKidsFine : 0); r.topo[2] = part;
   r.topo[3] = __float_as_int(sz);
-  a.soup[t] = r;
   T chk = v0.x + v0.y + v0.z + e1.x + e1.y + e1.z + e2.x + e2.y + e2.z;
   if (!isfinite(chk)) atomicOr(a.status, DEM_DEV_NONFINITE);
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void flatten_one(const FlatArgs<T>& a, int t, int cb, int cc, int part) {
+  a.soup[t] = flatten_rec(a, t, cb, cc, part);
 }
 
 // Every triangle (eager), or the surrogates and root triangles only (lazy:
 // fine children are written by k_fine once a pair with their parent
 // survives).  Lazy mode also clears the surrogates' survival flags.
+// The block's records go through LDS so that the stores leave as whole
+// contiguous 16-byte chunks of the block's output range (a record per lane
+// would scatter each store instruction over 64 lines).  Launched with
+// kFlatBlock threads per block.
+constexpr int kFlatBlock = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_flatten(FlatArgs<T> a) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.n_tris) return;
-  const int cc = a.ccnt[t];
-  if (cc < 0 || cc > DEM_MAX_CHILDREN) atomicOr(a.status, DEM_DEV_BAD_TREE);
-  const int part = a.tpart[t];
-  if (a.lazy) {
-    if (cc > 0) {
-      a.mark[t] = 0;
-    } else if ((uint32_t)(t - a.root_begin[part]) >= (uint32_t)a.root_count[part]) {
-      return;  // a fine triangle below a surrogate
+__global__ void __launch_bounds__(kFlatBlock) k_flatten(FlatArgs<T> a) {
+  __shared__ SoupRec<T> stage[kFlatBlock];
+  __shared__ uint8_t act[kFlatBlock];
+  const int t = blockIdx.x * kFlatBlock + threadIdx.x;
+  bool on = t < a.n_tris;
+  if (on) {
+    const int cc = a.ccnt[t];
+    if (cc < 0 || cc > DEM_MAX_CHILDREN) atomicOr(a.status, DEM_DEV_BAD_TREE);
+    const int part = a.tpart[t];
+    if (a.lazy) {
+      if (cc > 0) a.mark[t] = 0;
+      else if ((uint32_t)(t - a.root_begin[part]) >= (uint32_t)a.root_count[part]) on = false;  // fine, below a surrogate
     }
+    if (on) stage[threadIdx.x] = flatten_rec(a, t, a.cbeg[t], cc, part);
   }
-  flatten_one(a, t, a.cbeg[t], cc, part);
+  act[threadIdx.x] = on ? 1 : 0;
+  __syncthreads();
+  constexpr int kChunks = (int)(sizeof(SoupRec<T>) / 16);
+  static_assert(sizeof(SoupRec<T>) % 16 == 0, "16-byte chunks");
+  const uint4* src = reinterpret_cast<const uint4*>(stage);
+  uint4* dst = reinterpret_cast<uint4*>(a.soup + (size_t)blockIdx.x * kFlatBlock);
+  for (int c = threadIdx.x; c < kFlatBlock * kChunks; c += kFlatBlock)
+    if (act[c / kChunks]) dst[c] = src[c];
 }
 
 // Lazy mode, after the descent at depth d: the children of every depth-d
@@ -2313,7 +2333,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   fa.mark = reinterpret_cast<uint8_t*>(base + L.mark);
   fa.lazy = p.mode == DEM_MODE_HIER && s->fine_parents != nullptr;
   fa.status = status;
-  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + 255) / 256), dim3(256), 0, st, fa);
+  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + kFlatBlock - 1) / kFlatBlock), dim3(kFlatBlock), 0, st, fa);
   mark();
   // per-segment capacities
   const int64_t qseg = p.queue_capacity / kSeg, nseg = p.near_capacity / kSeg;
@@ -2468,7 +2488,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   fl.mark = reinterpret_cast<uint8_t*>(base + FL.w.mark);
   fl.lazy = 0;  // leaves may sit at any depth: every record is written
   fl.status = status;
-  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + 255) / 256), dim3(256), 0, st, fl);
+  hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + kFlatBlock - 1) / kFlatBlock), dim3(kFlatBlock), 0, st, fl);
   mark();
   const int64_t nseg = p.near_capacity / kSeg;
   FrontierArgs fa{};
