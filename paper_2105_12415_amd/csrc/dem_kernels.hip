@@ -292,23 +292,45 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten(FlatArgs<T> a) {
 constexpr int kFineLanes = 4;
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_fine(FlatArgs<T> a, const int32_t* __restrict__ parents, int n) {
+__global__ void __launch_bounds__(kFlatBlock) k_fine(FlatArgs<T> a, const int32_t* __restrict__ parents, int n) {
+  // a lane's first child goes through LDS (whole 16-byte chunks of sibling
+  // records leave together, as in k_flatten); further children of a parent
+  // with more than kFineLanes are stored directly
+  __shared__ SoupRec<T> stage[kFlatBlock];
+  __shared__ int dest[kFlatBlock];
   const int64_t total = (int64_t)n * kFineLanes;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int s = parents[i / kFineLanes];
-    const int slot = (int)(i % kFineLanes);
-    if ((uint32_t)s >= (uint32_t)a.n_tris) {
-      if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
-      continue;
+  for (int64_t base = blockIdx.x * (int64_t)kFlatBlock; base < total; base += (int64_t)gridDim.x * kFlatBlock) {
+    const int64_t i = base + threadIdx.x;
+    int d = -1;
+    if (i < total) {
+      const int s = parents[i / kFineLanes];
+      const int slot = (int)(i % kFineLanes);
+      if ((uint32_t)s >= (uint32_t)a.n_tris) {
+        if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
+      } else if (a.mark[s]) {
+        const int cb = a.cbeg[s], cc = a.ccnt[s];
+        if (cc < 1 || cc > DEM_MAX_CHILDREN || cb < 0 || cb > a.n_tris - cc) {
+          if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
+        } else {
+          if (slot < cc) {
+            d = cb + slot;
+            stage[threadIdx.x] = flatten_rec(a, d, a.cbeg[d], a.ccnt[d], a.tpart[d]);
+          }
+          for (int c = cb + slot + kFineLanes; c < cb + cc; c += kFineLanes)
+            flatten_one(a, c, a.cbeg[c], a.ccnt[c], a.tpart[c]);
+        }
+      }
     }
-    if (!a.mark[s]) continue;
-    const int cb = a.cbeg[s], cc = a.ccnt[s];
-    if (cc < 1 || cc > DEM_MAX_CHILDREN || cb < 0 || cb > a.n_tris - cc) {
-      if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
-      continue;
+    dest[threadIdx.x] = d;
+    __syncthreads();
+    constexpr int kChunks = (int)(sizeof(SoupRec<T>) / 16);
+    const uint4* src = reinterpret_cast<const uint4*>(stage);
+    uint4* out = reinterpret_cast<uint4*>(a.soup);
+    for (int c = threadIdx.x; c < kFlatBlock * kChunks; c += kFlatBlock) {
+      const int dr = dest[c / kChunks];
+      if (dr >= 0) out[(size_t)dr * kChunks + c % kChunks] = src[c];
     }
-    for (int c = cb + slot; c < cb + cc; c += kFineLanes) flatten_one(a, c, a.cbeg[c], a.ccnt[c], a.tpart[c]);
+    __syncthreads();
   }
 }
 
@@ -2369,7 +2391,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         const int f0 = fa.lazy ? s->fine_parent_begin[lev] : 0;
         const int nf = fa.lazy ? s->fine_parent_begin[lev + 1] - f0 : 0;
         if (nf > 0)
-          hipLaunchKernelGGL(k_fine<T>, dim3(std::min((nf * kFineLanes + 255) / 256, 8192)), dim3(256), 0,
+          hipLaunchKernelGGL(k_fine<T>, dim3(std::min((nf * kFineLanes + kFlatBlock - 1) / kFlatBlock, 8192)), dim3(kFlatBlock), 0,
                              st, fa, s->fine_parents + f0, nf);
         mark();
       }
