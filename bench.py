@@ -562,7 +562,7 @@ def main():
         print(json.dumps({"calib_copy_bytes": 4 * n, "copies": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
