@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
   for (uint32_t first = (blockIdx.x / kSeg) * batch; first < fill; first += per * batch) {
     const int n = (int)min(batch, fill - first);
     const int4* seg_items = a.qin + (size_t)x * (size_t)a.qcap + first;
-    int np = 0;
+    int np = 0, quad_item = 1;
     if ((int)threadIdx.x < n) {
       int4 it = seg_items[threadIdx.x];
       if (it.y < 1 || it.y > DEM_MAX_CHILDREN || it.w < 1 || it.w > DEM_MAX_CHILDREN) {
@@ -527,17 +527,27 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
       }
       items[threadIdx.x] = it;
       np = it.y * it.w;
+      quad_item = it.y == 4 && it.w == 4;
     }
-    block_scan(np, offs, wsum, n);
-    const int total = offs[n];
-    // small batches (the usual 4x4 children products) map pair -> item
-    // through an LDS table; large ones (root chunks) search the offsets
-    const bool mapped = total <= BLOCK * 8 && n <= 256;
-    if (mapped && (int)threadIdx.x < n) {
-      const int o = offs[threadIdx.x];
-      for (int q = 0; q < np; ++q) owner_s[o + q] = (uint8_t)threadIdx.x;
+    // a batch of 4 x 4 products only (the subdivision's children): pair e is
+    // child pair e mod 16 of item e / 16, no scan or table needed
+    const bool quad = __syncthreads_and(quad_item) != 0;
+    int total;
+    bool mapped = false;
+    if (quad) {
+      total = 16 * n;
+    } else {
+      block_scan(np, offs, wsum, n);
+      total = offs[n];
+      // small batches map pair -> item through an LDS table; large ones
+      // (root chunks) search the offsets
+      mapped = total <= BLOCK * 8 && n <= 256;
+      if (mapped && (int)threadIdx.x < n) {
+        const int o = offs[threadIdx.x];
+        for (int q = 0; q < np; ++q) owner_s[o + q] = (uint8_t)threadIdx.x;
+      }
+      if (mapped) __syncthreads();
     }
-    if (mapped) __syncthreads();
     int round = 0;
     for (int base = 0; base < total; base += bdim, ++round) {
       const int e = base + (int)threadIdx.x;
@@ -545,23 +555,31 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
       int4 nx = make_int4(0, 0, 0, 0);
       int ci = 0, cj = 0;
       if (e < total) {
-        // item owning flat index e: last k with offs[k] <= e
-        int lo = 0, hi = n - 1;
-        if (mapped) {
-          lo = owner_s[e];
+        int4 it;
+        int qd, rr;
+        if (quad) {
+          it = items[e >> 4];
+          qd = (e >> 2) & 3;
+          rr = e & 3;
         } else {
-          while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (offs[mid] <= e) lo = mid; else hi = mid - 1;
+          // item owning flat index e: last k with offs[k] <= e
+          int lo = 0, hi = n - 1;
+          if (mapped) {
+            lo = owner_s[e];
+          } else {
+            while (lo < hi) {
+              int mid = (lo + hi + 1) >> 1;
+              if (offs[mid] <= e) lo = mid; else hi = mid - 1;
+            }
           }
+          it = items[lo];
+          const int l = e - offs[lo];
+          const int jn = it.w;
+          qd = (int)((float)l * rcp_fast((float)jn));
+          rr = l - qd * jn;
+          if (rr < 0) { qd -= 1; rr += jn; }
+          if (rr >= jn) { qd += 1; rr -= jn; }
         }
-        int4 it = items[lo];
-        int l = e - offs[lo];
-        int jn = it.w;
-        int qd = (int)((float)l * rcp_fast((float)jn));
-        int rr = l - qd * jn;
-        if (rr < 0) { qd -= 1; rr += jn; }
-        if (rr >= jn) { qd += 1; rr -= jn; }
         ci = it.x + qd;
         cj = it.z + rr;
         int cbi, cci, pi_, cbj, ccj, pj_;
