@@ -1189,6 +1189,7 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
   for (uint32_t base = lo; base < hi; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     bool near = false;
+    int dep = -1;  // the leaf's pair depth, for the per-depth evaluation counts
     const int4 lf = i < hi ? lin[i] : make_int4(0, 0, 0, 0);
     const bool valid = (uint32_t)lf.x < (uint32_t)a.n_tris && (uint32_t)lf.y < (uint32_t)a.n_tris;
     if (i < hi && !valid) {
@@ -1229,7 +1230,18 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
       near = out == kOutNear;
       my_unf += out == kOutUnfold;
       my_near += near;
-      atomicAdd(&hist[D], 1u);
+      if (D < (uint32_t)DEM_MAX_LEVELS) dep = (int)D;
+    }
+    if (a.stats) {
+      // one LDS atomic per depth present in the wave (most lanes share one)
+      unsigned long long pending = __ballot(dep >= 0);
+      while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int d0 = __shfl(dep, leader);
+        const unsigned long long same = __ballot(dep == d0) & pending;
+        if (lane_id() == leader) atomicAdd(&hist[d0], (uint32_t)__popcll(same));
+        pending &= ~same;
+      }
     }
     lds_append(near, make_int2((int)i, 0), qn.buf, &qn.n);
     __syncthreads();
