@@ -385,6 +385,27 @@ dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* cont
                                 const void* workspace, size_t workspace_bytes,
                                 uint32_t* dev_status, dem_stream_t stream);
 
+/*
+ * dem_sort_contacts -- a deterministic order for a contact list: contacts
+ * sorted by (ti, tj), the global triangle numbers (a contact's triangle pair
+ * is unique, so the order is total and the same on every run, whatever order
+ * the kernels' atomics produced).  All fields (pi, pj, ti, tj, d, x, n) move
+ * together, in place; the count is unchanged.  Contacts naming a triangle
+ * outside the scene come last in their input order and set DEM_DEV_BAD_TREE.
+ * Kernels only (no memset, no host synchronisation): graph-capturable.
+ *
+ * scene      the scene the contacts refer to (its n_tris sizes the buckets).
+ * contacts   device SoA as written by dem_find_contacts or dem_frontier_step;
+ *            the first min(*count, capacity) entries are sorted.
+ * workspace  device, >= dem_sort_contacts_workspace_bytes(scene, capacity)
+ *            bytes, 256-byte aligned; scratch only.
+ * dev_status device uint32: DEM_DEV_* bits are OR-ed in (not cleared).
+ * Cost: O(n_tris + count) plus an insertion sort within each t_i bucket.
+ */
+size_t dem_sort_contacts_workspace_bytes(const dem_scene* scene, int64_t contact_capacity);
+dem_status dem_sort_contacts(const dem_scene* scene, const dem_contacts* contacts, void* workspace,
+                             size_t workspace_bytes, uint32_t* dev_status, dem_stream_t stream);
+
 /* ------------------------------------------------------------------ frontier */
 
 /*

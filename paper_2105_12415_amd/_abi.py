@@ -30,7 +30,8 @@ EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "d
            "dem_find_contacts", "dem_contact_backward", "dem_status_string", "dem_version",
            "dem_default_tree_opts", "dem_build_surrogate_tree", "dem_surrogate_tree_free",
            "dem_frontier_workspace_bytes", "dem_frontier_init", "dem_frontier_step",
-           "dem_contact_forces_workspace_bytes", "dem_contact_forces")
+           "dem_contact_forces_workspace_bytes", "dem_contact_forces",
+           "dem_sort_contacts_workspace_bytes", "dem_sort_contacts")
 
 
 class BuildOpts(C.Structure):
@@ -143,6 +144,10 @@ def lib():
         L.dem_find_contacts.argtypes = [C.POINTER(Scene), vp, C.c_int32, C.POINTER(Params),
                                         C.POINTER(Contacts), vp, C.c_size_t, vp, vp, vp, vp]
         L.dem_find_contacts.restype = C.c_int
+        L.dem_sort_contacts_workspace_bytes.argtypes = [C.POINTER(Scene), C.c_int64]
+        L.dem_sort_contacts_workspace_bytes.restype = C.c_size_t
+        L.dem_sort_contacts.argtypes = [C.POINTER(Scene), C.POINTER(Contacts), vp, C.c_size_t, vp, vp]
+        L.dem_sort_contacts.restype = C.c_int
         L.dem_contact_backward.argtypes = [C.POINTER(Scene), C.POINTER(Contacts), C.c_double, vp, vp,
                                            vp, vp, C.c_size_t, vp, vp]
         L.dem_contact_backward.restype = C.c_int

@@ -283,18 +283,43 @@ class ContactBuffers:
         return s
 
 
+class ContactSorter:
+    """dem_sort_contacts with its workspace: a contact list of up to
+    ``capacity`` entries put in (ti, tj) order, in place, on the current
+    stream (graph-capturable)."""
+
+    def __init__(self, ds: "DeviceScene", capacity: int):
+        self.ds, self.capacity = ds, int(capacity)
+        nbytes = lib().dem_sort_contacts_workspace_bytes(C.byref(ds.c), self.capacity)
+        if nbytes == 0:
+            raise DemError("dem_sort_contacts_workspace_bytes rejected the scene or capacity")
+        self.ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=ds.device)
+        self.ws_ptr = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        self.ws_bytes = int(nbytes)
+
+    def run(self, contacts: "ContactBuffers", status: torch.Tensor):
+        assert contacts.capacity <= self.capacity
+        cs = contacts.c()
+        st = lib().dem_sort_contacts(C.byref(self.ds.c), C.byref(cs), C.c_void_p(self.ws_ptr), self.ws_bytes,
+                                     _ptr(status), C.c_void_p(torch.cuda.current_stream(self.ds.device).cuda_stream))
+        check(st, "dem_sort_contacts")
+
+
 class ContactEngine:
     """Preallocated buffers + the C-ABI calls for one scene.
 
-    ``forward()`` enqueues dem_find_contacts (contacts and energy),
+    ``forward()`` enqueues dem_find_contacts (contacts and energy), and with
+    ``deterministic`` dem_sort_contacts after it (contacts in (ti, tj) order);
     ``backward()`` dem_contact_backward.  Neither synchronises, so a step can
     be captured in a CUDA/HIP graph; ``check()`` synchronises and raises on
     device-reported overflow.
     """
 
     def __init__(self, ds: DeviceScene, params: Optional[_abi.Params] = None,
-                 contact_capacity: Optional[int] = None, energy_k: float = 1e4):
+                 contact_capacity: Optional[int] = None, energy_k: float = 1e4, deterministic: bool = False):
         self.ds = ds
+        self.deterministic = deterministic
+        self.sorter = None
         self.p = params if params is not None else make_params("hier")
         self.p.energy_k = float(energy_k)
         dev = ds.device
@@ -335,6 +360,10 @@ class ContactEngine:
                                      self.ws_bytes, _ptr(self.stats), _ptr(self.status),
                                      _ptr(self.energy) if with_energy else None, self._stream())
         check(st, "dem_find_contacts")
+        if self.deterministic:
+            if self.sorter is None or self.sorter.capacity < self.contacts.capacity:
+                self.sorter = ContactSorter(self.ds, self.contacts.capacity)
+            self.sorter.run(self.contacts, self.status)
 
     def backward(self, grad_verts: torch.Tensor, grad_E: Optional[torch.Tensor] = None,
                  energy: bool = False):

@@ -145,6 +145,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 template <typename V>
 __device__ __forceinline__ V wave_min(V v) {
 #pragma unroll
@@ -2711,6 +2717,243 @@ dem_status run_forces(const dem_scene* s, const dem_contacts* c, const void* mas
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
 
+
+// ------------------------------------------------------------------ deterministic order
+// dem_sort_contacts: the contacts reordered by (t_i, t_j), the global triangle
+// numbers (a contact's triangle pair is unique, so the order is total): a
+// counting sort by t_i, with the bucket offsets from a prefix sum over the
+// triangles, then every bucket sorted by t_j.  Kernels only, so the call can
+// be captured in a graph.  Contacts naming a triangle outside the scene keep
+// their relative order after all others (and are flagged).
+constexpr uint32_t kSortThreads = 256;
+constexpr uint32_t kSortPer = 16;                          // buckets per thread in the scan
+constexpr uint32_t kSortChunk = kSortThreads * kSortPer;   // buckets per scan block
+
+struct SortArgs {
+  int32_t* pi;
+  int32_t* pj;
+  int32_t* ti;
+  int32_t* tj;
+  void* d;
+  void* x;
+  void* n;
+  const uint32_t* count;
+  int64_t cap;
+  uint32_t n_buckets;         // n_tris + 1 (the last one: invalid triangle numbers)
+  uint32_t* hist;             // [n_buckets]: counts, then exclusive offsets
+  uint32_t* fill;             // [n_buckets]
+  unsigned long long* bsum;   // [scan blocks + 1]
+  int32_t* idx;               // [cap]: input contact of every output position
+  char* tmp;                  // [cap] records of the reordered fields
+  uint32_t* status;
+};
+
+struct SortLayout {
+  size_t hist, fill, bsum, idx, tmp, total;
+  uint32_t n_buckets, n_blocks;
+};
+
+__device__ __forceinline__ uint32_t cs_count(const SortArgs& a) {
+  return (uint32_t)min((uint64_t)*a.count, (uint64_t)a.cap);
+}
+
+__device__ __forceinline__ uint32_t cs_bucket(const SortArgs& a, uint32_t c) {
+  const uint32_t t = (uint32_t)a.ti[c];
+  return t < a.n_buckets - 1 ? t : a.n_buckets - 1;
+}
+
+__global__ void k_cs_clear(SortArgs a) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < a.n_buckets; k += gridDim.x * blockDim.x) {
+    a.hist[k] = 0;
+    a.fill[k] = 0;
+  }
+}
+
+__global__ void k_cs_count(SortArgs a) {
+  const uint32_t cnt = cs_count(a);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
+    const uint32_t b = cs_bucket(a, c);
+    if (b == a.n_buckets - 1 || (uint32_t)a.tj[c] >= a.n_buckets - 1) atomicOr(a.status, DEM_DEV_BAD_TREE);
+    atomicAdd(a.hist + b, 1u);
+  }
+}
+
+// Scan block b covers buckets [b * kSortChunk, ...): thread t its kSortPer
+// consecutive buckets.
+__global__ void __launch_bounds__(kSortThreads) k_cs_bsum(SortArgs a) {
+  __shared__ unsigned long long red[kSortThreads / kWave];
+  const uint32_t lo = blockIdx.x * kSortChunk + threadIdx.x * kSortPer;
+  unsigned long long s = 0;
+  for (uint32_t k = 0; k < kSortPer; ++k)
+    if (lo + k < a.n_buckets) s += a.hist[lo + k];
+  s = wave_sum_u64(s);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (uint32_t w = 0; w < kSortThreads / kWave; ++w) t += red[w];
+    a.bsum[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_cs_top(SortArgs a, uint32_t n_blocks) {
+  block_scan_u64(a.bsum, n_blocks);
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_cs_local(SortArgs a) {
+  __shared__ unsigned long long wsum[kSortThreads / kWave];
+  const uint32_t lo = blockIdx.x * kSortChunk + threadIdx.x * kSortPer;
+  uint32_t v[kSortPer];
+  unsigned long long s = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kSortPer; ++k) {
+    v[k] = lo + k < a.n_buckets ? a.hist[lo + k] : 0u;
+    s += v[k];
+  }
+  const int lane = lane_id(), wid = threadIdx.x / kWave;
+  unsigned long long x = s;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = x;
+  __syncthreads();
+  unsigned long long before = a.bsum[blockIdx.x];
+  for (int w = 0; w < wid; ++w) before += wsum[w];
+  unsigned long long run = before + x - s;
+#pragma unroll
+  for (uint32_t k = 0; k < kSortPer; ++k) {
+    if (lo + k < a.n_buckets) a.hist[lo + k] = (uint32_t)run;
+    run += v[k];
+  }
+}
+
+__global__ void k_cs_scatter(SortArgs a) {
+  const uint32_t cnt = cs_count(a);
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
+    const uint32_t b = cs_bucket(a, c);
+    a.idx[a.hist[b] + atomicAdd(a.fill + b, 1u)] = (int32_t)c;
+  }
+}
+
+// Every bucket by t_j (the last bucket, of invalid triangle numbers, by
+// input position): insertion sort, one thread per bucket.
+__global__ void k_cs_bucket(SortArgs a) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < a.n_buckets; b += gridDim.x * blockDim.x) {
+    const uint32_t lo = a.hist[b], m = a.fill[b];
+    if (m < 2) continue;
+    const bool by_input = b == a.n_buckets - 1;
+    int32_t* e = a.idx + lo;
+    for (uint32_t i = 1; i < m; ++i) {
+      const int32_t c = e[i];
+      const int64_t key = by_input ? c : a.tj[c];
+      uint32_t j = i;
+      while (j > 0) {
+        const int32_t p = e[j - 1];
+        const int64_t kp = by_input ? p : a.tj[p];
+        if (kp <= key) break;
+        e[j] = p;
+        --j;
+      }
+      e[j] = c;
+    }
+  }
+}
+
+template <typename T>
+struct SortRec {
+  int32_t pi, pj, ti, tj;
+  T d, x[3], n[3];
+};
+
+template <typename T>
+__global__ void k_cs_gather(SortArgs a) {
+  const uint32_t cnt = cs_count(a);
+  const T* d = static_cast<const T*>(a.d);
+  const T* x = static_cast<const T*>(a.x);
+  const T* n = static_cast<const T*>(a.n);
+  SortRec<T>* out = reinterpret_cast<SortRec<T>*>(a.tmp);
+  const size_t C = (size_t)a.cap;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+    const int32_t c = a.idx[k];
+    SortRec<T> r;
+    r.pi = a.pi[c]; r.pj = a.pj[c]; r.ti = a.ti[c]; r.tj = a.tj[c];
+    r.d = d[c];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      r.x[q] = x[q * C + c];
+      r.n[q] = n[q * C + c];
+    }
+    out[k] = r;
+  }
+}
+
+template <typename T>
+__global__ void k_cs_write(SortArgs a) {
+  const uint32_t cnt = cs_count(a);
+  T* d = static_cast<T*>(a.d);
+  T* x = static_cast<T*>(a.x);
+  T* n = static_cast<T*>(a.n);
+  const SortRec<T>* in = reinterpret_cast<const SortRec<T>*>(a.tmp);
+  const size_t C = (size_t)a.cap;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+    const SortRec<T> r = in[k];
+    a.pi[k] = r.pi; a.pj[k] = r.pj; a.ti[k] = r.ti; a.tj[k] = r.tj;
+    d[k] = r.d;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      x[q * C + k] = r.x[q];
+      n[q * C + k] = r.n[q];
+    }
+  }
+}
+
+SortLayout sort_layout(int32_t n_tris, int64_t cap) {
+  SortLayout L;
+  L.n_buckets = (uint32_t)n_tris + 1;
+  L.n_blocks = (L.n_buckets + kSortChunk - 1) / kSortChunk;
+  const size_t B = L.n_buckets, C = (size_t)std::max<int64_t>(cap, 1);
+  size_t o = 0;
+  L.hist = o; o = align_up(o + 4 * B, 256);
+  L.fill = o; o = align_up(o + 4 * B, 256);
+  L.bsum = o; o = align_up(o + 8 * ((size_t)L.n_blocks + 1), 256);
+  L.idx = o; o = align_up(o + 4 * C, 256);
+  L.tmp = o; o = align_up(o + sizeof(SortRec<double>) * C, 256);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+dem_status run_sort(const dem_contacts* c, int32_t n_tris, void* ws, const SortLayout& L, uint32_t* status,
+                    hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  SortArgs a;
+  a.pi = c->pi; a.pj = c->pj; a.ti = c->ti; a.tj = c->tj;
+  a.d = c->d; a.x = c->x; a.n = c->n;
+  a.count = c->count;
+  a.cap = c->capacity;
+  a.n_buckets = L.n_buckets;
+  a.hist = reinterpret_cast<uint32_t*>(base + L.hist);
+  a.fill = reinterpret_cast<uint32_t*>(base + L.fill);
+  a.bsum = reinterpret_cast<unsigned long long*>(base + L.bsum);
+  a.idx = reinterpret_cast<int32_t*>(base + L.idx);
+  a.tmp = base + L.tmp;
+  a.status = status;
+  (void)n_tris;
+  const dim3 g(2048), b(256);
+  hipLaunchKernelGGL(k_cs_clear, dim3(4096), b, 0, st, a);
+  hipLaunchKernelGGL(k_cs_count, g, b, 0, st, a);
+  hipLaunchKernelGGL(k_cs_bsum, dim3(L.n_blocks), dim3(kSortThreads), 0, st, a);
+  hipLaunchKernelGGL(k_cs_top, dim3(1), dim3(kScanThreads), 0, st, a, L.n_blocks);
+  hipLaunchKernelGGL(k_cs_local, dim3(L.n_blocks), dim3(kSortThreads), 0, st, a);
+  hipLaunchKernelGGL(k_cs_scatter, g, b, 0, st, a);
+  hipLaunchKernelGGL(k_cs_bucket, dim3(4096), b, 0, st, a);
+  hipLaunchKernelGGL(k_cs_gather<T>, g, b, 0, st, a);
+  hipLaunchKernelGGL(k_cs_write<T>, g, b, 0, st, a);
+  return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2851,6 +3094,25 @@ dem_status dem_frontier_step(const dem_scene* scene, const dem_params* pp, const
   if (scene->precision == DEM_F64)
     return run_frontier_step<double>(scene, p, f, out, workspace, FL, dev_stats, dev_status, dev_energy, st);
   return run_frontier_step<float>(scene, p, f, out, workspace, FL, dev_stats, dev_status, dev_energy, st);
+}
+
+size_t dem_sort_contacts_workspace_bytes(const dem_scene* scene, int64_t contact_capacity) {
+  if (!scene || scene->n_tris <= 0 || contact_capacity < 0 || contact_capacity > (int64_t)0xFFFFFFFF) return 0;
+  return sort_layout(scene->n_tris, contact_capacity).total;
+}
+
+dem_status dem_sort_contacts(const dem_scene* scene, const dem_contacts* c, void* workspace, size_t workspace_bytes,
+                             uint32_t* dev_status, dem_stream_t stream) {
+  if (!scene_ok(scene) || !c || !c->count || !dev_status || !workspace) return DEM_ERR_ARG;
+  if (c->capacity < 0 || c->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
+  if (c->capacity > 0 && (!c->pi || !c->pj || !c->ti || !c->tj || !c->d || !c->x || !c->n)) return DEM_ERR_ARG;
+  const SortLayout L = sort_layout(scene->n_tris, c->capacity);
+  if (workspace_bytes < L.total) return DEM_ERR_CAPACITY;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
+  if (c->capacity == 0) return DEM_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (scene->precision == DEM_F64) return run_sort<double>(c, scene->n_tris, workspace, L, dev_status, st);
+  return run_sort<float>(c, scene->n_tris, workspace, L, dev_status, st);
 }
 
 size_t dem_contact_forces_workspace_bytes(int64_t contact_capacity) {

@@ -543,3 +543,63 @@ def test_reduced_precision_iteration_keeps_the_contacts(half_depths):
     assert len(k32) > 100 and k32 == k16
     say(f"evals fp32 {s32['evals'][:3].tolist()} half {s16['evals'][:3].tolist()}")
     assert s16["evals"].sum() <= 1.05 * s32["evals"].sum()
+
+
+# ------------------------------------------------------------------ deterministic order
+def _keys(r):
+    return (r["ti"].astype(np.int64) << 32) | r["tj"].astype(np.int64)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_deterministic_contact_order(prec):
+    """dem_sort_contacts: the contacts come in strictly increasing (ti, tj)
+    order, the arrays are identical on every run, and set and values are the
+    unsorted forward's."""
+    if prec == "f32":
+        scene = sg.two_spheres(4, [2, 3, 4], "f32", 2.02, 4, "two_spheres_s4_f32")
+    else:
+        scene = sg.two_spheres_s3_f64()
+    ds = api.DeviceScene(scene, device="cuda:0")
+    plain = api.ContactEngine(ds, api.make_params("hier"))
+    assert plain.run() == 0
+    r0 = plain.result()
+    det = api.ContactEngine(ds, api.make_params("hier"), deterministic=True)
+    runs = []
+    for _ in range(3):
+        assert det.run() == 0
+        runs.append(det.result())
+    k = _keys(runs[0])
+    assert len(k) > 100 and np.all(np.diff(k) > 0)
+    for r in runs[1:]:
+        for f in ("pi", "pj", "ti", "tj", "d", "x", "n"):
+            assert np.array_equal(r[f], runs[0][f]), f
+    o = np.argsort(_keys(r0))
+    assert np.array_equal(_keys(r0)[o], k)
+    for f in ("pi", "pj", "d", "x", "n"):
+        assert np.array_equal(r0[f][o], runs[0][f]), f
+
+
+def test_deterministic_order_in_a_graph():
+    """Forward + sort captured in one HIP graph, replayed twice with eager work
+    in between: the same arrays as the eager deterministic forward."""
+    scene = sg.two_spheres(4, [2, 3, 4], "f32", 2.02, 4, "two_spheres_s4_f32")
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params("hier"), deterministic=True)
+    assert eng.run() == 0
+    ref = eng.result()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            eng.forward()
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(2):
+        eng.forward()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert eng.check() == 0
+        got = eng.result()
+        for f in ("pi", "pj", "ti", "tj", "d", "x", "n"):
+            assert np.array_equal(got[f], ref[f]), (rep, f)
