@@ -2745,11 +2745,13 @@ struct SortArgs {
   unsigned long long* bsum;   // [scan blocks + 1]
   int32_t* idx;               // [cap]: input contact of every output position
   char* tmp;                  // [cap] records of the reordered fields
+  uint32_t* blist;            // [n_buckets]: buckets of two or more contacts
+  uint32_t* blist_n;          // their number
   uint32_t* status;
 };
 
 struct SortLayout {
-  size_t hist, fill, bsum, idx, tmp, total;
+  size_t hist, fill, bsum, idx, tmp, blist, total;
   uint32_t n_buckets, n_blocks;
 };
 
@@ -2767,14 +2769,41 @@ __global__ void k_cs_clear(SortArgs a) {
     a.hist[k] = 0;
     a.fill[k] = 0;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.blist_n = 0;
+}
+
+// Runs of neighbouring lanes with one bucket (the contacts of one triangle
+// come in short runs): the run's first lane counts or reserves for all of it.
+struct LaneRun {
+  bool lead;      // first lane of its run
+  int len;        // run length (at the leader)
+  int leader;     // the run's first lane
+};
+
+__device__ __forceinline__ LaneRun lane_run(bool act, uint32_t key) {
+  const int lane = lane_id();
+  const uint32_t prev = __shfl_up(key, 1);
+  const bool prev_act = __shfl_up((int)act, 1) != 0;
+  LaneRun r;
+  r.lead = act && (lane == 0 || !prev_act || prev != key);
+  const unsigned long long leaders = __ballot(r.lead), members = __ballot(act);
+  const unsigned long long after = lane == 63 ? 0ull : (~0ull << (lane + 1));
+  const unsigned long long stops = (leaders | ~members) & after;
+  r.len = (stops ? __ffsll((long long)stops) - 1 : 64) - lane;
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  r.leader = act ? 63 - __clzll((long long)(leaders & upto)) : lane;
+  return r;
 }
 
 __global__ void k_cs_count(SortArgs a) {
   const uint32_t cnt = cs_count(a);
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
-    const uint32_t b = cs_bucket(a, c);
-    if (b == a.n_buckets - 1 || (uint32_t)a.tj[c] >= a.n_buckets - 1) atomicOr(a.status, DEM_DEV_BAD_TREE);
-    atomicAdd(a.hist + b, 1u);
+  for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    const bool act = c < cnt;
+    const uint32_t b = act ? cs_bucket(a, c) : 0u;
+    if (act && (b == a.n_buckets - 1 || (uint32_t)a.tj[c] >= a.n_buckets - 1)) atomicOr(a.status, DEM_DEV_BAD_TREE);
+    const LaneRun r = lane_run(act, b);
+    if (r.lead) atomicAdd(a.hist + b, (uint32_t)r.len);
   }
 }
 
@@ -2831,33 +2860,84 @@ __global__ void __launch_bounds__(kSortThreads) k_cs_local(SortArgs a) {
 
 __global__ void k_cs_scatter(SortArgs a) {
   const uint32_t cnt = cs_count(a);
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < cnt; c += gridDim.x * blockDim.x) {
-    const uint32_t b = cs_bucket(a, c);
-    a.idx[a.hist[b] + atomicAdd(a.fill + b, 1u)] = (int32_t)c;
+  const int lane = lane_id();
+  for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+    const uint32_t c = base + threadIdx.x;
+    const bool act = c < cnt;
+    const uint32_t b = act ? cs_bucket(a, c) : 0u;
+    const LaneRun r = lane_run(act, b);
+    uint32_t pos = 0;
+    if (r.lead) pos = a.hist[b] + atomicAdd(a.fill + b, (uint32_t)r.len);
+    pos = __shfl(pos, r.leader) + (uint32_t)(lane - r.leader);
+    if (act) a.idx[pos] = (int32_t)c;
   }
 }
 
 // Every bucket by t_j (the last bucket, of invalid triangle numbers, by
-// input position): insertion sort, one thread per bucket.
-__global__ void k_cs_bucket(SortArgs a) {
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < a.n_buckets; b += gridDim.x * blockDim.x) {
-    const uint32_t lo = a.hist[b], m = a.fill[b];
-    if (m < 2) continue;
-    const bool by_input = b == a.n_buckets - 1;
-    int32_t* e = a.idx + lo;
-    for (uint32_t i = 1; i < m; ++i) {
-      const int32_t c = e[i];
-      const int64_t key = by_input ? c : a.tj[c];
-      uint32_t j = i;
-      while (j > 0) {
-        const int32_t p = e[j - 1];
-        const int64_t kp = by_input ? p : a.tj[p];
-        if (kp <= key) break;
-        e[j] = p;
-        --j;
+// input position).  A lane looks at one bucket; the wave then sorts its
+// lanes' buckets of two or more contacts one after the other, by ranks: every
+// contact's position is the number of smaller keys in its bucket (the keys of
+// a bucket are distinct).  Lanes hold 64 contacts at a time and count against
+// the bucket's keys streamed through the wave's LDS slice in chunks; the
+// ranked contacts go through the staging area and back.
+constexpr uint32_t kBucketLds = 512;
+
+__device__ __forceinline__ long long cs_key(const SortArgs& a, bool by_input, int32_t c) {
+  return by_input ? (long long)c : (long long)a.tj[c];
+}
+
+// The buckets to sort (two or more contacts), listed so that the sorting
+// waves share them evenly (contacts cluster in the triangle numbering).
+__global__ void k_cs_list(SortArgs a) {
+  for (uint32_t base = blockIdx.x * blockDim.x; base < a.n_buckets; base += gridDim.x * blockDim.x) {
+    const uint32_t b = base + threadIdx.x;
+    const bool need = b < a.n_buckets && a.fill[b] >= 2;
+    uint32_t ok;
+    const uint32_t slot = wave_append(need, a.blist_n, ok);
+    if (need && ok && slot < a.n_buckets) a.blist[slot] = b;
+  }
+}
+
+// One wave per listed bucket.
+__global__ void __launch_bounds__(256) k_cs_bucket(SortArgs a) {
+  __shared__ long long skey[256 / kWave][kBucketLds];
+  const uint32_t lane = (uint32_t)lane_id();
+  const int w = threadIdx.x / kWave;
+  int32_t* stage = reinterpret_cast<int32_t*>(a.tmp);  // free until the gather
+  const uint32_t nl = min(*a.blist_n, a.n_buckets);
+  const uint32_t nw = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t q = blockIdx.x * (blockDim.x / kWave) + (uint32_t)w; q < nl; q += nw) {
+    const uint32_t bw = a.blist[q];
+    const uint32_t mw = a.fill[bw], low = a.hist[bw];
+    const bool by_input = bw == a.n_buckets - 1;
+    int32_t* e = a.idx + low;
+    for (uint32_t k0 = 0; k0 < mw; k0 += kWave) {
+      const uint32_t k = k0 + lane;
+      const bool act = k < mw;
+      const int32_t v = act ? e[k] : 0;
+      const long long kk = act ? cs_key(a, by_input, v) : LLONG_MAX;
+      uint32_t rank = 0;
+      if (mw <= (uint32_t)kWave) {
+        skey[w][lane] = kk;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t j = 0; j < mw; ++j) rank += skey[w][j] < kk ? 1u : 0u;
+        __builtin_amdgcn_wave_barrier();
+      } else {
+        for (uint32_t c0 = 0; c0 < mw; c0 += kBucketLds) {
+          const uint32_t n = min(kBucketLds, mw - c0);
+          for (uint32_t r = lane; r < n; r += kWave) skey[w][r] = cs_key(a, by_input, e[c0 + r]);
+          __builtin_amdgcn_wave_barrier();
+          for (uint32_t j = 0; j < n; ++j) rank += skey[w][j] < kk ? 1u : 0u;
+          __builtin_amdgcn_wave_barrier();
+        }
       }
-      e[j] = c;
+      if (act) stage[low + rank] = v;
     }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t k = lane; k < mw; k += kWave) e[k] = stage[low + k];
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -2920,6 +3000,7 @@ SortLayout sort_layout(int32_t n_tris, int64_t cap) {
   L.bsum = o; o = align_up(o + 8 * ((size_t)L.n_blocks + 1), 256);
   L.idx = o; o = align_up(o + 4 * C, 256);
   L.tmp = o; o = align_up(o + sizeof(SortRec<double>) * C, 256);
+  L.blist = o; o = align_up(o + 4 * (B + 1), 256);
   L.total = o;
   return L;
 }
@@ -2939,6 +3020,8 @@ dem_status run_sort(const dem_contacts* c, int32_t n_tris, void* ws, const SortL
   a.bsum = reinterpret_cast<unsigned long long*>(base + L.bsum);
   a.idx = reinterpret_cast<int32_t*>(base + L.idx);
   a.tmp = base + L.tmp;
+  a.blist = reinterpret_cast<uint32_t*>(base + L.blist);
+  a.blist_n = a.blist + L.n_buckets;
   a.status = status;
   (void)n_tris;
   const dim3 g(2048), b(256);
@@ -2948,6 +3031,7 @@ dem_status run_sort(const dem_contacts* c, int32_t n_tris, void* ws, const SortL
   hipLaunchKernelGGL(k_cs_top, dim3(1), dim3(kScanThreads), 0, st, a, L.n_blocks);
   hipLaunchKernelGGL(k_cs_local, dim3(L.n_blocks), dim3(kSortThreads), 0, st, a);
   hipLaunchKernelGGL(k_cs_scatter, g, b, 0, st, a);
+  hipLaunchKernelGGL(k_cs_list, dim3(4096), b, 0, st, a);
   hipLaunchKernelGGL(k_cs_bucket, dim3(4096), b, 0, st, a);
   hipLaunchKernelGGL(k_cs_gather<T>, g, b, 0, st, a);
   hipLaunchKernelGGL(k_cs_write<T>, g, b, 0, st, a);
