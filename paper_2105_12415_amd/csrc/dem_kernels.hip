@@ -2877,9 +2877,10 @@ __global__ void k_cs_scatter(SortArgs a) {
 // input position).  A lane looks at one bucket; the wave then sorts its
 // lanes' buckets of two or more contacts one after the other, by ranks: every
 // contact's position is the number of smaller keys in its bucket (the keys of
-// a bucket are distinct).  Lanes hold 64 contacts at a time and count against
-// the bucket's keys streamed through the wave's LDS slice in chunks; the
-// ranked contacts go through the staging area and back.
+// a bucket are distinct).  A bucket of up to 64 contacts is ranked with one
+// contact per lane and placed directly; a longer one 64 contacts at a time
+// against its keys streamed through the wave's LDS slice in chunks, placed
+// through the staging area and copied back.
 constexpr uint32_t kBucketLds = 512;
 
 __device__ __forceinline__ long long cs_key(const SortArgs& a, bool by_input, int32_t c) {
@@ -2911,32 +2912,39 @@ __global__ void __launch_bounds__(256) k_cs_bucket(SortArgs a) {
     const uint32_t mw = a.fill[bw], low = a.hist[bw];
     const bool by_input = bw == a.n_buckets - 1;
     int32_t* e = a.idx + low;
+    if (mw <= (uint32_t)kWave) {
+      // one contact per lane: every read of the bucket precedes the writes
+      const bool act = lane < mw;
+      const int32_t v = act ? e[lane] : 0;
+      const long long kk = act ? cs_key(a, by_input, v) : LLONG_MAX;
+      skey[w][lane] = kk;
+      __builtin_amdgcn_wave_barrier();
+      uint32_t rank = 0;
+      for (uint32_t j = 0; j < mw; ++j) rank += skey[w][j] < kk ? 1u : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (act) e[rank] = v;
+      continue;
+    }
     for (uint32_t k0 = 0; k0 < mw; k0 += kWave) {
       const uint32_t k = k0 + lane;
       const bool act = k < mw;
       const int32_t v = act ? e[k] : 0;
       const long long kk = act ? cs_key(a, by_input, v) : LLONG_MAX;
       uint32_t rank = 0;
-      if (mw <= (uint32_t)kWave) {
-        skey[w][lane] = kk;
+      for (uint32_t c0 = 0; c0 < mw; c0 += kBucketLds) {
+        const uint32_t n = min(kBucketLds, mw - c0);
+        for (uint32_t r = lane; r < n; r += kWave) skey[w][r] = cs_key(a, by_input, e[c0 + r]);
         __builtin_amdgcn_wave_barrier();
-        for (uint32_t j = 0; j < mw; ++j) rank += skey[w][j] < kk ? 1u : 0u;
+        for (uint32_t j = 0; j < n; ++j) rank += skey[w][j] < kk ? 1u : 0u;
         __builtin_amdgcn_wave_barrier();
-      } else {
-        for (uint32_t c0 = 0; c0 < mw; c0 += kBucketLds) {
-          const uint32_t n = min(kBucketLds, mw - c0);
-          for (uint32_t r = lane; r < n; r += kWave) skey[w][r] = cs_key(a, by_input, e[c0 + r]);
-          __builtin_amdgcn_wave_barrier();
-          for (uint32_t j = 0; j < n; ++j) rank += skey[w][j] < kk ? 1u : 0u;
-          __builtin_amdgcn_wave_barrier();
-        }
       }
       if (act) stage[low + rank] = v;
     }
-    __threadfence_block();
+    // lanes read back what other lanes placed: device-scope fences
+    __threadfence();
     __builtin_amdgcn_wave_barrier();
     for (uint32_t k = lane; k < mw; k += kWave) e[k] = stage[low + k];
-    __threadfence_block();
+    __threadfence();
     __builtin_amdgcn_wave_barrier();
   }
 }
