@@ -116,6 +116,30 @@ def test_workspace_bytes_and_validation():
     assert st == _abi.DEM_ERR_ARG
 
 
+def test_sort_contacts_sizing_and_validation():
+    """dem_sort_contacts: workspace grows with the triangle count and the
+    capacity; bad arguments are rejected before any device work."""
+    L = _abi.lib()
+    s = _fake_scene()
+    n0 = L.dem_sort_contacts_workspace_bytes(C.byref(s), 0)
+    n1 = L.dem_sort_contacts_workspace_bytes(C.byref(s), 1 << 20)
+    assert 0 < n0 < n1
+    assert L.dem_sort_contacts_workspace_bytes(C.byref(s), -1) == 0
+    big = _fake_scene()
+    big.n_tris = s.n_tris * 64
+    assert L.dem_sort_contacts_workspace_bytes(C.byref(big), 0) > n0
+    out = _abi.Contacts()
+    assert L.dem_sort_contacts(C.byref(s), None, C.c_void_p(4096), n1, C.c_void_p(4096), None) == _abi.DEM_ERR_ARG
+    out.count = 4096
+    out.capacity = 1 << 20  # buffers missing
+    assert L.dem_sort_contacts(C.byref(s), C.byref(out), C.c_void_p(4096), n1, C.c_void_p(4096),
+                               None) == _abi.DEM_ERR_ARG
+    out.capacity = 0
+    assert L.dem_sort_contacts(C.byref(s), C.byref(out), C.c_void_p(4096), 16, C.c_void_p(4096),
+                               None) == _abi.DEM_ERR_CAPACITY
+    assert L.dem_sort_contacts(C.byref(s), C.byref(out), C.c_void_p(4096), n0, None, None) == _abi.DEM_ERR_ARG
+
+
 def _levels(p):
     sizes = [len(l) for l in p.levels]
     offs = np.cumsum([0] + sizes)
