@@ -100,3 +100,32 @@ def test_third_law_and_angular_momentum_on_spheres():
     for g, root in enumerate(np.unique(merged["labels"])):
         m = x[merged["labels"] == root]
         assert np.all(merged["x"][g] >= m.min(0) - 1e-12) and np.all(merged["x"][g] <= m.max(0) + 1e-12)
+
+
+def test_merge_groups_match_brute_force_single_linkage():
+    """merge_groups (k-d tree pairs + connected components) against a
+    brute-force single linkage written out directly: all pairwise distances,
+    a union-find over the pairs closer than the radius, within one particle
+    pair only; labels are the smallest index of each group."""
+    rng = np.random.default_rng(11)
+    n = 400
+    x = rng.uniform(0, 1, (n, 3)) * np.array([1.0, 1.0, 0.2])
+    pi = rng.integers(0, 3, n)
+    pj = pi + 1 + rng.integers(0, 2, n)
+    radius = np.where(pi == 0, 0.06, 0.09)
+    lab = of.merge_groups(x, pi, pj, radius)
+    parent = list(range(n))
+
+    def find(a):
+        while parent[a] != a:
+            a = parent[a]
+        return a
+    for a in range(n):
+        for b in range(a + 1, n):
+            if pi[a] == pi[b] and pj[a] == pj[b] and np.sqrt(((x[a] - x[b]) ** 2).sum()) < radius[a]:
+                ra, rb = find(a), find(b)
+                if ra != rb:
+                    parent[max(ra, rb)] = min(ra, rb)
+    want = np.array([find(a) for a in range(n)])
+    assert np.array_equal(lab, want)
+    assert len(np.unique(want)) < n  # some points did merge
