@@ -357,6 +357,36 @@ dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32
                              double* dev_energy, dem_stream_t stream);
 
 /*
+ * dem_find_contacts_noalloc -- dem_find_contacts for callers that cannot
+ * allocate device memory: code under HIP graph capture that may not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, kernels and results as dem_find_contacts, except that the
+ * workspace is a library-owned static device array of DEM_SCRATCH_BYTES
+ * (one per GPU, allocated when the library's code object is loaded on that
+ * device and held until the process ends) instead of a caller buffer.  The
+ * call itself allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); the caller still passes pairs, contact buffers and status.
+ *
+ * Returns DEM_ERR_CAPACITY when dem_workspace_bytes(scene, n_pairs, p)
+ * exceeds DEM_SCRATCH_BYTES (lower p->queue_capacity / near_capacity or use
+ * dem_find_contacts), DEM_ERR_HIP when the scratch address of the current
+ * device cannot be looked up (the first call on each device does that
+ * lookup; make it outside graph capture), and the argument errors of
+ * dem_find_contacts.  The current device must be the device of `stream`.
+ *
+ * Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's contents (counters are cleared by the call's first kernel): calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  The triangle soup it leaves is not available to
+ * dem_contact_backward; use dem_find_contacts with a workspace when
+ * gradients are needed.
+ */
+#define DEM_SCRATCH_BYTES (64u << 20)
+dem_status dem_find_contacts_noalloc(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
+                                     const dem_params* p, const dem_contacts* out, dem_stats* dev_stats,
+                                     uint32_t* dev_status, double* dev_energy, dem_stream_t stream);
+
+/*
  * dem_contact_backward -- adjoint of the penalty contact energy
  * E = k * sum over contacts of max(0, delta - d)^2 (delta = eps_i + eps_j).
  *

@@ -24,6 +24,7 @@ DEM_DEV_BAD_TREE = 0x10
 DEM_DEV_FRONTIER_OVERFLOW = 0x20
 DEM_MAX_LEVELS = 32
 DEM_MAX_CHILDREN = 16
+DEM_SCRATCH_BYTES = 64 << 20
 
 # Every exported symbol declared in include/dem.h.
 EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "dem_workspace_bytes",
@@ -31,7 +32,7 @@ EXPORTS = ("dem_build_hierarchy", "dem_hierarchy_free", "dem_default_params", "d
            "dem_default_tree_opts", "dem_build_surrogate_tree", "dem_surrogate_tree_free",
            "dem_frontier_workspace_bytes", "dem_frontier_init", "dem_frontier_step",
            "dem_contact_forces_workspace_bytes", "dem_contact_forces",
-           "dem_sort_contacts_workspace_bytes", "dem_sort_contacts")
+           "dem_sort_contacts_workspace_bytes", "dem_sort_contacts", "dem_find_contacts_noalloc")
 
 
 class BuildOpts(C.Structure):
@@ -144,6 +145,9 @@ def lib():
         L.dem_find_contacts.argtypes = [C.POINTER(Scene), vp, C.c_int32, C.POINTER(Params),
                                         C.POINTER(Contacts), vp, C.c_size_t, vp, vp, vp, vp]
         L.dem_find_contacts.restype = C.c_int
+        L.dem_find_contacts_noalloc.argtypes = [C.POINTER(Scene), vp, C.c_int32, C.POINTER(Params),
+                                                C.POINTER(Contacts), vp, vp, vp, vp]
+        L.dem_find_contacts_noalloc.restype = C.c_int
         L.dem_sort_contacts_workspace_bytes.argtypes = [C.POINTER(Scene), C.c_int64]
         L.dem_sort_contacts_workspace_bytes.restype = C.c_size_t
         L.dem_sort_contacts.argtypes = [C.POINTER(Scene), C.POINTER(Contacts), vp, C.c_size_t, vp, vp]

@@ -24,6 +24,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "dem.h"
 #include "dem_geom.hpp"
@@ -3048,6 +3049,58 @@ dem_status run_sort(const dem_contacts* c, int32_t n_tris, void* ws, const SortL
 
 }  // namespace
 
+// Device scratch of dem_find_contacts_noalloc: the workspace (soup, level
+// queues, near list, counters) of callers that cannot allocate device memory.
+// One copy per GPU, held until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory itself: its device
+// address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and only that address is passed to kernels.
+static __device__ __align__(256) uint8_t scratch[DEM_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on that device).
+dem_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return DEM_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DEM_ERR_HIP;
+    if (reinterpret_cast<uintptr_t>(ptr) % 256) return DEM_ERR_HIP;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return DEM_OK;
+}
+
+// Argument checks shared by dem_find_contacts and its no-allocation variant.
+dem_status find_args_ok(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs, const dem_params& p,
+                        const dem_contacts* out, const uint32_t* dev_status) {
+  if (!scene_ok(scene) || !params_ok(p)) return DEM_ERR_ARG;
+  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return DEM_ERR_ARG;
+  if (!out || !out->count || out->capacity < 0 || out->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
+  if (out->capacity > 0 && (!out->pi || !out->pj || !out->ti || !out->tj || !out->d || !out->x || !out->n))
+    return DEM_ERR_ARG;
+  if (!dev_status) return DEM_ERR_ARG;
+  return DEM_OK;
+}
+
+dem_status find_dispatch(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs, const dem_params& p,
+                         const dem_contacts* out, void* ws, const WsLayout& L, dem_stats* dev_stats,
+                         uint32_t* dev_status, double* dev_energy, hipStream_t st) {
+  if (scene->precision == DEM_F64)
+    return run_find<double>(scene, pairs, n_pairs, p, out, ws, L, dev_stats, dev_status, dev_energy, st);
+  return run_find<float>(scene, pairs, n_pairs, p, out, ws, L, dev_stats, dev_status, dev_energy, st);
+}
+
+}  // namespace
+
 extern "C" {
 
 void dem_default_params(dem_params* p) {
@@ -3085,21 +3138,30 @@ dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32
                              double* dev_energy, dem_stream_t stream) {
   dem_params p;
   if (pp) p = *pp; else dem_default_params(&p);
-  if (!scene_ok(scene) || !params_ok(p)) return DEM_ERR_ARG;
-  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return DEM_ERR_ARG;
-  if (!out || !out->count || out->capacity < 0 || out->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
-  if (out->capacity > 0 && (!out->pi || !out->pj || !out->ti || !out->tj || !out->d || !out->x || !out->n))
-    return DEM_ERR_ARG;
-  if (!workspace || !dev_status) return DEM_ERR_ARG;
+  const dem_status a = find_args_ok(scene, pairs, n_pairs, p, out, dev_status);
+  if (a != DEM_OK) return a;
+  if (!workspace) return DEM_ERR_ARG;
   WsLayout L = ws_layout(scene->precision, scene->n_tris, p.queue_capacity, p.near_capacity);
   if (workspace_bytes < L.total) return DEM_ERR_CAPACITY;
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (scene->precision == DEM_F64)
-    return run_find<double>(scene, pairs, n_pairs, p, out, workspace, L, dev_stats, dev_status,
-                            dev_energy, st);
-  return run_find<float>(scene, pairs, n_pairs, p, out, workspace, L, dev_stats, dev_status,
-                         dev_energy, st);
+  return find_dispatch(scene, pairs, n_pairs, p, out, workspace, L, dev_stats, dev_status, dev_energy,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+dem_status dem_find_contacts_noalloc(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
+                                     const dem_params* pp, const dem_contacts* out, dem_stats* dev_stats,
+                                     uint32_t* dev_status, double* dev_energy, dem_stream_t stream) {
+  dem_params p;
+  if (pp) p = *pp; else dem_default_params(&p);
+  const dem_status a = find_args_ok(scene, pairs, n_pairs, p, out, dev_status);
+  if (a != DEM_OK) return a;
+  WsLayout L = ws_layout(scene->precision, scene->n_tris, p.queue_capacity, p.near_capacity);
+  if (L.total > (size_t)DEM_SCRATCH_BYTES) return DEM_ERR_CAPACITY;
+  void* ws = nullptr;
+  const dem_status sa = scratch_address(&ws);
+  if (sa != DEM_OK) return sa;
+  return find_dispatch(scene, pairs, n_pairs, p, out, ws, L, dev_stats, dev_status, dev_energy,
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* c, double k,

@@ -116,6 +116,26 @@ def test_workspace_bytes_and_validation():
     assert st == _abi.DEM_ERR_ARG
 
 
+def test_find_contacts_noalloc_validation():
+    """dem_find_contacts_noalloc rejects bad arguments and workspaces beyond
+    its static scratch before any device call."""
+    L = _abi.lib()
+    s = _fake_scene()
+    p = _abi.default_params()
+    out = _abi.Contacts()
+    assert L.dem_find_contacts_noalloc(C.byref(s), None, 1, C.byref(p), C.byref(out), None, None, None,
+                                       None) == _abi.DEM_ERR_ARG
+    out.count = 4096
+    out.capacity = 0
+    # default capacities need 2 x 64 MiB of queues alone
+    assert L.dem_workspace_bytes(C.byref(s), 1, C.byref(p)) > _abi.DEM_SCRATCH_BYTES
+    assert L.dem_find_contacts_noalloc(C.byref(s), C.c_void_p(4096), 1, C.byref(p), C.byref(out), None,
+                                       C.c_void_p(4096), None, None) == _abi.DEM_ERR_CAPACITY
+    p.block = 100
+    assert L.dem_find_contacts_noalloc(C.byref(s), C.c_void_p(4096), 1, C.byref(p), C.byref(out), None,
+                                       C.c_void_p(4096), None, None) == _abi.DEM_ERR_ARG
+
+
 def test_sort_contacts_sizing_and_validation():
     """dem_sort_contacts: workspace grows with the triangle count and the
     capacity; bad arguments are rejected before any device work."""
