@@ -99,9 +99,21 @@ class Step:
         poses = np.concatenate([Rs.reshape(len(Rs), P, 9), shift], axis=2)
         self.poses = torch.as_tensor(poses, device=ds.device, dtype=ds.dtype).contiguous()
         self.grad = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device=ds.device)
+        # a device status word per step, so that a flag raised by any step of
+        # a replayed graph is seen (each call clears the word it writes)
+        self.status_words = torch.zeros(len(self.poses), dtype=torch.int32, device=ds.device)
 
     def pose(self, k: int):
         self.ds.set_pose(self.poses[k % len(self.poses)])
+        self.eng.status = self.status_words[k % len(self.poses):k % len(self.poses) + 1]
+
+    def check_all(self, what: str):
+        torch = sys.modules["torch"]
+        torch.cuda.synchronize()
+        w = self.status_words.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+        bad = np.nonzero(w)[0]
+        if len(bad):
+            raise RuntimeError(f"device status {int(w[bad[0]]):#x} at step {int(bad[0])} {what}")
 
     def __call__(self, k: int):
         self.pose(k)
@@ -156,6 +168,9 @@ def frontier_kernel_times(torch, step: FrontierStep, K: int):
             eng.backward(step.grad)
             b1.record()
             torch.cuda.synchronize()
+            status = eng.check()
+            if status:
+                raise RuntimeError(f"device status {status:#x} in eager frontier step {k}")
             for i in range(len(names)):
                 acc[i] += evs[i].elapsed_time(evs[i + 1])
             bwd += b0.elapsed_time(b1)
@@ -228,6 +243,9 @@ def kernel_times(torch, step: Step, K: int):
                 eng.backward(step.grad)
                 b1.record()
             torch.cuda.synchronize()
+            status = eng.check()
+            if status:
+                raise RuntimeError(f"device status {status:#x} in eager step {k}")
             for i in range(n_launch):
                 acc[i] += evs[i].elapsed_time(evs[i + 1])
             if step.backward:
@@ -284,10 +302,9 @@ def run_mode(torch, api, ds, mode, backward, K, warmup, params_kw, contact_capac
         eng.p.half_depths = half_depths
         step.pose(0)
         eng.run()
+    step.status_words.zero_()
     ms_graph, ms_wall, graph = time_graph(torch, step, K, warmup)
-    status = eng.check()
-    if status:
-        raise RuntimeError(f"device status {status:#x} after graph replay")
+    step.check_all("after graph replay")
     kt, bwd_ms, st = kernel_times(torch, step, K)
     del graph
     return eng, step, ms_graph, ms_wall, kt, bwd_ms, st
@@ -369,10 +386,9 @@ def run_frontier_bench(torch, api, ds, args, params_kw, desc, log):
         status = eng.check()
         if status:
             raise RuntimeError(f"device status {status:#x} in eager frontier step {k}")
+    step.status_words.zero_()
     ms, ms_wall, graph = time_graph(torch, step, K, args.warmup)
-    status = eng.check()
-    if status:
-        raise RuntimeError(f"device status {status:#x} after graph replay")
+    step.check_all("after graph replay")
     del graph
     kt, bwd_ms, st = frontier_kernel_times(torch, step, K)
     evals = float(st["frontier_leaves"])
@@ -449,9 +465,12 @@ def run_forces_bench(torch, api, ds, scene, args, params_kw, desc, log):
         fstep(k)
         if eng.check() or fe.check():
             raise RuntimeError(f"device status {eng.check():#x} / {fe.check():#x} in eager step {k}")
+    step.status_words.zero_()
     ms_fwd, _, g0 = time_graph(torch, step, K, args.warmup)
+    step.check_all("after graph replay (contacts)")
     del g0
     ms, ms_wall, g1 = time_graph(torch, fstep, K, args.warmup)
+    step.check_all("after graph replay (contacts + forces)")
     del g1
     if fe.check():
         raise RuntimeError(f"device status {fe.check():#x} after graph replay")

@@ -347,8 +347,14 @@ size_t dem_workspace_bytes(const dem_scene* scene, int32_t n_pairs, const dem_pa
  * out        contact buffers (host struct of device pointers).
  * workspace  device, >= dem_workspace_bytes(scene, n_pairs, p) bytes.
  * dev_stats  device dem_stats or NULL.
- * dev_status device uint32: cleared, then DEM_DEV_* bits.
- * dev_energy device double or NULL: receives k * sum max(0, delta - d)^2.
+ * dev_status device uint32: cleared, then DEM_DEV_* bits.  Every input
+ *            vertex is checked: a non-finite coordinate sets
+ *            DEM_DEV_NONFINITE (the contacts of such a call are meaningless,
+ *            but the call completes).
+ * dev_energy device double or NULL: receives k * sum max(0, delta - d)^2
+ *            over every contact found, including contacts beyond
+ *            out->capacity (DEM_DEV_CONTACT_OVERFLOW): rerun with a larger
+ *            capacity before differentiating.
  * stream     hipStream_t to enqueue on.
  */
 dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
@@ -398,7 +404,12 @@ dem_status dem_find_contacts_noalloc(const dem_scene* scene, const int32_t* pair
  * over the two triangles).  Intersecting pairs (d = 0) add energy but no
  * gradient.
  *
- * contacts   the output of dem_find_contacts (device count is read on device).
+ * contacts   the output of the immediately preceding dem_find_contacts (or
+ *            dem_frontier_step) on this workspace (device count is read on
+ *            device).  A contact naming a triangle outside the scene is
+ *            skipped and sets DEM_DEV_BAD_TREE; a contact list from another
+ *            call reads soup records that may not have been written there
+ *            and gives a meaningless gradient.
  * grad_E     device double scalar multiplying the gradient, or NULL for 1.
  * grad_verts device [3][n_verts] with respect to world positions,
  *            ACCUMULATED into (caller zeroes it); NULL for energy only.

@@ -339,6 +339,7 @@ class ContactEngine:
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.energy = torch.zeros(1, dtype=torch.float64, device=dev)
         self.energy_bwd = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.generation = 0  # forward() calls so far: the soup and contacts belong to the last one
         self._alloc_ws()
 
     def _alloc_ws(self):
@@ -354,6 +355,7 @@ class ContactEngine:
         return C.c_void_p(torch.cuda.current_stream(self.ds.device).cuda_stream)
 
     def forward(self, with_energy: bool = True):
+        self.generation += 1
         cs = self.contacts.c()
         st = lib().dem_find_contacts(C.byref(self.ds.c), _ptr(self.ds.pairs), self.ds.n_pairs,
                                      C.byref(self.p), C.byref(cs), C.c_void_p(self.ws_ptr),
@@ -706,13 +708,20 @@ class DemContactEnergy(torch.autograd.Function):
     def forward(ctx, verts: torch.Tensor, engine: ContactEngine):
         if verts.data_ptr() != engine.ds.verts.data_ptr():
             engine.ds.set_verts(verts.detach().contiguous())
-        engine.forward(with_energy=True)
+        # run(): synchronises, grows the buffers and repeats the call on any
+        # overflow, and raises on non-finite input, so that the energy and
+        # the contact list the backward differentiates are complete
+        engine.run(with_energy=True)
         ctx.engine = engine
+        ctx.generation = engine.generation
         return engine.energy[0].to(verts.dtype).clone()
 
     @staticmethod
     def backward(ctx, grad_E: torch.Tensor):
         eng = ctx.engine
+        if eng.generation != ctx.generation:
+            raise DemError("the engine ran another forward since this energy was computed; its contacts and "
+                           "soup now belong to that call (use one engine per pending backward)")
         g = torch.zeros(3, eng.ds.n_verts, dtype=eng.ds.dtype, device=eng.ds.device)
         gE = grad_E.detach().to(torch.float64).reshape(1).contiguous()
         eng.backward(g, gE)

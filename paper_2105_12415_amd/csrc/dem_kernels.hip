@@ -271,6 +271,12 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten(FlatArgs<T> a) {
   __shared__ SoupRec<T> stage[kFlatBlock];
   __shared__ uint8_t act[kFlatBlock];
   const int t = blockIdx.x * kFlatBlock + threadIdx.x;
+  // every input vertex is checked once per step, also the vertices of fine
+  // triangles below pruned surrogates that no record reads this step
+  for (int v = t; v < a.n_verts; v += gridDim.x * kFlatBlock) {
+    const T vx = a.verts[v], vy = a.verts[a.n_verts + v], vz = a.verts[2 * (size_t)a.n_verts + v];
+    if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) atomicOr(a.status, DEM_DEV_NONFINITE);
+  }
   bool on = t < a.n_tris;
   if (on) {
     const int cc = a.ccnt[t];
@@ -994,6 +1000,10 @@ __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__
       const uint32_t c = cb + j;
       if (c >= cnt) break;
       const int ti = cti[c], tj = ctj[c];
+      if ((uint32_t)ti >= (uint32_t)n_tris || (uint32_t)tj >= (uint32_t)n_tris) {
+        atomicOr(status, DEM_DEV_BAD_TREE);  // not a triangle of this scene: skipped
+        continue;
+      }
       int cbi, cci, pi_, cbj, ccj, pj_;
       Tri<T> A = load_tri(soup, ti, cbi, cci, pi_);
       Tri<T> B = load_tri(soup, tj, cbj, ccj, pj_);
