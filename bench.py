@@ -38,15 +38,17 @@ PEAK_HBM_GBS = 8000.0
 def flops_per_eval(n_iter: int) -> int:
     """Algorithmic floating-point operations of one iterate-and-bound
     evaluation, counted from its formulas (FMA = 2; add, mul, min, max,
-    compare, reciprocal, rsqrt = 1; sign changes and selects = 0): 80 per
+    compare, rsqrt = 1; sign changes, absolute values and selects = 0): 74 per
     Newton iteration (residual 24, gradient 20, diagonal step 8, two penalty
-    half-steps 28; the first step starts at (a, b) = 0 where the residual is
-    the vertex difference itself, 24 fewer) plus 93 for the pair set-up, the
-    projection of both iterates onto their triangles, the search direction,
-    the two support functions, the rounding slack and the threshold test."""
+    half-steps 22; the first starts at (a, b) = 0 where the residual is the
+    vertex difference itself, 24 fewer), plus 3 for the vertex difference, 8
+    for clamping the four parameters, 63 for the bound along the direction
+    between the two points (residual 24, its length 5, five dot products 25,
+    the two support functions 4, combination and normalisation 5) and 10 for
+    the rounding slack, the threshold and the test."""
     if n_iter == 0:
-        return 93
-    return 80 * n_iter - 24 + 93
+        return 84
+    return 74 * n_iter - 24 + 84
 
 
 FLATTEN_BYTES_PER_TRI = 12 + 16 + 64  # indices, per-triangle static data, soup record
@@ -70,6 +72,60 @@ WORKLOADS = {
                          "gaps U(0,0.1), full icosphere cascades, FP32; persistent active sets "
                          "(dem_frontier_step, one level of widening / narrowing per step)", True),
 }
+
+
+def measure_peaks(torch, log=print) -> dict:
+    """Achievable peaks of this GPU from the project's microbenchmarks
+    (libpeak.so): FP32 and FP64 VALU loops over every SIMD (16 independent
+    chains per lane, 8 waves per SIMD) -- FMA with a uniform (SGPR) operand,
+    FMA with three VGPR operands (accumulating form), and FP32 add, multiply
+    and max -- and a 1 GiB device-to-device copy.  For each FP32 kind: the
+    issue cycles of one wave64 instruction on a SIMD at the published
+    2.4 GHz clock."""
+    lib = C.CDLL(os.path.join(ROOT, "paper_2105_12415_amd", "libpeak.so"))
+    lib.peak_fma.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    lib.peak_fma_per_lane.argtypes = [C.c_int]
+    lib.peak_fma_per_lane.restype = C.c_longlong
+    lib.peak_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    blocks = 256 * 8  # 256 CUs x 8 blocks of 4 waves = 8 waves per SIMD
+
+    def timed(fn, reps):
+        best = None
+        for rep in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rc = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if rc:
+                raise RuntimeError(f"microbenchmark launch failed ({rc})")
+            ms = e0.elapsed_time(e1)
+            if rep > 0 and (best is None or ms < best):
+                best = ms
+        return best
+
+    out = {}
+    kinds = (("fp32_fma", 0, 0, 2), ("fp32_fmac", 0, 1, 2), ("fp32_add", 0, 2, 1), ("fp32_mul", 0, 3, 1),
+             ("fp32_max", 0, 4, 1), ("fp64_fma", 1, 0, 2), ("fp64_fmac", 1, 1, 2))
+    for name, fp64, kind, flop in kinds:
+        iters = 10000 if fp64 else 20000
+        buf = torch.empty(blocks * 256, dtype=torch.float64 if fp64 else torch.float32, device="cuda")
+        ms = timed(lambda: lib.peak_fma(fp64, kind, blocks, iters, C.c_void_p(buf.data_ptr()), stream), 4)
+        ops = blocks * 256 * lib.peak_fma_per_lane(iters)
+        out[f"{name}_tflops"] = flop * ops / (ms * 1e-3) / 1e12
+        out[f"{name}_cycles_per_wave64"] = ms * 1e-3 * 2.4e9 * 1024 / (blocks * 4 * lib.peak_fma_per_lane(iters))
+    out["fp32_fma_peak_tflops"] = max(out["fp32_fma_tflops"], out["fp32_fmac_tflops"])
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    ms = timed(lambda: lib.peak_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), n, 256 * 16, stream), 5)
+    out["copy_gbs"] = 2.0 * n / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log("[bench] peaks: " + ", ".join(f"{k} {v:.2f}" for k, v in out.items()))
+    return out
 
 
 def workload(name: str):

@@ -16,6 +16,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdem.so")
 SOURCES = ["dem_kernels.hip", "dem_hierarchy.cpp", "dem_surrogate.cpp"]
+# achievable-peak microbenchmarks (FMA loop, device copy) used by bench.py
+PEAK_LIB = os.path.join(HERE, "libpeak.so")
+PEAK_SOURCES = ["peak_probe.hip"]
 ARCH = os.environ.get("DEM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -53,5 +56,12 @@ def build(verbose: bool = False, lib_path: str = LIB, extra_flags=(), sources=No
     return lib_path
 
 
+def build_all(verbose: bool = False):
+    """libdem.so and libpeak.so."""
+    build(verbose)
+    build(verbose, lib_path=PEAK_LIB, sources=[os.path.join(CSRC, s) for s in PEAK_SOURCES])
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    build_all(verbose="-v" in sys.argv)
+    print(LIB, PEAK_LIB)

@@ -124,10 +124,10 @@ DEM_HD float rsq_fast(float x) {
 }
 DEM_HD double rsq_fast(double x) { return 1.0 / sqrt(x); }
 
-// A triangle in "soup" form: first vertex, two edge vectors, epsilon,
-// diagonal of the regularised Hessian block (inverted) for its two
-// barycentric parameters, and a size bound (max|e1| + max|e2| over
-// components) for the rounding slack.
+// A triangle in "soup" form: first vertex, two edge vectors, epsilon, the
+// negated damped Newton step lengths of its two barycentric parameters (ia,
+// ib; see newton_steps), and a size bound (max|e1| + max|e2| over components)
+// for the rounding slack.
 template <typename T>
 struct Tri {
   V3<T> v0, e1, e2;
@@ -137,102 +137,127 @@ struct Tri {
 // ------------------------------------------------------------------ iteration
 struct IterParams {
   int n_iter;
-  float omega;
-  float kappa1, kappa2;  // penalty half-step gains for 1 and 2 active constraints
+  float nkappa;          // negated penalty half-step gain -alpha_it / (alpha_it + alpha_reg)
   int init_centroid;
 };
 
-// One half-step on the penalty part of J for the parameters (a, b) of one
-// triangle: quadratic exterior penalty alpha_it/2 * sum max(0, g)^2 over
-// g in {-a, -b, a+b-1} (reading of the constraint terms), Hessian diagonal
-// alpha_it * (#active constraints on the coordinate), regularised by
-// alpha_reg.  With kappa_m = alpha_it / (m alpha_it + alpha_reg) the step is
-// a scaled projection back onto the triangle.
+DEM_HD float mn3_(float a, float b, float c) { return fminf(a, fminf(b, c)); }
+DEM_HD double mn3_(double a, double b, double c) { return fmin(a, fmin(b, c)); }
+DEM_HD _Float16 mn3_(_Float16 a, _Float16 b, _Float16 c) { return mn_(a, mn_(b, c)); }
+DEM_HD float mx3_(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
+DEM_HD double mx3_(double a, double b, double c) { return fmax(a, fmax(b, c)); }
+DEM_HD _Float16 mx3_(_Float16 a, _Float16 b, _Float16 c) { return mx_(a, mx_(b, c)); }
+
+// Stored step lengths of a triangle's two barycentric parameters in the
+// damped diagonal-Newton update of the distance term (Section 3: Newton step
+// with the diagonal of the Hessian, regularised by alpha_reg), negated so
+// that every update of the iteration is an accumulating fused multiply-add:
+//     x <- x + d_x (r . e_x),   d_x = -omega / (|e_x|^2 + alpha_reg),
+// with alpha_reg = alpha_reg_rel (|e1|^2 + |e2|^2) / 2.  A parameter whose
+// curvature is zero (an edge of zero length, no regularisation) keeps its
+// value: step 0.
 template <typename T>
-DEM_HD void penalty_half_step(T& a, T& b, T k1, T k2) {
-  T ca = mx_(-a, T(0));
-  T cb = mx_(-b, T(0));
-  T cs = mx_(a + b - T(1), T(0));
-  bool sa = cs > T(0);
-  T ka = (ca > T(0) && sa) ? k2 : k1;
-  T kb = (cb > T(0) && sa) ? k2 : k1;
-  a += ka * (ca - cs);
-  b += kb * (cb - cs);
+DEM_HD void newton_steps(V3<T> e1, V3<T> e2, T areg_rel, T omega, T& d1, T& d2) {
+  const T n1 = dot(e1, e1), n2 = dot(e2, e2);
+  const T areg = areg_rel * T(0.5) * (n1 + n2);
+  d1 = n1 + areg > T(0) ? -omega / (n1 + areg) : T(0);
+  d2 = n2 + areg > T(0) ? -omega / (n2 + areg) : T(0);
 }
 
-// Point of the triangle for parameters (a, b) pulled into a, b >= 0 and
-// rescaled onto a + b <= 1 (it only fixes the search direction).
+// Half-step on the penalty part of J for one triangle's parameters: the
+// quadratic exterior penalty alpha_it/2 sum max(0, g)^2 over the constraints
+// g in {-a, -b, a + b - 1}, one Newton step with the curvature of one active
+// constraint, alpha_it + alpha_reg, per coordinate (nk = -alpha_it /
+// (alpha_it + alpha_reg)):
+//     a <- a + nk (min(a, 0) + max(a + b - 1, 0)),  b likewise.
+// Triangle B's parameters are kept negated, (c, d) = (-a2, -b2), so its
+// constraints read c <= 0, d <= 0, c + d >= -1:
+//     c <- c + nk (max(c, 0) + min(c + d + 1, 0)),  d likewise.
 template <typename T>
-DEM_HD void to_simplex(T& a, T& b) {
-  a = mx_(a, T(0));
-  b = mx_(b, T(0));
-  T inv = rcp_fast(mx_(a + b, T(1)));
-  a *= inv;
-  b *= inv;
+DEM_HD void penalty_pos(T& a, T& b, T nk) {
+  const T cs = mx_(a + b - T(1), T(0));
+  const T ta = mn_(a, T(0)) + cs;
+  const T tb = mn_(b, T(0)) + cs;
+  a = fm_(nk, ta, a);
+  b = fm_(nk, tb, b);
+}
+template <typename T>
+DEM_HD void penalty_neg(T& c, T& d, T nk) {
+  const T cs = mn_(c + d + T(1), T(0));
+  const T tc = mx_(c, T(0)) + cs;
+  const T td = mx_(d, T(0)) + cs;
+  c = fm_(nk, tc, c);
+  d = fm_(nk, td, d);
 }
 
-// N modified-Newton iterations on J (Section 3: diagonal Newton step on the
-// distance term, then a half-step on the constraint penalties; N fixed as
-// in Algorithm 4) for triangles A, B in pair-local coordinates (A.v0 at the
-// origin, B's first vertex at -D0).  Leaves the parameters projected into
-// the two triangles.
+// N modified-Newton iterations on J (Section 3: a diagonal Newton step on the
+// distance term, then a half-step on the constraint penalties; N fixed as in
+// Algorithm 4) for triangles A, B in pair-local coordinates (A.v0 at the
+// origin, B's first vertex at -D0).  Returns A's parameters (a1, b1) and B's
+// negated, (c2, d2) = (-a2, -b2); the residual between the two points is
+//     m = p_A - p_B = D0 + a1 e1A + b1 e2A + c2 e1B + d2 e2B.
 template <typename T, int N>
 DEM_HD void iterate_theta(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip, T& a1,
-                          T& b1, T& a2, T& b2) {
-  const T om = T(ip.omega), k1 = T(ip.kappa1), k2 = T(ip.kappa2);
-  // damped inverse diagonal of the regularised Hessian, per parameter
-  const T s1 = om * A.ia, s2 = om * A.ib, s3 = om * B.ia, s4 = om * B.ib;
-  V3<T> r;  // residual t_A(a1,b1) - t_B(a2,b2)
+                          T& b1, T& c2, T& d2) {
+  const T nk = T(ip.nkappa);
+  V3<T> r;
   if (ip.init_centroid) {
-    a1 = b1 = a2 = b2 = T(1) / T(3);
-    r = fma3(a1, A.e1 + A.e2, fma3(-a2, B.e1 + B.e2, D0));
+    a1 = b1 = T(1) / T(3);
+    c2 = d2 = -(T(1) / T(3));
+    r = fma3(c2, B.e1 + B.e2, fma3(a1, A.e1 + A.e2, D0));
   } else {
-    a1 = b1 = a2 = b2 = T(0);
+    a1 = b1 = c2 = d2 = T(0);
     r = D0;
   }
 #pragma unroll
   for (int it = 0; it < N; ++it) {
-    if (it > 0) r = fma3(a1, A.e1, fma3(b1, A.e2, fma3(-a2, B.e1, fma3(-b2, B.e2, D0))));
-    // gradient of 1/2 |r|^2 and the diagonal Newton step
-    a1 -= s1 * dot(r, A.e1);
-    b1 -= s2 * dot(r, A.e2);
-    a2 += s3 * dot(r, B.e1);
-    b2 += s4 * dot(r, B.e2);
+    if (it > 0) r = fma3(d2, B.e2, fma3(c2, B.e1, fma3(b1, A.e2, fma3(a1, A.e1, D0))));
+    // gradient of 1/2 |r|^2 and the diagonal Newton step (A.ia ... B.ib hold
+    // the negated step lengths)
+    a1 = fm_(A.ia, dot(r, A.e1), a1);
+    b1 = fm_(A.ib, dot(r, A.e2), b1);
+    c2 = fm_(B.ia, dot(r, B.e1), c2);
+    d2 = fm_(B.ib, dot(r, B.e2), d2);
     // constraint half-step
-    penalty_half_step(a1, b1, k1, k2);
-    penalty_half_step(a2, b2, k1, k2);
+    penalty_pos(a1, b1, nk);
+    penalty_neg(c2, d2, nk);
   }
-  to_simplex(a1, b1);
-  to_simplex(a2, b2);
 }
 
-// The iteration followed by the lower bound on the distance along the unit
-// direction u between the two iterate points:
-//     d(A, B) >= min_k u.b_k - max_k u.a_k.
-// Returns the bound (-inf if the two points coincide: nothing is pruned).
-// Lower bound along the unit direction between the points of parameters
-// (a1, b1) on A and (a2, b2) on B.
+// Lower bound on d(A, B) along the direction u = (p_B - p_A)/|p_B - p_A|
+// between the iterate's points: any unit u gives
+//     d(A, B) >= min_k u.w_k - max_k u.v_k
+// (support of B minus support of A), which with m = p_A - p_B = -|m| u and
+// A.v0 at the origin is
+//     (m.D0 + min(0, m.e1A, m.e2A) - max(0, m.e1B, m.e2B)) / |m|.
+// For m = 0 every product is 0 and so is the bound (nothing is pruned).
 template <typename T>
-DEM_HD T bound_along(const Tri<T>& A, const Tri<T>& B, V3<T> D0, T a1, T b1, T a2, T b2) {
-  // w = p2 - p1 between the two (feasible) iterate points
-  V3<T> w = fma3(a2, B.e1, fma3(b2, B.e2, fma3(-a1, A.e1, fma3(-b1, A.e2, -D0))));
-  T ww = dot(w, w);
-  V3<T> u = rsq_fast(mx_(ww, T(1e-30))) * w;
-  // support of A along u (max) and of B along u (min)
-  T hA = mx_(T(0), mx_(dot(u, A.e1), dot(u, A.e2)));
-  T hB = mn_(T(0), mn_(dot(u, B.e1), dot(u, B.e2))) - dot(u, D0);
-  return ww > T(0) ? hB - hA : -T(INFINITY);
+DEM_HD T bound_along(const Tri<T>& A, const Tri<T>& B, V3<T> D0, T a1, T b1, T c2, T d2) {
+  const V3<T> m = fma3(d2, B.e2, fma3(c2, B.e1, fma3(b1, A.e2, fma3(a1, A.e1, D0))));
+  const T mm = dot(m, m);
+  const T lo_a = mn3_(T(0), dot(m, A.e1), dot(m, A.e2));
+  const T hi_b = mx3_(T(0), dot(m, B.e1), dot(m, B.e2));
+  return (dot(m, D0) + lo_a - hi_b) * rsq_fast(mx_(mm, T(1e-30)));
 }
 
+// The iteration followed by the bound.  The final parameters are clamped to
+// [0, 1] each (B's to [-1, 0]): the points then lie in the parallelograms
+// spanned by the triangles' edges, which keeps the direction between them
+// informative when the undamped Jacobi step has overshot (the bound itself
+// holds for any direction).
 template <typename T, int N>
 DEM_HD T iterate_bound(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip) {
-  T a1, b1, a2, b2;
-  iterate_theta<T, N>(A, B, D0, ip, a1, b1, a2, b2);
-  return bound_along(A, B, D0, a1, b1, a2, b2);
+  T a1, b1, c2, d2;
+  iterate_theta<T, N>(A, B, D0, ip, a1, b1, c2, d2);
+  a1 = mn_(mx_(a1, T(0)), T(1));
+  b1 = mn_(mx_(b1, T(0)), T(1));
+  c2 = mx_(mn_(c2, T(0)), T(-1));
+  d2 = mx_(mn_(d2, T(0)), T(-1));
+  return bound_along(A, B, D0, a1, b1, c2, d2);
 }
 
 // Reduced-precision variant for FP32 scenes: the Newton iteration runs in
-// half precision on the pair-local edges, offsets and Hessian diagonals; the
+// half precision on the pair-local edges, offsets and step lengths; the
 // bound along the resulting direction is formed in FP32.  The bound holds for
 // any direction, so the half-precision rounding only changes how much is
 // pruned, and the FP32 rounding slack (bound_slack) still covers the bound.
@@ -242,11 +267,13 @@ DEM_HD float iterate_bound_mixed(const Tri<float>& A, const Tri<float>& B, V3<fl
   Tri<_Float16> Ah, Bh;
   Ah.e1 = h3(A.e1); Ah.e2 = h3(A.e2); Ah.ia = (_Float16)A.ia; Ah.ib = (_Float16)A.ib;
   Bh.e1 = h3(B.e1); Bh.e2 = h3(B.e2); Bh.ia = (_Float16)B.ia; Bh.ib = (_Float16)B.ib;
-  _Float16 a1, b1, a2, b2;
-  iterate_theta<_Float16, N>(Ah, Bh, h3(D0), ip, a1, b1, a2, b2);
-  // back in FP32: a non-finite parameter becomes a vertex (still a valid direction)
-  auto f = [](_Float16 v) { float x = (float)v; return (x >= 0.0f && x <= 1.0f) ? x : 0.0f; };
-  return bound_along(A, B, D0, f(a1), f(b1), f(a2), f(b2));
+  _Float16 a1, b1, c2, d2;
+  iterate_theta<_Float16, N>(Ah, Bh, h3(D0), ip, a1, b1, c2, d2);
+  // back in FP32, clamped as in iterate_bound; a non-finite parameter
+  // becomes 0 (a vertex; still a valid direction)
+  auto fa = [](_Float16 v) { float x = (float)v; return x > 0.0f ? fminf(x, 1.0f) : 0.0f; };
+  auto fb = [](_Float16 v) { float x = (float)v; return x < 0.0f ? fmaxf(x, -1.0f) : 0.0f; };
+  return bound_along(A, B, D0, fa(a1), fa(b1), fb(c2), fb(d2));
 }
 
 // Rounding slack of the bound above: the computed bound of a pair at true
@@ -514,8 +541,8 @@ DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T
 template <typename T, int N>
 DEM_HD bool certify_pair(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip, T rel_tol,
                          T abs_tol, T& d, V3<T>& p, V3<T>& q, T wp[3], T wq[3]) {
-  T a1, b1, a2, b2;
-  iterate_theta<T, N>(A, B, D0, ip, a1, b1, a2, b2);
+  T a1, b1, nb1, nb2;  // B's negated parameters are not needed here
+  iterate_theta<T, N>(A, B, D0, ip, a1, b1, nb1, nb2);
   const V3<T> z = {T(0), T(0), T(0)};
   const V3<T> b0 = -D0;
   V3<T> p1 = fma3(a1, A.e1, b1 * A.e2);

@@ -204,6 +204,7 @@ struct FlatArgs {
   const T* teps;
   const T* pose;
   T areg_rel;
+  T omega;
   const int32_t* root_begin;
   const int32_t* root_count;
   const int32_t* fine_begin;
@@ -234,9 +235,8 @@ __device__ __forceinline__ SoupRec<T> flatten_rec(const FlatArgs<T>& a, int t, i
     e1 = V3<T>{dot(r0, e1), dot(r1, e1), dot(r2, e1)};
     e2 = V3<T>{dot(r0, e2), dot(r1, e2), dot(r2, e2)};
   }
-  T n1 = dot(e1, e1), n2 = dot(e2, e2);
-  T areg = a.areg_rel * T(0.5) * (n1 + n2);
-  T ia = T(1) / (n1 + areg), ib = T(1) / (n2 + areg);
+  T ia, ib;
+  newton_steps(e1, e2, a.areg_rel, a.omega, ia, ib);
   SoupRec<T> r;
   r.g[0] = v0.x; r.g[1] = v0.y; r.g[2] = v0.z; r.g[3] = a.teps[t];
   r.g[4] = e1.x; r.g[5] = e1.y; r.g[6] = e1.z; r.g[7] = ia;
@@ -2268,10 +2268,8 @@ __global__ void k_cf_reset(uint32_t* ocount) {
 IterParams make_iter(const dem_params& p) {
   IterParams ip;
   ip.n_iter = p.n_iter;
-  ip.omega = p.omega;
   double rho = p.alpha_it_ratio;
-  ip.kappa1 = (float)(rho / (rho + 1.0));
-  ip.kappa2 = (float)(rho / (2.0 * rho + 1.0));
+  ip.nkappa = (float)(-rho / (rho + 1.0));
   ip.init_centroid = p.init_centroid;
   return ip;
 }
@@ -2395,6 +2393,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   fa.teps = static_cast<const T*>(s->tri_eps);
   fa.pose = static_cast<const T*>(s->pose);
   fa.areg_rel = T(p.alpha_reg_rel);
+  fa.omega = T(p.omega);
   fa.root_begin = s->root_begin;
   fa.root_count = s->root_count;
   fa.fine_begin = s->fine_begin;
@@ -2550,6 +2549,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   fl.teps = static_cast<const T*>(s->tri_eps);
   fl.pose = static_cast<const T*>(s->pose);
   fl.areg_rel = T(p.alpha_reg_rel);
+  fl.omega = T(p.omega);
   fl.root_begin = s->root_begin;
   fl.root_count = s->root_count;
   fl.fine_begin = s->fine_begin;

@@ -28,19 +28,13 @@ static void bound_one(const double* P, const float* prm, double* out) {
   B.v0 = b0; B.e1 = b1 - b0; B.e2 = b2 - b0; B.eps = 0;
   A.size = tri_size(A.e1, A.e2);
   B.size = tri_size(B.e1, B.e2);
-  T areg = (T)prm[2];
-  T n1 = dot(A.e1, A.e1), n2 = dot(A.e2, A.e2);
-  T r = areg * T(0.5) * (n1 + n2);
-  A.ia = T(1) / (n1 + r); A.ib = T(1) / (n2 + r);
-  n1 = dot(B.e1, B.e1); n2 = dot(B.e2, B.e2);
-  r = areg * T(0.5) * (n1 + n2);
-  B.ia = T(1) / (n1 + r); B.ib = T(1) / (n2 + r);
+  const T areg = (T)prm[2], omega = (T)prm[1];
+  newton_steps(A.e1, A.e2, areg, omega, A.ia, A.ib);
+  newton_steps(B.e1, B.e2, areg, omega, B.ia, B.ib);
   IterParams ip;
   ip.n_iter = (int)prm[0];
-  ip.omega = prm[1];
   double rho = prm[3];
-  ip.kappa1 = (float)(rho / (rho + 1.0));
-  ip.kappa2 = (float)(rho / (2.0 * rho + 1.0));
+  ip.nkappa = (float)(-rho / (rho + 1.0));
   ip.init_centroid = (int)prm[4];
   V3<T> D0 = A.v0 - B.v0;
   T L;
@@ -94,19 +88,13 @@ static void certify_one(const double* P, const float* prm, double* out) {
   B.v0 = b0; B.e1 = b1 - b0; B.e2 = b2 - b0; B.eps = 0;
   A.size = tri_size(A.e1, A.e2);
   B.size = tri_size(B.e1, B.e2);
-  T areg = (T)prm[2];
-  T n1 = dot(A.e1, A.e1), n2 = dot(A.e2, A.e2);
-  T r = areg * T(0.5) * (n1 + n2);
-  A.ia = T(1) / (n1 + r); A.ib = T(1) / (n2 + r);
-  n1 = dot(B.e1, B.e1); n2 = dot(B.e2, B.e2);
-  r = areg * T(0.5) * (n1 + n2);
-  B.ia = T(1) / (n1 + r); B.ib = T(1) / (n2 + r);
+  const T areg = (T)prm[2], omega = (T)prm[1];
+  newton_steps(A.e1, A.e2, areg, omega, A.ia, A.ib);
+  newton_steps(B.e1, B.e2, areg, omega, B.ia, B.ib);
   IterParams ip;
   ip.n_iter = 4;
-  ip.omega = prm[1];
   double rho = prm[3];
-  ip.kappa1 = (float)(rho / (rho + 1.0));
-  ip.kappa2 = (float)(rho / (2.0 * rho + 1.0));
+  ip.nkappa = (float)(-rho / (rho + 1.0));
   ip.init_centroid = (int)prm[4];
   V3<T> D0 = A.v0 - B.v0;
   T d, wp[3], wq[3];

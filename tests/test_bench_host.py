@@ -27,7 +27,7 @@ def test_traffic_only_for_matching_sources_and_launch(tmp_path):
 
 
 def test_flops_per_eval_counts():
-    # 80 per Newton iteration, 24 saved by the first, 93 for set-up and bound
-    assert bench.flops_per_eval(4) == 389
-    assert bench.flops_per_eval(0) == 93
-    assert bench.flops_per_eval(1) == 149
+    # 74 per Newton iteration, 24 saved by the first, 84 for set-up, clamp and bound
+    assert bench.flops_per_eval(4) == 356
+    assert bench.flops_per_eval(0) == 84
+    assert bench.flops_per_eval(1) == 134
