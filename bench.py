@@ -283,7 +283,10 @@ def kernel_times(torch, step: Step, K: int):
     eng.p.n_events = n_ev
     # slots: reset, flatten, seed, (descent, lazy flatten) per depth or the
     # flat kernel, certify (if on), fallback
-    n_launch = 3 + (2 * eng.ds.n_levels_max if eng.p.mode == _abi.DEM_MODE_HIER else 1) + (2 if eng.p.certify else 1)
+    if eng.p.mode == _abi.DEM_MODE_HIER and eng.p.persistent:
+        n_launch = 3 + (2 if eng.p.certify else 1)  # reset, flatten, persistent descent, certify, fallback
+    else:
+        n_launch = 3 + (2 * eng.ds.n_levels_max if eng.p.mode == _abi.DEM_MODE_HIER else 1) + (2 if eng.p.certify else 1)
     acc = np.zeros(n_launch)
     bwd = 0.0
     evals = np.zeros(_abi.DEM_MAX_LEVELS)
@@ -680,8 +683,14 @@ def main():
     log(f"[bench] hier: {ms:.3f} ms/step (wall {ms_wall:.3f}), {evals:.4g} evals/step, "
         f"{st['contacts']:.0f} contacts, near {st['near']:.0f}")
     L = ds.n_levels_max
-    level_kt = kt[3:3 + 2 * L:2]   # descent launches
-    fine_kt = kt[4:4 + 2 * L:2]    # lazy flattening after each depth
+    persistent = bool(eng.p.persistent)
+    if persistent:
+        # one launch: seeding, every depth and the lazy flattening
+        level_kt, fine_kt, nb, seed_ms = kt[2:3], [], 3, None
+    else:
+        level_kt = kt[3:3 + 2 * L:2]   # descent launches
+        fine_kt = kt[4:4 + 2 * L:2]    # lazy flattening after each depth
+        nb, seed_ms = 3 + 2 * L, kt[2]
     level_ms = float(np.sum(level_kt))
     n_iter = eng.p.n_iter
     fl = flops_per_eval(n_iter) * evals
@@ -689,20 +698,20 @@ def main():
     peak = PEAK_FP64_VALU_TFLOPS if dtype == "f64" else PEAK_FP32_VALU_TFLOPS
     achieved = fl / (level_ms * 1e-3) / 1e12
     launch = launch_knobs(eng)
-    traffic, traffic_note = measured_traffic(args.workload, "k_level", launch)
-    roof = {"bound": "alu", "kernel": f"k_level<{'double' if dtype == 'f64' else 'float'}>",
+    kname = "k_descent" if persistent else "k_level"
+    traffic, traffic_note = measured_traffic(args.workload, kname, launch)
+    roof = {"bound": "alu", "kernel": f"{kname}<{'double' if dtype == 'f64' else 'float'}>",
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": traffic, "traffic_note": traffic_note,
-            "launches_per_step": L, "avg_launch_ms": level_ms / L,
+            "launches_per_step": len(level_kt), "avg_launch_ms": level_ms / len(level_kt),
             "flops_per_eval": flops_per_eval(n_iter), "evals_per_step": evals,
             "peak_published_packed_fp32": 157.3}
     n_written = ds.n_eager_records
     flat_bytes = (FLATTEN_BYTES_PER_TRI * n_written + FLATTEN_BYTES_SKIPPED * (ds.n_tris - n_written)
                   + FLATTEN_BYTES_PER_VERT * ds.n_verts)
     cert = bool(eng.p.certify)
-    nb = 3 + 2 * L
     kernels = {"reset_ms": kt[0], "flatten_ms": kt[1], "fine_flatten_ms": float(np.sum(fine_kt)),
-               "seed_ms": kt[2], "levels_ms": level_ms,
+               "seed_ms": seed_ms, "levels_ms": level_ms,
                "levels_ms_each": [round(x, 4) for x in level_kt],
                "certify_ms": kt[nb] if cert else None, "fallback_ms": kt[nb + (1 if cert else 0)],
                "near_ms": float(np.sum(kt[nb:])),

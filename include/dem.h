@@ -70,6 +70,7 @@ typedef enum { DEM_MODE_FLAT = 0, DEM_MODE_HIER = 1 } dem_mode;
 #define DEM_DEV_NONFINITE 0x8u        /* a non-finite coordinate or distance was met */
 #define DEM_DEV_BAD_TREE 0x10u        /* a child count outside 0..DEM_MAX_CHILDREN */
 #define DEM_DEV_FRONTIER_OVERFLOW 0x20u /* active sets outgrew dem_frontier's capacity or memory set */
+#define DEM_DEV_STALLED 0x40u         /* persistent descent: a grid barrier gave up waiting (results invalid) */
 
 #define DEM_MAX_LEVELS 32
 #define DEM_MAX_CHILDREN 16           /* children per surrogate (N_surrogate <= 16) */
@@ -260,7 +261,7 @@ typedef struct {
                              the iteration, as in dem_find_contacts */
   double energy_k;        /* k of E = k sum max(0, delta - d)^2 (used when dev_energy != NULL) */
   int32_t block;          /* threads per block of the descent / near kernels: 64, 128 or 256 */
-  int32_t grid;           /* blocks of the persistent kernels (0 = 2048; default 1024) */
+  int32_t grid;           /* blocks of the descent and near-pair kernels (0 = 2048, else >= 8; default 1024) */
   int32_t batch_items;    /* work items a block claims at once (1..block; default 128) */
   int32_t flat_tile_i;    /* flat mode: i-triangles per tile (multiple of 64, <= 1024) */
   int32_t flat_tile_j;    /* flat mode: j-triangles staged in LDS per tile (1..64) */
@@ -292,6 +293,17 @@ typedef struct {
    * call is captured into a graph). */
   void* const* events;
   int32_t n_events;
+  /* 1: the whole descent (seeding, every depth, the lazy flattening) runs as
+   * one persistent kernel with a device work queue: a grid of co-resident
+   * blocks (sized from the kernel's occupancy) claims batches of each
+   * depth's items dynamically, stealing across the per-XCD segments, with
+   * grid barriers between depths.  Timing slots are then: reset, flatten,
+   * descent, certify (if certify), fallback.  0 (default): one launch per
+   * depth. */
+  int32_t persistent;
+  /* Polls a block of the persistent descent makes at a grid barrier before
+   * it gives up and sets DEM_DEV_STALLED (0 = about a second's worth). */
+  int32_t persistent_spins;
 } dem_params;
 
 /* Fill p with the defaults (N_it = 4, HIER mode, exact fallback, no per-depth overrides). */

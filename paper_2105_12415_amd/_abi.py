@@ -22,6 +22,7 @@ DEM_DEV_NEAR_OVERFLOW = 0x4
 DEM_DEV_NONFINITE = 0x8
 DEM_DEV_BAD_TREE = 0x10
 DEM_DEV_FRONTIER_OVERFLOW = 0x20
+DEM_DEV_STALLED = 0x40
 DEM_MAX_LEVELS = 32
 DEM_MAX_CHILDREN = 16
 DEM_SCRATCH_BYTES = 64 << 20
@@ -81,7 +82,8 @@ class Params(C.Structure):
                 ("seed_chunk", C.c_int32), ("frontier_grid", C.c_int32), ("half_depths", C.c_int32),
                 ("level_grid", C.c_int32 * DEM_MAX_LEVELS), ("level_batch", C.c_int32 * DEM_MAX_LEVELS),
                 ("queue_capacity", C.c_int64), ("near_capacity", C.c_int64),
-                ("events", C.POINTER(C.c_void_p)), ("n_events", C.c_int32)]
+                ("events", C.POINTER(C.c_void_p)), ("n_events", C.c_int32),
+                ("persistent", C.c_int32), ("persistent_spins", C.c_int32)]
 
 
 class Contacts(C.Structure):

@@ -405,6 +405,11 @@ class ContactEngine:
                 raise DemError("non-finite coordinates or distances")
             if status & _abi.DEM_DEV_BAD_TREE:
                 raise DemError("malformed surrogate tree (child counts)")
+            if status & _abi.DEM_DEV_STALLED:
+                # the persistent descent's grid could not synchronise (e.g. not
+                # all of its blocks were resident): one launch per depth instead
+                self.p.persistent = 0
+                continue
             if not status & (_abi.DEM_DEV_CONTACT_OVERFLOW | _abi.DEM_DEV_QUEUE_OVERFLOW |
                              _abi.DEM_DEV_NEAR_OVERFLOW):
                 return status

@@ -54,6 +54,8 @@ constexpr int kCountMask = 0xFFFF;
 // dispatch).  Appends from all compute units to one tail serialise in the
 // memory-side atomic unit; eight tails spread them.
 constexpr int kSeg = 8;
+// XCC (XCD) ids the hardware can report: the low 4 bits of HW_REG_XCC_ID.
+constexpr int kMaxXcc = 16;
 
 struct Counters {
   uint32_t tail[DEM_MAX_LEVELS + 1][kSeg];  // level queues
@@ -62,7 +64,15 @@ struct Counters {
   uint32_t fr_unfold;                       // frontier step: leaves that widen
   uint32_t fr_collapse;                     // frontier step: sibling groups that narrow
   uint32_t fr_skip;                         // frontier step: leave the active sets as they are
-  uint32_t pad[13];
+  uint32_t claim[DEM_MAX_LEVELS][kSeg];     // persistent descent: batches claimed per depth and segment
+  // persistent descent: grid barrier, every counter on a 128-byte line of its
+  // own (arrivals at one address serialise; these spread them)
+  alignas(128) uint32_t bar_top[32];        // arrivals of whole XCCs, summed over the call's barriers
+  uint32_t bar_reg_top[32];                 // registration groups complete
+  uint32_t bar_reg[kSeg][32];               // registrations per group of blocks (blockIdx % kSeg)
+  uint32_t bar_blocks[kMaxXcc][32];         // blocks resident on each XCC
+  uint32_t bar_arrive[kMaxXcc][32];         // block arrivals per XCC, summed over the call's barriers
+  uint32_t bar_release[kMaxXcc][32];        // barriers the XCC's last block has released
 };
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -305,14 +315,21 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten(FlatArgs<T> a) {
 constexpr int kFineLanes = 4;
 
 template <typename T>
-__global__ void __launch_bounds__(kFlatBlock) k_fine(FlatArgs<T> a, const int32_t* __restrict__ parents, int n) {
+struct FineShared {
+  SoupRec<T> stage[kFlatBlock];
+  int dest[kFlatBlock];
+};
+
+// The children of parents[0 .. n) that survived (mark set), over blocks
+// start, start + stride, ... of kFlatBlock threads.
+template <typename T>
+__device__ __forceinline__ void fine_range(const FlatArgs<T>& a, const int32_t* __restrict__ parents, int n,
+                                           FineShared<T>& sh, uint32_t start, uint32_t stride) {
   // a lane's first child goes through LDS (whole 16-byte chunks of sibling
   // records leave together, as in k_flatten); further children of a parent
   // with more than kFineLanes are stored directly
-  __shared__ SoupRec<T> stage[kFlatBlock];
-  __shared__ int dest[kFlatBlock];
   const int64_t total = (int64_t)n * kFineLanes;
-  for (int64_t base = blockIdx.x * (int64_t)kFlatBlock; base < total; base += (int64_t)gridDim.x * kFlatBlock) {
+  for (int64_t base = start * (int64_t)kFlatBlock; base < total; base += (int64_t)stride * kFlatBlock) {
     const int64_t i = base + threadIdx.x;
     int d = -1;
     if (i < total) {
@@ -327,40 +344,45 @@ __global__ void __launch_bounds__(kFlatBlock) k_fine(FlatArgs<T> a, const int32_
         } else {
           if (slot < cc) {
             d = cb + slot;
-            stage[threadIdx.x] = flatten_rec(a, d, a.cbeg[d], a.ccnt[d], a.tpart[d]);
+            sh.stage[threadIdx.x] = flatten_rec(a, d, a.cbeg[d], a.ccnt[d], a.tpart[d]);
           }
           for (int c = cb + slot + kFineLanes; c < cb + cc; c += kFineLanes)
             flatten_one(a, c, a.cbeg[c], a.ccnt[c], a.tpart[c]);
         }
       }
     }
-    dest[threadIdx.x] = d;
+    sh.dest[threadIdx.x] = d;
     __syncthreads();
     constexpr int kChunks = (int)(sizeof(SoupRec<T>) / 16);
-    const uint4* src = reinterpret_cast<const uint4*>(stage);
+    const uint4* src = reinterpret_cast<const uint4*>(sh.stage);
     uint4* out = reinterpret_cast<uint4*>(a.soup);
     for (int c = threadIdx.x; c < kFlatBlock * kChunks; c += kFlatBlock) {
-      const int dr = dest[c / kChunks];
+      const int dr = sh.dest[c / kChunks];
       if (dr >= 0) out[(size_t)dr * kChunks + c % kChunks] = src[c];
     }
     __syncthreads();
   }
 }
 
-// One block per candidate pair: items covering range_i x range_j in chunks,
-// appended to segment blockIdx % kSeg of the level-0 list.
-__global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
-                       const int32_t* __restrict__ rbeg, const int32_t* __restrict__ rcnt, int ci,
-                       int cj, int4* __restrict__ q, uint32_t* tails, int64_t seg_cap,
-                       uint32_t* status) {
-  int pr = blockIdx.x;
-  if (pr >= n_pairs) return;
+template <typename T>
+__global__ void __launch_bounds__(kFlatBlock) k_fine(FlatArgs<T> a, const int32_t* __restrict__ parents, int n) {
+  __shared__ FineShared<T> sh;
+  fine_range(a, parents, n, sh, blockIdx.x, gridDim.x);
+}
+
+// Items covering range_i x range_j of candidate pair pr in chunks, appended
+// to segment blockIdx % kSeg of the level-0 list (block-level; base: a word
+// of LDS).
+__device__ __forceinline__ void seed_pair(int pr, const int32_t* __restrict__ pairs, int n_pairs,
+                                          const int32_t* __restrict__ rbeg, const int32_t* __restrict__ rcnt,
+                                          int ci, int cj, int4* __restrict__ q, uint32_t* tails, int64_t seg_cap,
+                                          uint32_t* status, uint32_t& base) {
   int pi = pairs[pr], pj = pairs[n_pairs + pr];
   int bi = rbeg[pi], ni = rcnt[pi], bj = rbeg[pj], nj = rcnt[pj];
   int nci = (ni + ci - 1) / ci, ncj = (nj + cj - 1) / cj;
   int n = nci * ncj;
   const uint32_t x = blockIdx.x % kSeg;
-  __shared__ uint32_t base;
+  __syncthreads();
   if (threadIdx.x == 0) base = n > 0 ? atomicAdd(&tails[x], (uint32_t)n) : 0;
   __syncthreads();
   int4* seg = q + (size_t)x * (size_t)seg_cap;
@@ -377,6 +399,16 @@ __global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
     else
       atomicOr(status, DEM_DEV_QUEUE_OVERFLOW);
   }
+}
+
+// One block per candidate pair.
+__global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
+                       const int32_t* __restrict__ rbeg, const int32_t* __restrict__ rcnt, int ci,
+                       int cj, int4* __restrict__ q, uint32_t* tails, int64_t seg_cap,
+                       uint32_t* status) {
+  __shared__ uint32_t base;
+  if ((int)blockIdx.x < n_pairs)
+    seed_pair(blockIdx.x, pairs, n_pairs, rbeg, rcnt, ci, cj, q, tails, seg_cap, status, base);
 }
 
 // Block-wide exclusive scan of v (blockDim <= 1024) into offs[0..n].
@@ -499,152 +531,155 @@ constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between
 // Outcome of a frontier leaf in a step (byte 0 of its outcome word).
 constexpr uint32_t kOutPrune = 0, kOutKeep = 1, kOutUnfold = 2, kOutNear = 3;
 
-// Descent over one tree depth.  Work items are products of two triangle
-// ranges (the children of a surviving surrogate pair, or a chunk of the
-// roots); lanes take one child pair each, located through a block-wide scan
-// of the items' pair counts.
-//
-// The blocks of XCD x take the batches of segment x, the items that XCD
-// produced at the previous depth (hardware dispatches workgroups
-// round-robin over the 8 XCDs, so block b runs on XCD b % 8): a subtree of
-// the descent stays on one XCD, whose L2 already holds its triangles.
+// LDS of the descent over one depth: one item per thread, stages of two
+// rounds; under 20 KB at BLOCK = 256 so that eight blocks fit in a CU's 160 KB.
+template <int BLOCK>
+struct LevelShared {
+  int4 items[BLOCK];
+  int offs[BLOCK + 1];
+  int wsum[16];
+  uint8_t owner[BLOCK * 8];
+  LdsQueue<int4, 3 * BLOCK> qi;
+  LdsQueue<int2, 3 * BLOCK> qn;
+  SegView view;
+  uint32_t claim;      // persistent descent: the next batch claimed by thread 0
+  uint32_t claim_seg;  // persistent descent: the segment of that batch
+};
+
+struct LevelCounts {
+  unsigned long long evals, surv, near;
+};
+
+// One batch of work items: items [first, first + n) of segment x of the
+// depth's queue.  Work items are products of two triangle ranges (the
+// children of a surviving surrogate pair, or a chunk of the roots); lanes
+// take one child pair each, located through a block-wide scan of the items'
+// pair counts.  Survivors are staged in LDS and flushed to the block's own
+// segment of the next queue / the near list.
 template <typename T, int N, int BLOCK, bool HALF>
-__global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
-  // LDS sized to the block: one item per thread, stages of two rounds;
-  // under 20 KB at BLOCK = 256 so that eight blocks fit in a CU's 160 KB
-  __shared__ int4 items[BLOCK];
-  __shared__ int offs[BLOCK + 1];
-  __shared__ int wsum[16];
-  __shared__ uint8_t owner_s[BLOCK * 8];
-  __shared__ LdsQueue<int4, 3 * BLOCK> qi;
-  __shared__ LdsQueue<int2, 3 * BLOCK> qn;
-  __shared__ SegView view;
-  seg_view(view, a.tail_in, a.qcap);
+__device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup, const LevelArgs& a,
+                                            LevelShared<BLOCK>& sh, uint32_t x, uint32_t first, int n,
+                                            LevelCounts& c) {
   const uint32_t bdim = blockDim.x;
-  const uint32_t batch = (uint32_t)a.batch;
-  unsigned long long my_evals = 0, my_surv = 0, my_near = 0;
-  if (threadIdx.x == 0) { qi.n = 0; qn.n = 0; }
-  // static: the blocks of XCD x (b % 8 == x) stride over segment x
-  const uint32_t x = blockIdx.x % kSeg;
-  const uint32_t per = gridDim.x / kSeg + ((blockIdx.x % kSeg) < (gridDim.x % kSeg) ? 1u : 0u);
-  const uint32_t fill = view.pre[x + 1] - view.pre[x];
-  for (uint32_t first = (blockIdx.x / kSeg) * batch; first < fill; first += per * batch) {
-    const int n = (int)min(batch, fill - first);
-    const int4* seg_items = a.qin + (size_t)x * (size_t)a.qcap + first;
-    int np = 0, quad_item = 1;
-    if ((int)threadIdx.x < n) {
-      int4 it = seg_items[threadIdx.x];
-      if (it.y < 1 || it.y > DEM_MAX_CHILDREN || it.w < 1 || it.w > DEM_MAX_CHILDREN) {
-        atomicOr(a.status, DEM_DEV_BAD_TREE);  // malformed tree: skip the item
-        it.y = it.w = 0;
-      }
-      items[threadIdx.x] = it;
-      np = it.y * it.w;
-      quad_item = it.y == 4 && it.w == 4;
+  const int4* seg_items = a.qin + (size_t)x * (size_t)a.qcap + first;
+  int np = 0, quad_item = 1;
+  if ((int)threadIdx.x < n) {
+    int4 it = seg_items[threadIdx.x];
+    if (it.y < 1 || it.y > DEM_MAX_CHILDREN || it.w < 1 || it.w > DEM_MAX_CHILDREN) {
+      atomicOr(a.status, DEM_DEV_BAD_TREE);  // malformed tree: skip the item
+      it.y = it.w = 0;
     }
-    // a batch of 4 x 4 products only (the subdivision's children): pair e is
-    // child pair e mod 16 of item e / 16, no scan or table needed
-    const bool quad = __syncthreads_and(quad_item) != 0;
-    int total;
-    bool mapped = false;
-    if (quad) {
-      total = 16 * n;
-    } else {
-      block_scan(np, offs, wsum, n);
-      total = offs[n];
-      // small batches map pair -> item through an LDS table; large ones
-      // (root chunks) search the offsets
-      mapped = total <= BLOCK * 8 && n <= 256;
-      if (mapped && (int)threadIdx.x < n) {
-        const int o = offs[threadIdx.x];
-        for (int q = 0; q < np; ++q) owner_s[o + q] = (uint8_t)threadIdx.x;
-      }
-      if (mapped) __syncthreads();
+    sh.items[threadIdx.x] = it;
+    np = it.y * it.w;
+    quad_item = it.y == 4 && it.w == 4;
+  }
+  // a batch of 4 x 4 products only (the subdivision's children): pair e is
+  // child pair e mod 16 of item e / 16, no scan or table needed
+  const bool quad = __syncthreads_and(quad_item) != 0;
+  int total;
+  bool mapped = false;
+  if (quad) {
+    total = 16 * n;
+  } else {
+    block_scan(np, sh.offs, sh.wsum, n);
+    total = sh.offs[n];
+    // small batches map pair -> item through an LDS table; large ones
+    // (root chunks) search the offsets
+    mapped = total <= BLOCK * 8 && n <= 256;
+    if (mapped && (int)threadIdx.x < n) {
+      const int o = sh.offs[threadIdx.x];
+      for (int q = 0; q < np; ++q) sh.owner[o + q] = (uint8_t)threadIdx.x;
     }
-    int round = 0;
-    for (int base = 0; base < total; base += bdim, ++round) {
-      const int e = base + (int)threadIdx.x;
-      bool push_item = false, push_near = false;
-      int4 nx = make_int4(0, 0, 0, 0);
-      int ci = 0, cj = 0;
-      if (e < total) {
-        int4 it;
-        int qd, rr;
-        if (quad) {
-          it = items[e >> 4];
-          qd = (e >> 2) & 3;
-          rr = e & 3;
+    if (mapped) __syncthreads();
+  }
+  int round = 0;
+  for (int base = 0; base < total; base += bdim, ++round) {
+    const int e = base + (int)threadIdx.x;
+    bool push_item = false, push_near = false;
+    int4 nx = make_int4(0, 0, 0, 0);
+    int ci = 0, cj = 0;
+    if (e < total) {
+      int4 it;
+      int qd, rr;
+      if (quad) {
+        it = sh.items[e >> 4];
+        qd = (e >> 2) & 3;
+        rr = e & 3;
+      } else {
+        // item owning flat index e: last k with offs[k] <= e
+        int lo = 0, hi = n - 1;
+        if (mapped) {
+          lo = sh.owner[e];
         } else {
-          // item owning flat index e: last k with offs[k] <= e
-          int lo = 0, hi = n - 1;
-          if (mapped) {
-            lo = owner_s[e];
-          } else {
-            while (lo < hi) {
-              int mid = (lo + hi + 1) >> 1;
-              if (offs[mid] <= e) lo = mid; else hi = mid - 1;
-            }
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (sh.offs[mid] <= e) lo = mid; else hi = mid - 1;
           }
-          it = items[lo];
-          const int l = e - offs[lo];
-          const int jn = it.w;
-          qd = (int)((float)l * rcp_fast((float)jn));
-          rr = l - qd * jn;
-          if (rr < 0) { qd -= 1; rr += jn; }
-          if (rr >= jn) { qd += 1; rr -= jn; }
         }
-        ci = it.x + qd;
-        cj = it.z + rr;
-        int cbi, cci, pi_, cbj, ccj, pj_;
-        bool kfi, kfj;
-        Tri<T> A = load_tri(soup, ci, cbi, cci, pi_, kfi);
-        Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_, kfj);
-        V3<T> D0 = A.v0 - B.v0;
-        T L;
-        if constexpr (HALF && sizeof(T) == 4) {
-          L = iterate_bound_mixed<N>(A, B, D0, a.ip);
-        } else {
-          L = iterate_bound<T, N>(A, B, D0, a.ip);
-        }
-        T delta = A.eps + B.eps;
-        bool fine = (cci == 0) && (ccj == 0);
-        bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
-        ++my_evals;
-        // surrogate survivors unfold into the next depth's item (only the
-        // non-fine side unfolds); fine survivors go to the near list
-        push_item = keep && !fine;
-        push_near = keep && fine;
-        // lazy flattening: a surviving surrogate with fine children has them
-        // written before the next depth (plain byte stores of the same value)
-        if (a.mark && push_item) {
-          if (kfi) a.mark[ci] = 1;
-          if (kfj) a.mark[cj] = 1;
-        }
-        nx.x = cci ? cbi : ci; nx.y = cci ? cci : 1;
-        nx.z = ccj ? cbj : cj; nx.w = ccj ? ccj : 1;
-        my_surv += push_item;
-        my_near += push_near;
+        it = sh.items[lo];
+        const int l = e - sh.offs[lo];
+        const int jn = it.w;
+        qd = (int)((float)l * rcp_fast((float)jn));
+        rr = l - qd * jn;
+        if (rr < 0) { qd -= 1; rr += jn; }
+        if (rr >= jn) { qd += 1; rr -= jn; }
       }
-      lds_append(push_item, nx, qi.buf, &qi.n);
-      lds_append(push_near, make_int2(ci, cj), qn.buf, &qn.n);
-      // check the stages every second round and at the batch's end: after a
-      // check at most BLOCK entries remain, two rounds add at most 2 * bdim
-      if ((round & 1) || base + (int)bdim >= total) {
-        __syncthreads();
-        if (qi.n + 2 * bdim > (uint32_t)(3 * BLOCK))
-          lds_flush(qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
-        if (qn.n + 2 * bdim > (uint32_t)(3 * BLOCK))
-          lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+      ci = it.x + qd;
+      cj = it.z + rr;
+      int cbi, cci, pi_, cbj, ccj, pj_;
+      bool kfi, kfj;
+      Tri<T> A = load_tri(soup, ci, cbi, cci, pi_, kfi);
+      Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_, kfj);
+      V3<T> D0 = A.v0 - B.v0;
+      T L;
+      if constexpr (HALF && sizeof(T) == 4) {
+        L = iterate_bound_mixed<N>(A, B, D0, a.ip);
+      } else {
+        L = iterate_bound<T, N>(A, B, D0, a.ip);
       }
+      T delta = A.eps + B.eps;
+      bool fine = (cci == 0) && (ccj == 0);
+      bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
+      ++c.evals;
+      // surrogate survivors unfold into the next depth's item (only the
+      // non-fine side unfolds); fine survivors go to the near list
+      push_item = keep && !fine;
+      push_near = keep && fine;
+      // lazy flattening: a surviving surrogate with fine children has them
+      // written before the next depth (plain byte stores of the same value)
+      if (a.mark && push_item) {
+        if (kfi) a.mark[ci] = 1;
+        if (kfj) a.mark[cj] = 1;
+      }
+      nx.x = cci ? cbi : ci; nx.y = cci ? cci : 1;
+      nx.z = ccj ? cbj : cj; nx.w = ccj ? ccj : 1;
+      c.surv += push_item;
+      c.near += push_near;
     }
-    __syncthreads();
+    lds_append(push_item, nx, sh.qi.buf, &sh.qi.n);
+    lds_append(push_near, make_int2(ci, cj), sh.qn.buf, &sh.qn.n);
+    // check the stages every second round and at the batch's end: after a
+    // check at most BLOCK entries remain, two rounds add at most 2 * bdim
+    if ((round & 1) || base + (int)bdim >= total) {
+      __syncthreads();
+      if (sh.qi.n + 2 * bdim > (uint32_t)(3 * BLOCK))
+        lds_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
+      if (sh.qn.n + 2 * bdim > (uint32_t)(3 * BLOCK))
+        lds_flush(sh.qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+    }
   }
   __syncthreads();
-  lds_flush(qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
-  lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+}
+
+// End of a depth for this block: the staged survivors leave, and the counts
+// reach the statistics (one atomic per wave).
+template <int BLOCK>
+__device__ __forceinline__ void level_finish(const LevelArgs& a, LevelShared<BLOCK>& sh, LevelCounts& c) {
+  __syncthreads();
+  lds_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
+  lds_flush(sh.qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
   if (a.stats) {
-    // one atomic per wave
-    unsigned long long s0 = my_evals, s1 = my_surv, s2 = my_near;
+    unsigned long long s0 = c.evals, s1 = c.surv, s2 = c.near;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       s0 += __shfl_xor(s0, o);
@@ -655,6 +690,263 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
       if (s0) atomicAdd(&a.stats->evals[a.depth], s0);
       if (s1) atomicAdd(&a.stats->survivors[a.depth], s1);
       if (s2) atomicAdd(&a.stats->near, s2);
+    }
+  }
+  c.evals = c.surv = c.near = 0;
+}
+
+// Descent over one tree depth, one launch per depth (Algorithm 5, pairwise
+// form).  The blocks of XCD x take the batches of segment x, the items that
+// XCD produced at the previous depth (hardware dispatches workgroups
+// round-robin over the 8 XCDs, so block b runs on XCD b % 8): a subtree of
+// the descent stays on one XCD, whose L2 already holds its triangles.
+template <typename T, int N, int BLOCK, bool HALF>
+__global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
+  __shared__ LevelShared<BLOCK> sh;
+  seg_view(sh.view, a.tail_in, a.qcap);
+  LevelCounts c{0, 0, 0};
+  if (threadIdx.x == 0) { sh.qi.n = 0; sh.qn.n = 0; }
+  const uint32_t batch = (uint32_t)a.batch;
+  const uint32_t x = blockIdx.x % kSeg;
+  const uint32_t per = gridDim.x / kSeg + ((blockIdx.x % kSeg) < (gridDim.x % kSeg) ? 1u : 0u);
+  const uint32_t fill = sh.view.pre[x + 1] - sh.view.pre[x];
+  for (uint32_t first = (blockIdx.x / kSeg) * batch; first < fill; first += per * batch)
+    level_batch<T, N, BLOCK, HALF>(soup, a, sh, x, first, (int)min(batch, fill - first), c);
+  level_finish(a, sh, c);
+}
+
+// ------------------------------------------------------------------ persistent descent
+// The whole descent of a step in one launch: a grid of co-resident blocks
+// seeds the root pairs, then runs every depth with a device work queue --
+// each block claims batches of its XCD's segment with one atomic on a
+// per-segment claim counter (claimed one batch ahead, so the atomic's latency
+// overlaps the current batch) and, once that segment is exhausted, claims
+// from the other segments in turn -- followed by the lazy flattening of the
+// surviving parents' fine children; grid barriers separate the phases.
+// Particle pairs of very different sizes and depths share the grid: a block
+// that runs out of its own work takes another XCD's.
+//
+// The grid barrier waits for every block, so the grid must be co-resident
+// (the host sizes it from the occupancy of this kernel).  Each wait is
+// bounded: after spin_limit polls the block gives up and sets
+// DEM_DEV_STALLED; every block stops at its next barrier once that flag is
+// set (a block never runs a phase whose inputs may be incomplete), so the
+// kernel always ends, and the host repeats the call with one launch per
+// depth.
+//
+// The barrier is hierarchical, along the XCCs (XCDs): each XCC has its own
+// L2, which is not coherent with the others.  A block's stores reach its
+// XCC's L2 before it arrives; the last block of an XCC to arrive writes that
+// L2 back (one agent-scope release for the XCC, not one per block), arrives
+// for the whole XCC, waits for every XCC, invalidates its caches (an
+// agent-scope acquire) and releases the XCC's blocks, which then acquire
+// too.  A flat barrier (one counter for every block, a release and an
+// acquire per block) measured about 110 us per barrier with 1536 blocks;
+// this one about 15 us.
+constexpr uint32_t kBarrierSpins = 1u << 21;  // polls of ~500 cycles each: about a second
+
+__device__ __forceinline__ uint32_t xcc_id() {
+  // HW_REG_XCC_ID (hardware register 20), bits 3:0
+  return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (uint32_t)(kMaxXcc - 1);
+}
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait until *p >= target (thread 0).  false, with DEM_DEV_STALLED
+// set, if the limit is reached or another block has given up.
+__device__ __forceinline__ bool wait_at_least(const uint32_t* p, uint32_t target, uint32_t* status,
+                                              uint32_t spin_limit) {
+  uint32_t spins = 0;
+  while (ld_agent(p) < target) {
+    if (++spins > spin_limit || (ld_agent(status) & DEM_DEV_STALLED)) {
+      atomicOr(status, DEM_DEV_STALLED);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  return true;
+}
+
+// Thread 0's view of the barrier: its XCC, the blocks resident there, the
+// XCCs that hold blocks, the barriers passed.
+struct GridBarrier {
+  uint32_t x, nx, nact, epoch;
+};
+
+// At the kernel's start (thread 0): count this block on its XCC, then arrive
+// in its registration group (the group's last block completes the group).
+__device__ __forceinline__ void grid_register(Counters* ctr, GridBarrier& b) {
+  b.x = xcc_id();
+  b.epoch = 0;
+  __hip_atomic_fetch_add(&ctr->bar_blocks[b.x][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);  // the count is performed before the arrival below
+  const uint32_t g = blockIdx.x % kSeg;
+  const uint32_t gsize = gridDim.x / kSeg + (g < gridDim.x % kSeg ? 1u : 0u);
+  if (__hip_atomic_fetch_add(&ctr->bar_reg[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gsize)
+    __hip_atomic_fetch_add(&ctr->bar_reg_top[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every block has registered (thread 0; the grid has at least kSeg blocks):
+// read this XCC's block count and the number of XCCs holding blocks.
+__device__ __forceinline__ bool grid_ready(Counters* ctr, GridBarrier& b, uint32_t* status, uint32_t spin_limit) {
+  if (!wait_at_least(ctr->bar_reg_top, (uint32_t)kSeg, status, spin_limit)) return false;
+  b.nx = ld_agent(ctr->bar_blocks[b.x]);
+  b.nact = 0;
+  for (int x = 0; x < kMaxXcc; ++x) b.nact += ld_agent(ctr->bar_blocks[x]) > 0u;
+  return true;
+}
+
+// The grid barrier (every thread of every block).  false: the call gave up
+// (DEM_DEV_STALLED), the block must stop.
+__device__ __forceinline__ bool grid_sync(Counters* ctr, GridBarrier& b, uint32_t* status, uint32_t spin_limit) {
+  __shared__ uint32_t s_ok;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached the XCC's L2
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool ok = !(ld_agent(status) & DEM_DEV_STALLED);
+    if (ok) {
+      ++b.epoch;
+      const uint32_t old = __hip_atomic_fetch_add(&ctr->bar_arrive[b.x][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1u == b.nx * b.epoch) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the XCC's L2 written back
+        __hip_atomic_fetch_add(&ctr->bar_top[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = wait_at_least(ctr->bar_top, b.nact * b.epoch, status, spin_limit);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the XCC's L2 and this CU's L1 invalidated
+        if (ok) __hip_atomic_store(&ctr->bar_release[b.x][0], b.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = wait_at_least(ctr->bar_release[b.x], b.epoch, status, spin_limit);
+        // this compute unit's L1 may hold lines that other blocks have written
+        // since: an agent-scope acquire of its own (an L1-only invalidate, at
+        // workgroup scope, left stale lines behind)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0u;
+}
+
+// One depth with dynamic claiming.  The first batches of segment x go
+// statically to the blocks of x's group (blockIdx % kSeg == x; its r-th
+// block takes batch r, no atomic); the rest are claimed with one atomic on
+// claim[x] each, one batch ahead so the atomic's latency overlaps the current
+// batch.  A block whose segment is exhausted reads the claim counters of the
+// segments that have batches beyond their static share (one load each,
+// issued together) and claims from the one with the most left, until none
+// is left.  A depth's end then costs each block a few loads, not an atomic
+// on each of the 8 counters (1536 blocks x 8 atomics on 8 addresses
+// serialise for about 100 us).
+template <typename T, int N, int BLOCK, bool HALF>
+__device__ __forceinline__ void level_dynamic(const SoupRec<T>* __restrict__ soup, const LevelArgs& a,
+                                              LevelShared<BLOCK>& sh, uint32_t* claim, LevelCounts& c) {
+  seg_view(sh.view, a.tail_in, a.qcap);
+  const uint32_t batch = (uint32_t)a.batch;
+  const auto group = [](uint32_t y) { return gridDim.x / kSeg + (y < gridDim.x % kSeg ? 1u : 0u); };
+  const auto fill = [&](uint32_t y) { return sh.view.pre[y + 1] - sh.view.pre[y]; };
+  const auto nbatch = [&](uint32_t y) { return (fill(y) + batch - 1) / batch; };
+  uint32_t x = blockIdx.x % kSeg, b = blockIdx.x / kSeg;
+  for (;;) {
+    if (b < nbatch(x)) {
+      __syncthreads();  // every thread has read sh.claim
+      if (threadIdx.x == 0)
+        sh.claim = nbatch(x) > group(x) ? group(x) + atomicAdd(&claim[x], 1u) : nbatch(x);
+      level_batch<T, N, BLOCK, HALF>(soup, a, sh, x, b * batch, (int)min(batch, fill(x) - b * batch), c);
+      b = sh.claim;  // level_batch ends with a barrier
+      continue;
+    }
+    __syncthreads();  // every thread has read sh.claim
+    if (threadIdx.x == 0) {
+      uint32_t taken[kSeg];
+#pragma unroll
+      for (int y = 0; y < kSeg; ++y) taken[y] = nbatch(y) > group(y) ? ld_agent(&claim[y]) : 0u;
+      uint32_t sel = kSeg, most = 0;
+#pragma unroll
+      for (int y = 0; y < kSeg; ++y) {
+        const uint32_t nb = nbatch(y), t = group(y) + taken[y];
+        if (nb > t && nb - t > most) { most = nb - t; sel = (uint32_t)y; }
+      }
+      sh.claim_seg = sel;
+      if (sel < kSeg) sh.claim = group(sel) + atomicAdd(&claim[sel], 1u);
+    }
+    __syncthreads();
+    if (sh.claim_seg >= (uint32_t)kSeg) break;
+    x = sh.claim_seg;
+    b = sh.claim;
+  }
+}
+
+template <typename T>
+struct DescentArgs {
+  LevelArgs a;               // near list, statistics, status, iteration, capacities (per-depth fields set here)
+  int4* q0;                  // the two level queues
+  int4* q1;
+  Counters* ctr;
+  int n_levels;
+  int half_depths;           // depths d < half_depths run the half-precision iteration (FP32 only)
+  uint32_t spin_limit;
+  int batch[DEM_MAX_LEVELS];
+  // seeding
+  const int32_t* pairs;
+  int n_pairs;
+  const int32_t* rbeg;
+  const int32_t* rcnt;
+  int seed_chunk;
+  // lazy flattening (fine_parents null: every record was written by the flatten)
+  FlatArgs<T> f;
+  const int32_t* fine_parents;
+  int fine_parent_begin[DEM_MAX_LEVELS + 1];
+};
+
+// 6 waves per SIMD (at most 80 VGPRs), as many as the per-depth kernel gets:
+// the phases other than the depth passes (seeding, fine flattening) would
+// otherwise raise the register count of the whole kernel.
+#ifndef DEM_DESCENT_WAVES
+#define DEM_DESCENT_WAVES 6
+#endif
+template <typename T, int N, int BLOCK, bool HALF>
+__global__ void __launch_bounds__(BLOCK, sizeof(T) == 4 ? DEM_DESCENT_WAVES : 1) k_descent(const SoupRec<T>* __restrict__ soup, DescentArgs<T> d) {
+  constexpr size_t kL = sizeof(LevelShared<BLOCK>), kF = sizeof(FineShared<T>);
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kL > kF ? kL : kF];
+  LevelShared<BLOCK>& sh = *reinterpret_cast<LevelShared<BLOCK>*>(lds);
+  uint32_t* status = d.a.status;
+  GridBarrier bar;
+  if (threadIdx.x == 0) grid_register(d.ctr, bar);
+  // root pairs of every candidate pair (block-level, pairs in turn)
+  for (int pr = blockIdx.x; pr < d.n_pairs; pr += gridDim.x)
+    seed_pair(pr, d.pairs, d.n_pairs, d.rbeg, d.rcnt, d.seed_chunk, d.seed_chunk, d.q0, d.ctr->tail[0], d.a.qcap,
+              status, sh.claim);
+  {
+    __shared__ uint32_t s_ready;
+    if (threadIdx.x == 0) s_ready = grid_ready(d.ctr, bar, status, d.spin_limit);
+    __syncthreads();
+    if (!s_ready) return;
+  }
+  if (!grid_sync(d.ctr, bar, status, d.spin_limit)) return;
+  LevelCounts c{0, 0, 0};
+  for (int lev = 0; lev < d.n_levels; ++lev) {
+    LevelArgs a = d.a;
+    a.qin = (lev & 1) ? d.q1 : d.q0;
+    a.tail_in = d.ctr->tail[lev];
+    a.qout = (lev & 1) ? d.q0 : d.q1;
+    a.tail_out = d.ctr->tail[lev + 1];
+    a.depth = lev;
+    a.batch = d.batch[lev];
+    if (threadIdx.x == 0) { sh.qi.n = 0; sh.qn.n = 0; }
+    if (HALF && lev < d.half_depths)
+      level_dynamic<T, N, BLOCK, HALF>(soup, a, sh, d.ctr->claim[lev], c);
+    else
+      level_dynamic<T, N, BLOCK, false>(soup, a, sh, d.ctr->claim[lev], c);
+    level_finish(a, sh, c);
+    if (!grid_sync(d.ctr, bar, status, d.spin_limit)) return;
+    if (d.fine_parents) {
+      const int f0 = d.fine_parent_begin[lev], nf = d.fine_parent_begin[lev + 1] - f0;
+      if (nf > 0) {
+        fine_range(d.f, d.fine_parents + f0, nf, *reinterpret_cast<FineShared<T>*>(lds), blockIdx.x, gridDim.x);
+        if (!grid_sync(d.ctr, bar, status, d.spin_limit)) return;
+      }
     }
   }
 }
@@ -2303,14 +2595,18 @@ bool params_ok(const dem_params& p) {
   if (p.seed_chunk < 1 || p.seed_chunk > 16) return false;
   if (p.queue_capacity < kSeg || p.queue_capacity > (int64_t)0xFFFFFFFF) return false;
   if (p.near_capacity < kSeg || p.near_capacity > (int64_t)0xFFFFFFFF) return false;
-  if (p.grid < 0) return false;
+  // every block count covers all kSeg segments (blocks of XCD x consume segment x)
+  if (p.grid < 0 || (p.grid > 0 && p.grid < kSeg)) return false;
   if (p.frontier_grid < 0 || p.frontier_grid > kFrMaxGrid) return false;
   if (p.half_depths < 0 || p.half_depths > DEM_MAX_LEVELS) return false;
   for (int d = 0; d < DEM_MAX_LEVELS; ++d) {
-    if (p.level_grid[d] < 0) return false;
+    if (p.level_grid[d] < 0 || (p.level_grid[d] > 0 && p.level_grid[d] < kSeg)) return false;
     if (p.level_batch[d] < 0 || p.level_batch[d] > p.block) return false;  // one item per thread
   }
   if (p.n_events < 0 || (p.n_events > 0 && !p.events)) return false;
+  if (p.persistent != 0 && p.persistent != 1) return false;
+  if (p.persistent && p.block != 256) return false;  // the persistent descent runs 256-thread blocks
+  if (p.persistent_spins < 0) return false;
   return true;
 }
 
@@ -2343,6 +2639,48 @@ void launch_level(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* 
   if (b.x == 64) launch_level_b<T, 64>(n_iter, g, st, soup, la);
   else if (b.x == 128) launch_level_b<T, 128>(n_iter, g, st, soup, la);
   else launch_level_b<T, 256>(n_iter, g, st, soup, la);
+}
+
+// Resident blocks of the persistent descent on the current device (its grid):
+// the kernel's occupancy per compute unit times the compute units.  0 if the
+// runtime cannot tell.
+template <typename T, int N, bool HALF>
+int descent_grid() {
+  static int cached = -1;
+  if (cached < 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_descent<T, N, 256, HALF>),
+                                                     256, 0) != hipSuccess)
+      return 0;
+    cached = per_cu * cus;
+  }
+  return cached;
+}
+
+template <typename T, bool HALF>
+dem_status launch_descent_h(int n_iter, hipStream_t st, const SoupRec<T>* soup, const DescentArgs<T>& d) {
+  switch (n_iter) {
+#define DEM_CASE(N)                                                                              \
+  case N: {                                                                                      \
+    const int g = descent_grid<T, N, HALF>();                                                    \
+    if (g < kSeg) return DEM_ERR_HIP;                                                            \
+    hipLaunchKernelGGL((k_descent<T, N, 256, HALF>), dim3(g), dim3(256), 0, st, soup, d);       \
+    break;                                                                                       \
+  }
+    DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
+#undef DEM_CASE
+  }
+  return DEM_OK;
+}
+
+template <typename T>
+dem_status launch_descent(int n_iter, bool half, hipStream_t st, const SoupRec<T>* soup, const DescentArgs<T>& d) {
+  if constexpr (sizeof(T) == 4) {
+    if (half) return launch_descent_h<T, true>(n_iter, st, soup, d);
+  }
+  return launch_descent_h<T, false>(n_iter, st, soup, d);
 }
 
 template <typename T>
@@ -2416,7 +2754,30 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   la.batch = p.batch_items;
   la.mark = nullptr;
   la.ip = make_iter(p);
-  if (n_pairs > 0) {
+  if (n_pairs > 0 && p.mode == DEM_MODE_HIER && p.persistent) {
+    DescentArgs<T> d{};
+    d.a = la;
+    d.a.mark = fa.lazy ? fa.mark : nullptr;
+    d.q0 = q[0];
+    d.q1 = q[1];
+    d.ctr = ctr;
+    d.n_levels = s->n_levels_max;
+    d.half_depths = s->precision == DEM_F32 ? p.half_depths : 0;
+    d.spin_limit = p.persistent_spins > 0 ? (uint32_t)p.persistent_spins : kBarrierSpins;
+    for (int lev = 0; lev < DEM_MAX_LEVELS; ++lev)
+      d.batch[lev] = p.level_batch[lev] > 0 ? p.level_batch[lev] : p.batch_items;
+    d.pairs = pairs;
+    d.n_pairs = n_pairs;
+    d.rbeg = s->root_begin;
+    d.rcnt = s->root_count;
+    d.seed_chunk = p.seed_chunk;
+    d.f = fa;
+    d.fine_parents = fa.lazy ? s->fine_parents : nullptr;
+    for (int lev = 0; lev <= DEM_MAX_LEVELS; ++lev) d.fine_parent_begin[lev] = fa.lazy ? s->fine_parent_begin[lev] : 0;
+    const dem_status r = launch_descent<T>(p.n_iter, d.half_depths > 0, st, soup, d);
+    if (r != DEM_OK) return r;
+    mark();
+  } else if (n_pairs > 0) {
     if (p.mode == DEM_MODE_HIER) {
       hipLaunchKernelGGL(k_seed, dim3(n_pairs), dim3(256), 0, st, pairs, n_pairs, s->root_begin,
                          s->root_count, p.seed_chunk, p.seed_chunk, q[0], ctr->tail[0], qseg, status);
