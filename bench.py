@@ -77,9 +77,10 @@ WORKLOADS = {
 def measure_peaks(torch, log=print) -> dict:
     """Achievable peaks of this GPU from the project's microbenchmarks
     (libpeak.so): FP32 and FP64 VALU loops over every SIMD (16 independent
-    chains per lane, 8 waves per SIMD) -- FMA with a uniform (SGPR) operand,
-    FMA with three VGPR operands (accumulating form), and FP32 add, multiply
-    and max -- and a 1 GiB device-to-device copy.  For each FP32 kind: the
+    chains per lane, 8 waves per SIMD) -- FMA with uniform (SGPR) operands,
+    FMA with three VGPR operands in the accumulating two-operand encoding
+    (VOP2 FMAC) and in the three-operand encoding (VOP3), and FP32 add,
+    multiply, max and three-input max -- and a 1 GiB device-to-device copy.  For each FP32 kind: the
     issue cycles of one wave64 instruction on a SIMD at the published
     2.4 GHz clock."""
     lib = C.CDLL(os.path.join(ROOT, "paper_2105_12415_amd", "libpeak.so"))
@@ -106,16 +107,21 @@ def measure_peaks(torch, log=print) -> dict:
         return best
 
     out = {}
-    kinds = (("fp32_fma", 0, 0, 2), ("fp32_fmac", 0, 1, 2), ("fp32_add", 0, 2, 1), ("fp32_mul", 0, 3, 1),
-             ("fp32_max", 0, 4, 1), ("fp64_fma", 1, 0, 2), ("fp64_fmac", 1, 1, 2))
-    for name, fp64, kind, flop in kinds:
+    # (name, fp64, kind, flop per operation, VALU instructions per operation:
+    # a two-input max also canonicalises one input)
+    kinds = (("fp32_fma_sgpr", 0, 0, 2, 1), ("fp32_fmac", 0, 1, 2, 1), ("fp32_add", 0, 2, 1, 1),
+             ("fp32_mul", 0, 3, 1, 1), ("fp32_max", 0, 4, 1, 2), ("fp32_fma_vop3", 0, 5, 2, 1),
+             ("fp32_max3", 0, 6, 2, 1), ("fp64_fma_sgpr", 1, 0, 2, 1), ("fp64_fmac", 1, 1, 2, 1))
+    for name, fp64, kind, flop, ipo in kinds:
         iters = 10000 if fp64 else 20000
         buf = torch.empty(blocks * 256, dtype=torch.float64 if fp64 else torch.float32, device="cuda")
         ms = timed(lambda: lib.peak_fma(fp64, kind, blocks, iters, C.c_void_p(buf.data_ptr()), stream), 4)
         ops = blocks * 256 * lib.peak_fma_per_lane(iters)
         out[f"{name}_tflops"] = flop * ops / (ms * 1e-3) / 1e12
-        out[f"{name}_cycles_per_wave64"] = ms * 1e-3 * 2.4e9 * 1024 / (blocks * 4 * lib.peak_fma_per_lane(iters))
-    out["fp32_fma_peak_tflops"] = max(out["fp32_fma_tflops"], out["fp32_fmac_tflops"])
+        out[f"{name}_cycles_per_wave64"] = ms * 1e-3 * 2.4e9 * 1024 / (blocks * 4 * ipo * lib.peak_fma_per_lane(iters))
+    out["fp32_fma_peak_tflops"] = max(out["fp32_fma_sgpr_tflops"], out["fp32_fmac_tflops"],
+                                      out["fp32_fma_vop3_tflops"])
+    out["fp64_fma_peak_tflops"] = max(out["fp64_fma_sgpr_tflops"], out["fp64_fmac_tflops"])
     n = 1 << 30
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
     b = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -626,6 +632,8 @@ def main():
     ap.add_argument("--half-depths", type=int, default=0,
                     help="run the descent's Newton iteration in half precision at tree depths below this "
                          "(applied on top of the stored launch parameters)")
+    ap.add_argument("--peaks-only", action="store_true",
+                    help="only run the achievable-peak microbenchmarks and print them as JSON")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -638,6 +646,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": 4 * n, "copies": 3}))
+        return
+    if args.peaks_only:
+        import torch
+        print(json.dumps(measure_peaks(torch)))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",

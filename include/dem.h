@@ -317,7 +317,23 @@ void dem_default_params(dem_params* p);
  * points and x lies on the segment between them at the centre of the overlap
  * of the two epsilon environments (Section 2: centre of the shortest path
  * for equal eps, shifted by (eps_i - eps_j)/2 otherwise); for d = 0, x = p_i
- * and n = 0.  Order is unspecified. */
+ * and n = 0.  Order is unspecified.
+ *
+ * adjoint (optional, NULL = none): [DEM_ADJOINT_ROWS][capacity] values of the
+ * scene's precision that the call producing the contacts writes beside
+ * them and dem_contact_backward reads instead of solving each pair's
+ * closest points again: row 0 delta = eps_i + eps_j; rows 1-3 the unit
+ * direction u = (p_j - p_i) / d (0 for d = 0); rows 4-6 the barycentric code
+ * of p_i on t_i, rows 7-8 the parameters of p_j on t_j, as
+ *   row 4 = code_i + 8 code_j (codes below), rows 5, 6 = a_i, b_i,
+ *   rows 7, 8 = a_j, b_j;
+ * code 0: weights (1 - a - b, a, b) on the triangle's vertices (v0, v1, v2);
+ * code 1..4: the point of a segment with weight a at its second end,
+ * segments v0->v1, v1->v2, v2->v0, v0->v2 (a = 0: the first end).  The
+ * weights are formed from these codes by the producing kernel itself, so
+ * the gradient from stored rows equals the one from a fresh solve bit for
+ * bit.  dem_sort_contacts moves the rows with their contacts. */
+#define DEM_ADJOINT_ROWS 9
 typedef struct {
   int64_t capacity;
   int32_t* pi;
@@ -328,6 +344,7 @@ typedef struct {
   void* x;          /* [3][capacity] */
   void* n;          /* [3][capacity] */
   uint32_t* count;  /* device scalar: contacts found (may exceed capacity) */
+  void* adjoint;    /* [DEM_ADJOINT_ROWS][capacity] or NULL (see above) */
 } dem_contacts;
 
 /* Per-call counters (device memory, cleared by dem_find_contacts). */
@@ -396,8 +413,8 @@ dem_status dem_find_contacts(const dem_scene* scene, const int32_t* pairs, int32
  * call's contents (counters are cleared by the call's first kernel): calls
  * that overlap on one GPU (other streams, other threads) race and must be
  * serialised by the caller.  The triangle soup it leaves is not available to
- * dem_contact_backward; use dem_find_contacts with a workspace when
- * gradients are needed.
+ * dem_contact_backward: contacts from this call are differentiated through
+ * their adjoint rows (out->adjoint set), which need no workspace.
  */
 #define DEM_SCRATCH_BYTES (64u << 20)
 dem_status dem_find_contacts_noalloc(const dem_scene* scene, const int32_t* pairs, int32_t n_pairs,
@@ -408,29 +425,32 @@ dem_status dem_find_contacts_noalloc(const dem_scene* scene, const int32_t* pair
  * dem_contact_backward -- adjoint of the penalty contact energy
  * E = k * sum over contacts of max(0, delta - d)^2 (delta = eps_i + eps_j).
  *
- * The closest points are recomputed for each contact (nothing but the
- * contact's triangle pair is kept from the forward call); with
- * u = (p_j - p_i) / d and barycentric weights w_i, w_j of the closest
+ * With u = (p_j - p_i) / d and barycentric weights w_i, w_j of the closest
  * points, dE/dv = +2k (delta - d) w_i u for the vertices of t_i and
  * -2k (delta - d) w_j u for those of t_j (envelope theorem: d is a minimum
  * over the two triangles).  Intersecting pairs (d = 0) add energy but no
- * gradient.
+ * gradient.  With contacts->adjoint set, delta, u and the weights come from
+ * its rows and d from contacts->d (no triangle data is read); otherwise the
+ * closest points are solved again for each contact's triangle pair from
+ * the workspace's triangle soup.
  *
  * contacts   the output of the immediately preceding dem_find_contacts (or
  *            dem_frontier_step) on this workspace (device count is read on
- *            device).  A contact naming a triangle outside the scene is
- *            skipped and sets DEM_DEV_BAD_TREE; a contact list from another
- *            call reads soup records that may not have been written there
- *            and gives a meaningless gradient.
+ *            device), possibly reordered by dem_sort_contacts.  A contact
+ *            naming a triangle outside the scene is skipped and sets
+ *            DEM_DEV_BAD_TREE; a contact list from another call reads soup
+ *            records (or adjoint rows) that may not belong to it and gives a
+ *            meaningless gradient.
  * grad_E     device double scalar multiplying the gradient, or NULL for 1.
  * grad_verts device [3][n_verts] with respect to world positions,
  *            ACCUMULATED into (caller zeroes it); NULL for energy only.
  * energy_out device double or NULL: set to E.
- * workspace  the workspace of the dem_find_contacts call that produced
- *            `contacts`, unchanged since, with the scene's verts and pose
- *            unchanged: the triangle soup flattened there is reused.
- *            Needs workspace_bytes >= the soup's end (any size
- *            dem_workspace_bytes returned for this scene suffices).
+ * workspace  without adjoint rows: the workspace of the dem_find_contacts
+ *            call that produced `contacts`, unchanged since, with the
+ *            scene's verts and pose unchanged: the triangle soup flattened
+ *            there is reused.  Needs workspace_bytes >= the soup's end (any
+ *            size dem_workspace_bytes returned for this scene suffices).
+ *            With contacts->adjoint set it is not read (may be NULL).
  * dev_status device uint32: DEM_DEV_* bits are OR-ed in (not cleared).
  */
 dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* contacts, double k,
@@ -443,7 +463,8 @@ dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* cont
  * sorted by (ti, tj), the global triangle numbers (a contact's triangle pair
  * is unique, so the order is total and the same on every run, whatever order
  * the kernels' atomics produced).  All fields (pi, pj, ti, tj, d, x, n) move
- * together, in place; the count is unchanged.  Contacts naming a triangle
+ * together, in place, with the adjoint rows when contacts->adjoint is set;
+ * the count is unchanged.  Contacts naming a triangle
  * outside the scene come last in their input order and set DEM_DEV_BAD_TREE.
  * Kernels only (no memset, no host synchronisation): graph-capturable.
  *

@@ -23,6 +23,7 @@ DEM_DEV_NONFINITE = 0x8
 DEM_DEV_BAD_TREE = 0x10
 DEM_DEV_FRONTIER_OVERFLOW = 0x20
 DEM_DEV_STALLED = 0x40
+DEM_ADJOINT_ROWS = 9
 DEM_MAX_LEVELS = 32
 DEM_MAX_CHILDREN = 16
 DEM_SCRATCH_BYTES = 64 << 20
@@ -89,7 +90,7 @@ class Params(C.Structure):
 class Contacts(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("pi", C.c_void_p), ("pj", C.c_void_p), ("ti", C.c_void_p),
                 ("tj", C.c_void_p), ("d", C.c_void_p), ("x", C.c_void_p), ("n", C.c_void_p),
-                ("count", C.c_void_p)]
+                ("count", C.c_void_p), ("adjoint", C.c_void_p)]
 
 
 class Stats(C.Structure):

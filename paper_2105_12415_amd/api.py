@@ -266,13 +266,16 @@ class ContactBuffers:
     x: torch.Tensor
     n: torch.Tensor
     count: torch.Tensor
+    adjoint: Optional[torch.Tensor] = None  # [DEM_ADJOINT_ROWS, capacity]: read by the backward
 
     @staticmethod
-    def alloc(capacity: int, dtype, device) -> "ContactBuffers":
-        cap = max(1, int(capacity))
+    def alloc(capacity: int, dtype, device, adjoint: bool = True) -> "ContactBuffers":
+        # a multiple of 4: the backward then reads four contacts' rows per 16-byte load
+        cap = max(4, (int(capacity) + 3) // 4 * 4)
         z = lambda *s, dt=torch.int32: torch.zeros(*s, dtype=dt, device=device)
         return ContactBuffers(cap, z(cap), z(cap), z(cap), z(cap), z(cap, dt=dtype), z(3, cap, dt=dtype),
-                              z(3, cap, dt=dtype), z(1))
+                              z(3, cap, dt=dtype), z(1),
+                              z(_abi.DEM_ADJOINT_ROWS, cap, dt=dtype) if adjoint else None)
 
     def c(self) -> _abi.Contacts:
         s = _abi.Contacts()
@@ -280,6 +283,7 @@ class ContactBuffers:
         s.pi, s.pj, s.ti, s.tj = (t.data_ptr() for t in (self.pi, self.pj, self.ti, self.tj))
         s.d, s.x, s.n = self.d.data_ptr(), self.x.data_ptr(), self.n.data_ptr()
         s.count = self.count.data_ptr()
+        s.adjoint = self.adjoint.data_ptr() if self.adjoint is not None else None
         return s
 
 
@@ -312,12 +316,16 @@ class ContactEngine:
     ``deterministic`` dem_sort_contacts after it (contacts in (ti, tj) order);
     ``backward()`` dem_contact_backward.  Neither synchronises, so a step can
     be captured in a CUDA/HIP graph; ``check()`` synchronises and raises on
-    device-reported overflow.
+    device-reported overflow.  With ``adjoint`` (default) the contacts carry
+    their adjoint rows, and the backward reads them instead of solving each
+    pair's closest points again.
     """
 
     def __init__(self, ds: DeviceScene, params: Optional[_abi.Params] = None,
-                 contact_capacity: Optional[int] = None, energy_k: float = 1e4, deterministic: bool = False):
+                 contact_capacity: Optional[int] = None, energy_k: float = 1e4, deterministic: bool = False,
+                 adjoint: bool = True):
         self.ds = ds
+        self.adjoint = adjoint
         self.deterministic = deterministic
         self.sorter = None
         self.p = params if params is not None else make_params("hier")
@@ -334,7 +342,7 @@ class ContactEngine:
             a, b = F[ds.pairs_host[:, 0]], F[ds.pairs_host[:, 1]]
             tiles = int(np.sum(((a + ti - 1) // ti) * ((b + tj - 1) // tj)))
             self.p.queue_capacity = max(int(self.p.queue_capacity), 2 * tiles + 8 * 64)
-        self.contacts = ContactBuffers.alloc(contact_capacity, ds.dtype, dev)
+        self.contacts = ContactBuffers.alloc(contact_capacity, ds.dtype, dev, adjoint=adjoint)
         self.stats = torch.zeros(_abi.STATS_WORDS, dtype=torch.int64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.energy = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -416,7 +424,7 @@ class ContactEngine:
             ctr = self.counters()
             if status & _abi.DEM_DEV_CONTACT_OVERFLOW:
                 self.contacts = ContactBuffers.alloc(int(self.count() * 1.25) + 1024, self.ds.dtype,
-                                                     self.ds.device)
+                                                     self.ds.device, adjoint=self.adjoint)
             grow = False
             # lists are split into 8 segments: size for the fullest one
             if status & _abi.DEM_DEV_QUEUE_OVERFLOW:
@@ -466,8 +474,9 @@ class FrontierEngine:
 
     def __init__(self, ds: DeviceScene, params: Optional[_abi.Params] = None,
                  capacity: Optional[int] = None, memory_capacity: Optional[int] = None,
-                 contact_capacity: Optional[int] = None, energy_k: float = 1e4):
+                 contact_capacity: Optional[int] = None, energy_k: float = 1e4, adjoint: bool = True):
         self.ds = ds
+        self.adjoint = adjoint
         self.p = params if params is not None else make_params("hier")
         self.p.energy_k = float(energy_k)
         dev = ds.device
@@ -482,7 +491,7 @@ class FrontierEngine:
         self._alloc_leaves(cap)
         if contact_capacity is None:
             contact_capacity = max(1 << 16, 64 * ds.n_pairs)
-        self.contacts = ContactBuffers.alloc(contact_capacity, ds.dtype, dev)
+        self.contacts = ContactBuffers.alloc(contact_capacity, ds.dtype, dev, adjoint=adjoint)
         self.stats = torch.zeros(_abi.STATS_WORDS, dtype=torch.int64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.energy = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -578,7 +587,8 @@ class FrontierEngine:
             if not status & over:
                 return status
             if status & _abi.DEM_DEV_CONTACT_OVERFLOW:
-                self.contacts = ContactBuffers.alloc(int(self.count() * 1.25) + 1024, self.ds.dtype, self.ds.device)
+                self.contacts = ContactBuffers.alloc(int(self.count() * 1.25) + 1024, self.ds.dtype, self.ds.device,
+                                                     adjoint=self.adjoint)
             if status & _abi.DEM_DEV_NEAR_OVERFLOW:
                 self.p.near_capacity = 2 * int(self.p.near_capacity)
             if status & _abi.DEM_DEV_FRONTIER_OVERFLOW:

@@ -289,12 +289,39 @@ template <typename T>
 DEM_HD T tri_size(V3<T> e1, V3<T> e2) { return absmax3(e1) + absmax3(e2); }
 
 // ------------------------------------------------------------------ exact
+// Barycentric weights of a point of a triangle in compact form (stored per
+// contact for the adjoint): code 0 = an interior point, weights
+// (1 - a - b, a, b); codes 1..4 = a point of the segment between two
+// vertices with weight a at its second end: 1 = v0->v1, 2 = v1->v2,
+// 3 = v2->v0, 4 = v0->v2 (a = 0 is the segment's first vertex).  Every
+// producer of weights below forms them through bary_weights(), so a stored
+// code reproduces its weights bit for bit.
+template <typename T>
+struct BaryCode {
+  int code;
+  T a, b;
+};
+
+template <typename T>
+DEM_HD void bary_weights(int code, T a, T b, T w[3]) {
+  const T c = T(1) - a;
+  w[0] = code == 0 ? c - b : ((code == 1 || code == 4) ? c : (code == 3 ? a : T(0)));
+  w[1] = (code == 0 || code == 1) ? a : (code == 2 ? c : T(0));
+  w[2] = code == 0 ? b : ((code == 2 || code == 4) ? a : (code == 3 ? c : T(0)));
+}
+
+template <typename T>
+DEM_HD void bary_weights(const BaryCode<T>& k, T w[3]) {
+  bary_weights(k.code, k.a, k.b, w);
+}
+
 template <typename T>
 struct Closest {
   T d2;         // squared distance
   V3<T> p, q;   // closest points on A and on B
   T wp[3], wq[3];
   int feature;  // 0-5 vertex-triangle, 6-14 edge-edge, 15 crossing
+  BaryCode<T> cp, cq;  // wp = bary_weights(cp), wq = bary_weights(cq)
 };
 
 // Closest point of triangle (a, a+e1, a+e2) to x.  The projection onto the
@@ -305,7 +332,7 @@ struct Closest {
 // projection falls outside, the closest point lies on one of the edges, each
 // a clamped 1-D projection.  Returns the squared distance.
 template <typename T>
-DEM_HD T point_tri(V3<T> x, V3<T> a, V3<T> e1, V3<T> e2, V3<T>& q, T w[3]) {
+DEM_HD T point_tri(V3<T> x, V3<T> a, V3<T> e1, V3<T> e2, V3<T>& q, T w[3], BaryCode<T>& k) {
   V3<T> r = x - a;
   V3<T> n = cross(e1, e2);
   T nn = dot(n, n);
@@ -329,18 +356,26 @@ DEM_HD T point_tri(V3<T> x, V3<T> a, V3<T> e1, V3<T> e2, V3<T>& q, T w[3]) {
   // best edge (first minimum in edge order)
   T best = n0;
   V3<T> qb = q0;
-  T wa = T(1) - s0, wb = s0, wc = T(0);
-  if (n1 < best) { best = n1; qb = q1; wa = T(0); wb = T(1) - s1; wc = s1; }
-  if (n2 < best) { best = n2; qb = q2; wa = T(1) - s2; wb = T(0); wc = s2; }
+  int code = 1;
+  T ka = s0, kb = T(0);
+  if (n1 < best) { best = n1; qb = q1; code = 2; ka = s1; }
+  if (n2 < best) { best = n2; qb = q2; code = 4; ka = s2; }
   T din = hn * hn * inn;
   if (inside && din <= best) {
     best = din;
     qb = fma3(-hn * inn, n, x);
-    wa = T(1) - s - t; wb = s; wc = t;
+    code = 0; ka = s; kb = t;
   }
   q = qb;
-  w[0] = wa; w[1] = wb; w[2] = wc;
+  k.code = code; k.a = ka; k.b = kb;
+  bary_weights(k, w);
   return best;
+}
+
+template <typename T>
+DEM_HD T point_tri(V3<T> x, V3<T> a, V3<T> e1, V3<T> e2, V3<T>& q, T w[3]) {
+  BaryCode<T> k;
+  return point_tri(x, a, e1, e2, q, w, k);
 }
 
 // Closest points of segments p0 + s d1 and q0 + t d2, s, t in [0, 1]:
@@ -483,7 +518,6 @@ DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T
   }
   // closest points and weights of the winning feature
   V3<T> bp, bq;
-  T wp[3], wq[3];
   if (feat < 6) {
     const bool fromB = feat >= 3;
     const int k = fromB ? feat - 3 : feat;
@@ -499,23 +533,20 @@ DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T
     const V3<T> y = fma3(-h * rcp_fast(nn), nY, x);
     bp = sel(fromB, y, x);
     bq = sel(fromB, x, y);
-    const T w0 = T(1) - bs - bt;
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      const T bary = v == 0 ? w0 : (v == 1 ? bs : bt);
-      const T unit = T(v == k);
-      wp[v] = fromB ? bary : unit;
-      wq[v] = fromB ? unit : bary;
-    }
+    // the face side interior (bs, bt), the vertex side its vertex k
+    out.cp.code = fromB ? 0 : 1 + k;
+    out.cp.a = fromB ? bs : T(0);
+    out.cp.b = fromB ? bt : T(0);
+    out.cq.code = fromB ? 1 + k : 0;
+    out.cq.a = fromB ? T(0) : bs;
+    out.cq.b = fromB ? T(0) : bt;
   } else {
     const int i = (feat - 6) / 3, j = (feat - 6) - 3 * ((feat - 6) / 3);
     bp = fma3(bs, pick3(i, EA[0], EA[1], EA[2]), pick3(i, A[0], A[1], A[2]));
     bq = fma3(bt, pick3(j, EB[0], EB[1], EB[2]), pick3(j, B[0], B[1], B[2]));
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      wp[v] = v == i ? T(1) - bs : (v == (i + 1) % 3 ? bs : T(0));
-      wq[v] = v == j ? T(1) - bt : (v == (j + 1) % 3 ? bt : T(0));
-    }
+    // edge k runs from vertex k to vertex k + 1 (mod 3): codes 1, 2, 3
+    out.cp = BaryCode<T>{1 + i, bs, T(0)};
+    out.cq = BaryCode<T>{1 + j, bt, T(0)};
   }
   if (hit) {
     best = T(0); bp = xh; bq = xh; feat = 15;
@@ -523,8 +554,8 @@ DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T
   out.d2 = best;
   out.p = bp;
   out.q = bq;
-  out.wp[0] = wp[0]; out.wp[1] = wp[1]; out.wp[2] = wp[2];
-  out.wq[0] = wq[0]; out.wq[1] = wq[1]; out.wq[2] = wq[2];
+  bary_weights(out.cp, out.wp);
+  bary_weights(out.cq, out.wq);
   out.feature = feat;
 }
 
@@ -540,16 +571,17 @@ DEM_HD void exact_tri_tri(V3<T> a0, V3<T> e1, V3<T> e2, V3<T> b0, V3<T> f1, V3<T
 // pair is "not terminated" and needs the comparison-based fallback.
 template <typename T, int N>
 DEM_HD bool certify_pair(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip, T rel_tol,
-                         T abs_tol, T& d, V3<T>& p, V3<T>& q, T wp[3], T wq[3]) {
+                         T abs_tol, T& d, V3<T>& p, V3<T>& q, T wp[3], T wq[3], BaryCode<T>& kp,
+                         BaryCode<T>& kq) {
   T a1, b1, nb1, nb2;  // B's negated parameters are not needed here
   iterate_theta<T, N>(A, B, D0, ip, a1, b1, nb1, nb2);
   const V3<T> z = {T(0), T(0), T(0)};
   const V3<T> b0 = -D0;
   V3<T> p1 = fma3(a1, A.e1, b1 * A.e2);
   V3<T> q1;
-  point_tri(p1, b0, B.e1, B.e2, q1, wq);
-  point_tri(q1, z, A.e1, A.e2, p, wp);
-  T d2 = point_tri(p, b0, B.e1, B.e2, q, wq);
+  point_tri(p1, b0, B.e1, B.e2, q1, wq, kq);
+  point_tri(q1, z, A.e1, A.e2, p, wp, kp);
+  T d2 = point_tri(p, b0, B.e1, B.e2, q, wq, kq);
   T U = sq_(d2);
   V3<T> w = q - p;
   V3<T> u = (U > T(0) ? T(1) / U : T(0)) * w;
@@ -558,6 +590,13 @@ DEM_HD bool certify_pair(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterP
   T Ls = hB - hA;
   d = U;
   return U > abs_tol && (U - Ls) <= rel_tol * U + abs_tol;
+}
+
+template <typename T, int N>
+DEM_HD bool certify_pair(const Tri<T>& A, const Tri<T>& B, V3<T> D0, const IterParams& ip, T rel_tol,
+                         T abs_tol, T& d, V3<T>& p, V3<T>& q, T wp[3], T wq[3]) {
+  BaryCode<T> kp, kq;
+  return certify_pair<T, N>(A, B, D0, ip, rel_tol, abs_tol, d, p, q, wp, wq, kp, kq);
 }
 
 }  // namespace dem

@@ -1036,15 +1036,32 @@ struct NearArgs {
   const int4* fr_buf1;
   const uint32_t* fr_state;
   uint8_t* fr_meta;
+  void* adj;               // contacts' adjoint rows, or null
 };
 
+// A contact staged in LDS: its output fields and its adjoint rows.
 template <typename T>
 struct ContactRec {
   int32_t pi, pj, ti, tj;
   T d, x[3], n[3];
+  T adj[DEM_ADJOINT_ROWS];
 };
 
-constexpr int kStageContacts = 512;
+// 496 FP32 records (80 bytes) keep a block of the exact pass within 40 KB of
+// LDS: four blocks per CU, as many as its registers allow.
+constexpr int kStageContacts = 496;
+
+// Adjoint rows of a settled pair (the layout is described with dem_contacts).
+template <typename T>
+__device__ __forceinline__ void adjoint_rows(T adj[DEM_ADJOINT_ROWS], T delta, T d, V3<T> cp, V3<T> cq,
+                                             const BaryCode<T>& kp, const BaryCode<T>& kq) {
+  const V3<T> u = d > T(0) ? (T(1) / d) * (cq - cp) : V3<T>{T(0), T(0), T(0)};
+  adj[0] = delta;
+  adj[1] = u.x; adj[2] = u.y; adj[3] = u.z;
+  adj[4] = T(kp.code + 8 * kq.code);
+  adj[5] = kp.a; adj[6] = kp.b;
+  adj[7] = kq.a; adj[8] = kq.b;
+}
 
 template <typename T>
 __device__ __forceinline__ void write_contacts(LdsQueue<ContactRec<T>, kStageContacts>& qc,
@@ -1052,6 +1069,7 @@ __device__ __forceinline__ void write_contacts(LdsQueue<ContactRec<T>, kStageCon
   T* dd = static_cast<T*>(a.d);
   T* xx = static_cast<T*>(a.x);
   T* nn = static_cast<T*>(a.n);
+  T* aj = static_cast<T*>(a.adj);
   if (threadIdx.x == 0) qc.gbase = qc.n ? atomicAdd(a.count, qc.n) : 0u;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < qc.n; k += blockDim.x) {
@@ -1062,6 +1080,10 @@ __device__ __forceinline__ void write_contacts(LdsQueue<ContactRec<T>, kStageCon
       dd[slot] = r.d;
       xx[slot] = r.x[0]; xx[a.ccap + slot] = r.x[1]; xx[2 * a.ccap + slot] = r.x[2];
       nn[slot] = r.n[0]; nn[a.ccap + slot] = r.n[1]; nn[2 * a.ccap + slot] = r.n[2];
+      if (aj) {
+#pragma unroll
+        for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) aj[q * a.ccap + slot] = r.adj[q];
+      }
     } else {
       atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
     }
@@ -1090,8 +1112,10 @@ struct CertTol<double> {
 // Otherwise: the exact comparison-based distance for every listed pair.
 // FR: entries are frontier leaf indices (see k_fr_eval); the leaf's outcome
 // becomes "contact" or "no contact".
+// (FP32: at most 128 VGPRs, four waves per SIMD, which the staging LDS
+// also allows)
 template <typename T, int N, bool CERTIFY, bool FR>
-__global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
   __shared__ LdsQueue<ContactRec<T>, kStageContacts> qc;
   __shared__ LdsQueue<int2, kStageNear> qf;
   __shared__ SegView view;
@@ -1126,11 +1150,12 @@ __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ sou
       V3<T> D0 = A.v0 - B.v0;
       T d;
       V3<T> cp, cq;
+      BaryCode<T> kp, kq;
       bool settled = true;
       if constexpr (CERTIFY) {
         T wp[3], wq[3];
         settled = certify_pair<T, N>(A, B, D0, a.ip, CertTol<T>::rel, CertTol<T>::abs * (A.size + B.size),
-                                     d, cp, cq, wp, wq);
+                                     d, cp, cq, wp, wq, kp, kq);
         my_cert += settled;
         defer = !settled;
       } else {
@@ -1140,6 +1165,8 @@ __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ sou
         d = sq_(c.d2);
         cp = c.p;
         cq = c.q;
+        kp = c.cp;
+        kq = c.cq;
       }
       if (settled) {
         T delta = a.dense ? T(INFINITY) : A.eps + B.eps;
@@ -1155,6 +1182,7 @@ __global__ void __launch_bounds__(256) k_near(const SoupRec<T>* __restrict__ sou
         if constexpr (FR) a.fr_meta[4 * (size_t)pr.x] = (uint8_t)(emit ? kOutKeep : kOutPrune);
         rec.x[0] = xc.x; rec.x[1] = xc.y; rec.x[2] = xc.z;
         rec.n[0] = nc.x; rec.n[1] = nc.y; rec.n[2] = nc.z;
+        adjoint_rows(rec.adj, A.eps + B.eps, d, cp, cq, kp, kq);
         if (emit && !a.dense) {
           double pen = (double)delta - (double)d;
           e_acc += a.k * pen * pen;
@@ -1249,8 +1277,13 @@ __device__ __forceinline__ void hash_add_tri(GradHash<T>& H, const int32_t* __re
   for (int v = 0; v < 3; ++v) {
     const bool nz = gv[v].x != T(0) || gv[v].y != T(0) || gv[v].z != T(0);
     slot[v] = (int)(((uint32_t)vid[v] * 2654435761u) >> (32 - kHashBits));
-    cur[v] = nz ? atomicCAS(&H.key[slot[v]], -1, vid[v]) : -2;
+    // a plain read first: most vertices of a chunk are already in the table,
+    // and only an empty slot needs the compare-and-swap
+    cur[v] = nz ? H.key[slot[v]] : -2;
   }
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+    if (cur[v] == -1) cur[v] = atomicCAS(&H.key[slot[v]], -1, vid[v]);
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     if (cur[v] == -2) continue;
@@ -1264,15 +1297,37 @@ __device__ __forceinline__ void hash_add_tri(GradHash<T>& H, const int32_t* __re
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__ soup,
+// Four consecutive values with 16-byte loads (p 16-byte aligned).
+__device__ __forceinline__ void ld4(const int32_t* p, int32_t o[4]) {
+  const int4 v = *reinterpret_cast<const int4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const float* p, float o[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const double* p, double o[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+
+// ADJ: d from the contacts and delta, u and the weights from their adjoint
+// rows (no triangle data read); with VEC (rows 16-byte aligned, capacity a
+// multiple of 4, so the four entries from a multiple of 4 below the count
+// are inside the arrays) a thread reads its four contacts' fields with one
+// 16-byte load per row.  Otherwise the pair's closest points are solved
+// again from the soup records.
+template <typename T, bool ADJ, bool VEC>
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_backward(const SoupRec<T>* __restrict__ soup,
                                                   const int32_t* __restrict__ tv, int n_tris,
                                                   int n_verts, const int32_t* __restrict__ cti,
-                                                  const int32_t* __restrict__ ctj,
+                                                  const int32_t* __restrict__ ctj, const T* __restrict__ cd,
+                                                  const T* __restrict__ adj,
                                                   const uint32_t* __restrict__ ccount, int64_t ccap,
                                                   double k, const double* __restrict__ grad_E,
                                                   T* __restrict__ grad, double* energy,
                                                   uint32_t* status) {
+  static_assert(kBwdPerThread == 4, "the vector reads take four contacts");
   __shared__ GradHash<T> H;
   const uint32_t cnt = min((uint64_t)*ccount, (uint64_t)ccap);
   const double gE = grad_E ? *grad_E : 1.0;
@@ -1288,28 +1343,67 @@ __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__
     const uint32_t cb = c0 + threadIdx.x * kBwdPerThread;
     int run = -1;      // t_i of the current run
     V3<T> rg[3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // its vertex contributions so far
+    int pti[kBwdPerThread], ptj[kBwdPerThread];
+    T pd[kBwdPerThread], pa[DEM_ADJOINT_ROWS][kBwdPerThread];
+    if constexpr (ADJ) {
+      const size_t C = (size_t)ccap;
+      if constexpr (VEC) {
+        ld4(cti + cb, pti);
+        ld4(ctj + cb, ptj);
+        ld4(cd + cb, pd);
+#pragma unroll
+        for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) ld4(adj + q * C + cb, pa[q]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kBwdPerThread; ++j) {
+          const uint32_t c = min(cb + j, cnt - 1);  // (entries past cnt are not used)
+          pti[j] = cti[c];
+          ptj[j] = ctj[c];
+          pd[j] = cd[c];
+#pragma unroll
+          for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) pa[q][j] = adj[q * C + c];
+        }
+      }
+    }
+#pragma unroll
     for (int j = 0; j < kBwdPerThread; ++j) {
       const uint32_t c = cb + j;
-      if (c >= cnt) break;
-      const int ti = cti[c], tj = ctj[c];
+      if (c >= cnt) continue;
+      const int ti = ADJ ? pti[j] : cti[c], tj = ADJ ? ptj[j] : ctj[c];
       if ((uint32_t)ti >= (uint32_t)n_tris || (uint32_t)tj >= (uint32_t)n_tris) {
         atomicOr(status, DEM_DEV_BAD_TREE);  // not a triangle of this scene: skipped
         continue;
       }
-      int cbi, cci, pi_, cbj, ccj, pj_;
-      Tri<T> A = load_tri(soup, ti, cbi, cci, pi_);
-      Tri<T> B = load_tri(soup, tj, cbj, ccj, pj_);
-      V3<T> D0 = A.v0 - B.v0;
-      Closest<T> cl;
-      exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, cl);
-      T d = sq_(cl.d2);
-      T delta = A.eps + B.eps;
+      T d, delta, wp[3], wq[3];
+      V3<T> u;
+      if constexpr (ADJ) {
+        d = pd[j];
+        delta = pa[0][j];
+        u = V3<T>{pa[1][j], pa[2][j], pa[3][j]};
+        const int code = (int)pa[4][j];
+        bary_weights(code & 7, pa[5][j], pa[6][j], wp);
+        bary_weights(code >> 3, pa[7][j], pa[8][j], wq);
+      } else {
+        int cbi, cci, pi_, cbj, ccj, pj_;
+        Tri<T> A = load_tri(soup, ti, cbi, cci, pi_);
+        Tri<T> B = load_tri(soup, tj, cbj, ccj, pj_);
+        V3<T> D0 = A.v0 - B.v0;
+        Closest<T> cl;
+        exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, cl);
+        d = sq_(cl.d2);
+        delta = A.eps + B.eps;
+        u = d > T(0) ? (T(1) / d) * (cl.q - cl.p) : V3<T>{T(0), T(0), T(0)};
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          wp[v] = cl.wp[v];
+          wq[v] = cl.wq[v];
+        }
+      }
       double pen = (double)delta - (double)d;
       if (!(pen >= 0.0)) continue;
       e_acc += k * pen * pen;
       if (!(d > T(0)) || grad == nullptr) continue;
       T g = T(2.0 * k * pen * gE);
-      V3<T> u = (T(1) / d) * (cl.q - cl.p);
       if (ti != run) {
         if (run >= 0) hash_add_tri(H, tv, n_tris, run, rg, grad, n_verts);
         run = ti;
@@ -1319,8 +1413,8 @@ __global__ void __launch_bounds__(256) k_backward(const SoupRec<T>* __restrict__
       V3<T> gq[3];
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        rg[v] = rg[v] + (g * cl.wp[v]) * u;
-        gq[v] = (-g * cl.wq[v]) * u;
+        rg[v] = rg[v] + (g * wp[v]) * u;
+        gq[v] = (-g * wq[v]) * u;
       }
       hash_add_tri(H, tv, n_tris, tj, gq, grad, n_verts);
     }
@@ -2823,6 +2917,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   na.fb_tail = ctr->fb_tail;
   na.pi = out->pi; na.pj = out->pj; na.ti = out->ti; na.tj = out->tj;
   na.d = out->d; na.x = out->x; na.n = out->n;
+  na.adj = out->adjoint;
   na.count = out->count;
   na.ccap = out->capacity;
   na.dense = p.dense_distance;
@@ -2954,6 +3049,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   na.fb_tail = ctr->fb_tail;
   na.pi = out->pi; na.pj = out->pj; na.ti = out->ti; na.tj = out->tj;
   na.d = out->d; na.x = out->x; na.n = out->n;
+  na.adj = out->adjoint;
   na.count = out->count;
   na.ccap = out->capacity;
   na.dense = 0;
@@ -3109,6 +3205,7 @@ struct SortArgs {
   void* d;
   void* x;
   void* n;
+  void* adj;                  // adjoint rows or null
   const uint32_t* count;
   int64_t cap;
   uint32_t n_buckets;         // n_tris + 1 (the last one: invalid triangle numbers)
@@ -3369,6 +3466,36 @@ __global__ void k_cs_write(SortArgs a) {
   }
 }
 
+// The adjoint rows move in a second pass through the same staging buffer
+// (DEM_ADJOINT_ROWS values of the scene's precision per contact fit in a
+// SortRec<double>).
+static_assert(DEM_ADJOINT_ROWS * sizeof(double) <= sizeof(SortRec<double>), "adjoint rows exceed the staging record");
+
+template <typename T>
+__global__ void k_cs_gather_adj(SortArgs a) {
+  const uint32_t cnt = cs_count(a);
+  const T* adj = static_cast<const T*>(a.adj);
+  T* out = reinterpret_cast<T*>(a.tmp);
+  const size_t C = (size_t)a.cap;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+    const int32_t c = a.idx[k];
+#pragma unroll
+    for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) out[(size_t)k * DEM_ADJOINT_ROWS + q] = adj[q * C + c];
+  }
+}
+
+template <typename T>
+__global__ void k_cs_write_adj(SortArgs a) {
+  const uint32_t cnt = cs_count(a);
+  T* adj = static_cast<T*>(a.adj);
+  const T* in = reinterpret_cast<const T*>(a.tmp);
+  const size_t C = (size_t)a.cap;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) adj[q * C + k] = in[(size_t)k * DEM_ADJOINT_ROWS + q];
+  }
+}
+
 SortLayout sort_layout(int32_t n_tris, int64_t cap) {
   SortLayout L;
   L.n_buckets = (uint32_t)n_tris + 1;
@@ -3392,6 +3519,7 @@ dem_status run_sort(const dem_contacts* c, int32_t n_tris, void* ws, const SortL
   SortArgs a;
   a.pi = c->pi; a.pj = c->pj; a.ti = c->ti; a.tj = c->tj;
   a.d = c->d; a.x = c->x; a.n = c->n;
+  a.adj = c->adjoint;
   a.count = c->count;
   a.cap = c->capacity;
   a.n_buckets = L.n_buckets;
@@ -3415,6 +3543,10 @@ dem_status run_sort(const dem_contacts* c, int32_t n_tris, void* ws, const SortL
   hipLaunchKernelGGL(k_cs_bucket, dim3(4096), b, 0, st, a);
   hipLaunchKernelGGL(k_cs_gather<T>, g, b, 0, st, a);
   hipLaunchKernelGGL(k_cs_write<T>, g, b, 0, st, a);
+  if (a.adj) {
+    hipLaunchKernelGGL(k_cs_gather_adj<T>, g, b, 0, st, a);
+    hipLaunchKernelGGL(k_cs_write_adj<T>, g, b, 0, st, a);
+  }
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
 
@@ -3468,6 +3600,27 @@ dem_status find_dispatch(const dem_scene* scene, const int32_t* pairs, int32_t n
   if (scene->precision == DEM_F64)
     return run_find<double>(scene, pairs, n_pairs, p, out, ws, L, dev_stats, dev_status, dev_energy, st);
   return run_find<float>(scene, pairs, n_pairs, p, out, ws, L, dev_stats, dev_status, dev_energy, st);
+}
+
+template <typename T>
+void launch_backward(int grid, hipStream_t st, const SoupRec<T>* soup, const dem_scene* scene, const dem_contacts* c,
+                     double k, const double* grad_E, T* grad, double* energy, uint32_t* status) {
+  const T* cd = static_cast<const T*>(c->d);
+  const T* adj = static_cast<const T*>(c->adjoint);
+  const auto a16 = [](const void* q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; };
+  const bool vec = c->capacity % 4 == 0 && a16(c->ti) && a16(c->tj) && a16(cd) && a16(adj);
+  if (adj && cd && vec)
+    hipLaunchKernelGGL((k_backward<T, true, true>), dim3(grid), dim3(256), 0, st, soup, scene->tri_verts,
+                       scene->n_tris, scene->n_verts, c->ti, c->tj, cd, adj, c->count, c->capacity, k, grad_E, grad,
+                       energy, status);
+  else if (adj && cd)
+    hipLaunchKernelGGL((k_backward<T, true, false>), dim3(grid), dim3(256), 0, st, soup, scene->tri_verts,
+                       scene->n_tris, scene->n_verts, c->ti, c->tj, cd, adj, c->count, c->capacity, k, grad_E, grad,
+                       energy, status);
+  else
+    hipLaunchKernelGGL((k_backward<T, false, false>), dim3(grid), dim3(256), 0, st, soup, scene->tri_verts,
+                       scene->n_tris, scene->n_verts, c->ti, c->tj, cd, adj, c->count, c->capacity, k, grad_E, grad,
+                       energy, status);
 }
 
 }  // namespace
@@ -3541,26 +3694,26 @@ dem_status dem_contact_backward(const dem_scene* scene, const dem_contacts* c, d
                                 dem_stream_t stream) {
   if (!scene_ok(scene) || !c || !c->count || !c->ti || !c->tj || !dev_status) return DEM_ERR_ARG;
   if (!grad_verts && !energy_out) return DEM_ERR_ARG;
-  if (!(k >= 0.0) || !workspace) return DEM_ERR_ARG;
+  if (!(k >= 0.0)) return DEM_ERR_ARG;
   if (c->capacity < 0 || c->capacity > (int64_t)0xFFFFFFFF) return DEM_ERR_ARG;
+  // with adjoint rows nothing is read from the workspace
+  const bool rows = c->adjoint && c->d;
   WsLayout L = ws_layout(scene->precision, scene->n_tris, 1, 1);
-  if (workspace_bytes < L.qa) return DEM_ERR_CAPACITY;
-  if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
+  if (!rows) {
+    if (!workspace) return DEM_ERR_ARG;
+    if (workspace_bytes < L.qa) return DEM_ERR_CAPACITY;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return DEM_ERR_ARG;
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const char* base = static_cast<const char*>(workspace);
+  const char* base = rows ? nullptr : static_cast<const char*>(workspace);
   if (energy_out) hipLaunchKernelGGL(k_zero_scalar, dim3(1), dim3(64), 0, st, energy_out);
   const int grid = 1024;
-  if (scene->precision == DEM_F64) {
-    hipLaunchKernelGGL(k_backward<double>, dim3(grid), dim3(256), 0, st,
-                       reinterpret_cast<const SoupRec<double>*>(base + L.soup), scene->tri_verts,
-                       scene->n_tris, scene->n_verts, c->ti, c->tj, c->count, c->capacity, k, grad_E,
-                       static_cast<double*>(grad_verts), energy_out, dev_status);
-  } else {
-    hipLaunchKernelGGL(k_backward<float>, dim3(grid), dim3(256), 0, st,
-                       reinterpret_cast<const SoupRec<float>*>(base + L.soup), scene->tri_verts,
-                       scene->n_tris, scene->n_verts, c->ti, c->tj, c->count, c->capacity, k, grad_E,
-                       static_cast<float*>(grad_verts), energy_out, dev_status);
-  }
+  if (scene->precision == DEM_F64)
+    launch_backward<double>(grid, st, rows ? nullptr : reinterpret_cast<const SoupRec<double>*>(base + L.soup), scene, c, k, grad_E,
+                            static_cast<double*>(grad_verts), energy_out, dev_status);
+  else
+    launch_backward<float>(grid, st, rows ? nullptr : reinterpret_cast<const SoupRec<float>*>(base + L.soup), scene, c, k, grad_E,
+                           static_cast<float*>(grad_verts), energy_out, dev_status);
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
 

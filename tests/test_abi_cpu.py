@@ -114,6 +114,15 @@ def test_workspace_bytes_and_validation():
     st = L.dem_contact_backward(C.byref(s), C.byref(out), -1.0, None, C.c_void_p(4096), None,
                                 C.c_void_p(4096), 1 << 20, C.c_void_p(4096), None)
     assert st == _abi.DEM_ERR_ARG
+    # without adjoint rows the backward needs the forward's workspace (soup)
+    out.ti = out.tj = 4096
+    out.adjoint = None
+    st = L.dem_contact_backward(C.byref(s), C.byref(out), 1.0, None, C.c_void_p(4096), None,
+                                None, 0, C.c_void_p(4096), None)
+    assert st == _abi.DEM_ERR_ARG
+    st = L.dem_contact_backward(C.byref(s), C.byref(out), 1.0, None, C.c_void_p(4096), None,
+                                C.c_void_p(4096), 16, C.c_void_p(4096), None)
+    assert st == _abi.DEM_ERR_CAPACITY
 
 
 def test_find_contacts_noalloc_validation():

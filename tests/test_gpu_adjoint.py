@@ -1,0 +1,184 @@
+"""Adjoint rows (dem_contacts.adjoint): what the forward stores per contact
+for the backward -- delta, the unit direction u and the closest points'
+barycentric codes -- against the FP64 oracle's closest points and weights,
+and the backward that reads them against the backward that solves each
+pair again (the same formulas on the same values, so equal up to the order
+of the floating-point accumulation), also after dem_sort_contacts and for
+the persistent active sets."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen as sg
+from paper_2105_12415_amd import _abi, api
+
+from test_gpu_parity import TOL, keyed, oracle_keyed, say
+
+pytestmark = pytest.mark.gpu
+
+
+def decode_weights(code, a, b):
+    """Barycentric weights from a code (the layout documented with
+    dem_contacts), written out here from that description."""
+    c = 1.0 - a
+    if code == 0:
+        return np.array([c - b, a, b])
+    return {1: np.array([c, a, 0.0]), 2: np.array([0.0, c, a]), 3: np.array([a, 0.0, c]),
+            4: np.array([c, 0.0, a])}[code]
+
+
+def host_rows(eng):
+    n = eng.count()
+    adj = eng.contacts.adjoint[:, :n].double().cpu().numpy()
+    return n, adj
+
+
+def _scene(prec):
+    if prec == "f32":
+        return sg.two_spheres(4, [2, 3, 4], "f32", sep=2.03, stream_id=71, name="adj32")
+    return sg.two_spheres(3, [1, 2, 3], "f64", sep=2.03, stream_id=72, name="adj64")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_adjoint_rows_match_oracle(prec):
+    """delta = eps_i + eps_j; u = (p_j - p_i) / d and the weights of p_i, p_j
+    against the oracle's exact closest points, on every contact whose
+    closest points are unique (the oracle's ambiguity flag clear) and whose
+    distance is not tiny against the pair's size."""
+    scene = _scene(prec)
+    tol = TOL[prec]
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params("hier"), energy_k=1e4)
+    assert eng.run() == 0
+    res = eng.result()
+    n, adj = host_rows(eng)
+    assert n > 100
+    fs = oracle.fine_scene(scene)
+    oracle.set_ambiguity_tol(tol["amb"])
+    ref = oracle.find_contacts(fs)
+    ko = oracle_keyed(scene, ref)
+    kg = keyed(ds, res)
+    eps = np.array([p.eps0 for p in scene.particles])
+    checked = 0
+    wtol = 2e-3 if prec == "f32" else 1e-8
+    for key, g in kg.items():
+        if key not in ko:
+            continue
+        r = ko[key]
+        pi, pj = key[0], key[1]
+        assert abs(adj[0, g] - (eps[pi] + eps[pj])) <= 1e-6 * (eps[pi] + eps[pj]) if prec == "f32" else \
+            abs(adj[0, g] - (eps[pi] + eps[pj])) <= 1e-14 * (eps[pi] + eps[pj])
+        d = ref["d"][r]
+        h = max(np.ptp(fs.verts[fs.tris[fs.tri_begin[pi] + key[2]]], axis=0).max(),
+                np.ptp(fs.verts[fs.tris[fs.tri_begin[pj] + key[3]]], axis=0).max())
+        if ref["ambiguous"][r] or d < 1e-2 * h:
+            continue
+        u_ref = (ref["p2"][r] - ref["p1"][r]) / d
+        assert np.abs(adj[1:4, g] - u_ref).max() <= (1e-3 if prec == "f32" else 1e-9), key
+        code = int(adj[4, g])
+        wi = decode_weights(code & 7, adj[5, g], adj[6, g])
+        wj = decode_weights(code >> 3, adj[7, g], adj[8, g])
+        assert np.abs(wi - ref["w1"][r]).max() <= wtol, (key, wi, ref["w1"][r])
+        assert np.abs(wj - ref["w2"][r]).max() <= wtol, (key, wj, ref["w2"][r])
+        checked += 1
+    say(f"[gpu-test] adjoint rows: {checked} of {n} contacts checked against the oracle")
+    assert checked > 0.5 * n
+
+
+def _grad(eng, contacts=None):
+    ds = eng.ds
+    g = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device="cuda:0")
+    full = eng.contacts
+    if contacts is not None:
+        eng.contacts = contacts
+    try:
+        eng.backward(g, energy=True)
+        torch.cuda.synchronize()
+    finally:
+        eng.contacts = full
+    assert eng.check() == 0
+    return g.double().cpu().numpy(), float(eng.energy_bwd.item())
+
+
+def _without_adjoint(cb):
+    return api.ContactBuffers(cb.capacity, cb.pi, cb.pj, cb.ti, cb.tj, cb.d, cb.x, cb.n, cb.count, None)
+
+
+@pytest.mark.parametrize("prec,certify", [("f32", 0), ("f64", 0), ("f32", 1)])
+def test_backward_from_rows_equals_fresh_solve(prec, certify):
+    """The backward from the stored rows and the backward that solves every
+    pair again give the same gradient and energy (exact path: the same
+    values summed in another order; certified path: the stored closest
+    points are the certificate's, the fresh solve's the exact ones, within
+    the certificate's tolerance)."""
+    scene = _scene(prec)
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params("hier", certify=certify), energy_k=1e4)
+    assert eng.run() == 0
+    g_rows, e_rows = _grad(eng)
+    g_solve, e_solve = _grad(eng, _without_adjoint(eng.contacts))
+    gmax = np.abs(g_solve).max()
+    assert gmax > 0
+    rtol = (1e-5 if certify else 1e-6) if prec == "f32" else 1e-12
+    err = np.abs(g_rows - g_solve).max() / gmax
+    say(f"[gpu-test] rows vs fresh solve: max gradient difference {err:.3g} of the largest")
+    assert err <= rtol
+    assert abs(e_rows - e_solve) <= rtol * e_solve
+
+
+def test_shuffled_contacts_with_their_rows():
+    """A shuffled contact list with its rows shuffled alike gives the whole
+    list's gradient: each contact's rows are read at its own index."""
+    scene = _scene("f32")
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params("hier"), energy_k=1e4)
+    assert eng.run() == 0
+    n = eng.count()
+    g0, e0 = _grad(eng)
+    cb = eng.contacts
+    perm = torch.as_tensor(np.random.default_rng(9).permutation(n), device="cuda:0")
+    sh = api.ContactBuffers(n, cb.pi[:n][perm].contiguous(), cb.pj[:n][perm].contiguous(),
+                            cb.ti[:n][perm].contiguous(), cb.tj[:n][perm].contiguous(), cb.d[:n][perm].contiguous(),
+                            cb.x[:, :n][:, perm].contiguous(), cb.n[:, :n][:, perm].contiguous(),
+                            torch.tensor([n], dtype=torch.int32, device="cuda:0"),
+                            cb.adjoint[:, :n][:, perm].contiguous())
+    g1, e1 = _grad(eng, sh)
+    gmax = np.abs(g0).max()
+    assert np.abs(g1 - g0).max() <= 1e-5 * gmax
+    assert abs(e1 - e0) <= 1e-5 * e0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_sorted_contacts_keep_their_rows(prec):
+    """dem_sort_contacts moves the rows with their contacts: after the sort
+    the backward from the rows equals the fresh solve on the sorted list."""
+    scene = _scene(prec)
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params("hier"), energy_k=1e4, deterministic=True)
+    assert eng.run() == 0
+    res = eng.result()
+    assert np.all(np.diff(res["ti"].astype(np.int64) * (1 << 32) + res["tj"]) > 0)
+    g_rows, e_rows = _grad(eng)
+    g_solve, e_solve = _grad(eng, _without_adjoint(eng.contacts))
+    gmax = np.abs(g_solve).max()
+    rtol = 1e-6 if prec == "f32" else 1e-12
+    assert np.abs(g_rows - g_solve).max() <= rtol * gmax
+    assert abs(e_rows - e_solve) <= rtol * e_solve
+
+
+def test_frontier_contacts_carry_rows():
+    """The persistent active sets' exact pass writes the rows too."""
+    scene = _scene("f32")
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.FrontierEngine(ds, api.make_params("hier"), energy_k=1e4)
+    eng.init()
+    for _ in range(6):
+        eng.step()
+    assert eng.check() == 0
+    g_rows, e_rows = _grad(eng)
+    g_solve, e_solve = _grad(eng, _without_adjoint(eng.contacts))
+    gmax = np.abs(g_solve).max()
+    assert gmax > 0
+    assert np.abs(g_rows - g_solve).max() <= 1e-6 * gmax
+    assert abs(e_rows - e_solve) <= 1e-6 * e_solve

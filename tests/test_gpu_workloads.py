@@ -122,6 +122,7 @@ def _grad_restricted(eng, ds, res_sel, k):
     idx = torch.as_tensor(res_sel, dtype=torch.int64, device=ds.device)
     for name in ("pi", "pj", "ti", "tj", "d"):
         getattr(cb, name)[:n] = getattr(c, name)[idx]
+    cb.adjoint[:, :n] = c.adjoint[:, idx]
     cb.count.fill_(n)
     keep = eng.contacts
     eng.contacts = cb

@@ -72,6 +72,19 @@ def run_both(scene):
     assert abs(float(energy.item()) - e_ref) <= 1e-12 * abs(e_ref) + 1e-300
     s_got, s_ref = api._stats_dict(stats), eng.stats_dict()
     assert s_got["contacts"] == s_ref["contacts"] and s_got["near"] == s_ref["near"]
+    # the gradient of the no-allocation call's contacts through their adjoint
+    # rows, with no workspace at all, against the workspace call's
+    g_ref = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device=ds.device)
+    eng.backward(g_ref)
+    g = torch.zeros_like(g_ref)
+    st = L.dem_contact_backward(C.byref(ds.c), C.byref(cs), float(p.energy_k), None, C.c_void_p(g.data_ptr()),
+                                None, None, 0, C.c_void_p(status.data_ptr()), stream())
+    _abi.check(st, "dem_contact_backward")
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0, hex(int(status.item()) & 0xFFFFFFFF)
+    gm = float(g_ref.abs().max())
+    assert gm > 0
+    assert float((g - g_ref).abs().max()) <= (1e-5 if ds.dtype == torch.float32 else 1e-12) * gm
     return len(got["ti"])
 
 
