@@ -51,6 +51,22 @@ def flops_per_eval(n_iter: int) -> int:
     return 74 * n_iter - 24 + 84
 
 
+def exact_pair_flops() -> int:
+    """Algorithmic floating-point operations of the exact comparison-based
+    distance of one triangle pair and its contact emission (same convention
+    as flops_per_eval; a dot product 5, a cross product 9, a 3-vector add 3,
+    an FMA on 3-vectors 6): vertices and edges of both triangles 18; normals
+    and their squared lengths 28; heights of each triangle's vertices over
+    the other's plane 48; the six edge-through-triangle crossing tests
+    2 x 157 (three in-plane edge normals 27, per edge the straddle tests 6,
+    the plane point 10, three inside tests 27); the six vertex-interior
+    candidates 2 x 89 (reciprocal and in-plane gradients 20, per vertex 23);
+    squared edge lengths and reciprocals 42; nine segment-segment distances
+    with the running minimum 9 x 85; the winner's closest points 30; weights
+    4; the square root 1; contact point, normal and adjoint rows 24."""
+    return 18 + 28 + 48 + 2 * 157 + 2 * 89 + 42 + 9 * 85 + 30 + 4 + 1 + 24
+
+
 FLATTEN_BYTES_PER_TRI = 12 + 16 + 64  # indices, per-triangle static data, soup record
 FLATTEN_BYTES_SKIPPED = 8             # child count and particle of a triangle left to the lazy pass
 FLATTEN_BYTES_PER_VERT = 12
@@ -72,6 +88,57 @@ WORKLOADS = {
                          "gaps U(0,0.1), full icosphere cascades, FP32; persistent active sets "
                          "(dem_frontier_step, one level of widening / narrowing per step)", True),
 }
+
+
+def step_roofline(ms_step: float, kernels: dict, st: dict, n_pairs: int, n_iter: int, fp64: bool,
+                  flat_bytes: float, touched_verts: int, peaks: dict = None) -> dict:
+    """Every kernel of the step against the roof that binds it, weighted by
+    its time: ALU-bound kernels (the descent, the exact pass) by their
+    algorithmic flops against the VALU peak, memory-bound ones (flatten,
+    seeding, lazy flattening, backward) by their algorithmic HBM bytes
+    against 8 TB/s.  weighted_frac = sum of ms x frac over the step's
+    milliseconds (time outside these kernels counts as 0).  Per-unit
+    figures: flatten as reported in ``kernels``; seeding 16 B per root item
+    written + 24 B per candidate pair read; lazy flattening 92 B per record
+    written; the backward 32 + 10 s bytes per contact (its triangle pair
+    8 B, its distance and nine adjoint rows of s-byte values, six vertex ids
+    24 B) + 6 s bytes per distinct vertex touched (gradient read and
+    written)."""
+    sz = 8 if fp64 else 4
+    peak_alu = PEAK_FP64_VALU_TFLOPS if fp64 else PEAK_FP32_VALU_TFLOPS
+    rows = {}
+
+    def add(name, ms, amount, bound):
+        if not ms or ms <= 0 or amount is None:
+            return
+        if bound == "alu":
+            ach = amount / (ms * 1e-3) / 1e12
+            row = {"bound": "alu", "ms": ms, "flops": amount, "achieved": ach, "peak": peak_alu, "unit": "TFLOP/s",
+                   "frac": ach / peak_alu}
+            if peaks:
+                ap = peaks["fp64_fma_peak_tflops" if fp64 else "fp32_fma_peak_tflops"]
+                row.update(achievable_peak=ap, frac_of_achievable=ach / ap)
+        else:
+            ach = amount / (ms * 1e-3) / 1e9
+            row = {"bound": "hbm", "ms": ms, "bytes": amount, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": ach / PEAK_HBM_GBS}
+            if peaks:
+                row.update(achievable_peak=peaks["copy_gbs"], frac_of_achievable=ach / peaks["copy_gbs"])
+        rows[name] = row
+
+    evals = float(np.sum(st["evals"]))
+    add("k_flatten", kernels.get("flatten_ms"), flat_bytes, "hbm")
+    add("k_seed", kernels.get("seed_ms"), 16.0 * float(st["items"][0]) + 24.0 * n_pairs, "hbm")
+    add("k_level", kernels.get("levels_ms"), flops_per_eval(n_iter) * evals, "alu")
+    add("k_fine", kernels.get("fine_flatten_ms"), FLATTEN_BYTES_PER_TRI * float(st.get("fine_records", 0)), "hbm")
+    if not kernels.get("certify_ms"):
+        add("k_near", kernels.get("near_ms"), exact_pair_flops() * float(st["fallback"]), "alu")
+    if kernels.get("backward_ms"):
+        add("k_backward", kernels["backward_ms"], (32 + 10 * sz) * float(st["contacts"]) + 6 * sz * touched_verts,
+            "hbm")
+    weighted = sum(r["ms"] * r["frac"] for r in rows.values()) / ms_step
+    return {"weighted_frac": weighted, "ms_step": ms_step, "ms_in_these_kernels": sum(r["ms"] for r in rows.values()),
+            "kernels": rows}
 
 
 def measure_peaks(torch, log=print) -> dict:
@@ -591,7 +658,13 @@ def forces_cpu_baseline(scene, n_sample: int):
             "seconds": dt}
 
 
-def cpu_baseline(scene, n_sample: int, backward: bool):
+def cpu_baseline(scene, n_sample: int, backward: bool, n_single: int = 12):
+    """The FP64 oracle on a seeded sample of candidate pairs: all host
+    threads, then one thread on a seeded subset of that sample.  ``value``
+    counts the triangle pairs the oracle actually evaluated exactly
+    (``tested``: the pairs its exact bounding-sphere test did not reject),
+    the same kind of unit as the GPU's evaluations; the fine pairs the sample
+    covers (decided, most by the rejection test) are reported beside it."""
     import oracle
     fs = oracle.fine_scene(scene)
     rng = np.random.default_rng(12345)
@@ -599,18 +672,31 @@ def cpu_baseline(scene, n_sample: int, backward: bool):
     idx = np.sort(rng.choice(len(scene.pairs), n, replace=False))
     P = np.asarray(scene.pairs)[idx]
     F = fs.tri_count.astype(np.int64)
-    pairs_fine = int(np.sum(F[P[:, 0]] * F[P[:, 1]]))
+
+    def run(pairs, threads):
+        t0 = time.perf_counter()
+        c = oracle.find_contacts(fs, pairs=pairs, n_threads=threads)
+        if backward:
+            oracle.energy_grad(fs, c, 1e4, pairs=pairs)
+        return c, time.perf_counter() - t0
+
     threads = oracle.default_threads()
-    t0 = time.perf_counter()
-    c = oracle.find_contacts(fs, pairs=P, n_threads=threads)
-    if backward:
-        oracle.energy_grad(fs, c, 1e4, pairs=P)
-    dt = time.perf_counter() - t0
-    return {"value": pairs_fine / dt, "unit": "tri-pair evals/s", "cores": threads, "kind": "oracle",
-            "sample": (f"{n} of {len(scene.pairs)} candidate particle pairs (seeded), {pairs_fine} fine "
-                       f"triangle pairs decided exactly in FP64 (flat all-pairs with exact bounding-sphere "
-                       f"rejection{', plus energy gradient' if backward else ''}) in {dt:.2f} s"),
-            "seconds": dt, "contacts": int(len(c["d"]))}
+    c, dt = run(P, threads)
+    fine = int(np.sum(F[P[:, 0]] * F[P[:, 1]]))
+    sub = P[np.sort(rng.choice(n, min(n_single, n), replace=False))]
+    c1, dt1 = run(sub, 1)
+    fine1 = int(np.sum(F[sub[:, 0]] * F[sub[:, 1]]))
+    what = "exact FP64 triangle-pair distances" + (", plus energy gradient" if backward else "")
+    return {"value": c["tested"] / dt, "unit": "tri-pair evals/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{n} of {len(scene.pairs)} candidate particle pairs (seeded): {fine} fine triangle "
+                       f"pairs decided, {c['tested']} of them evaluated exactly ({what}; the rest rejected by "
+                       f"the exact bounding-sphere test) in {dt:.2f} s on {threads} threads"),
+            "seconds": dt, "tested": int(c["tested"]), "fine_pairs": fine, "fine_pairs_per_s": fine / dt,
+            "contacts": int(len(c["d"])),
+            "single_thread": {"value": c1["tested"] / dt1, "unit": "tri-pair evals/s", "cores": 1,
+                              "sample": f"{len(sub)} of those pairs (seeded): {fine1} fine pairs, "
+                                        f"{c1['tested']} evaluated exactly, in {dt1:.2f} s",
+                              "seconds": dt1, "tested": int(c1["tested"]), "fine_pairs_per_s": fine1 / dt1}}
 
 
 def main():
@@ -743,7 +829,15 @@ def main():
            "stats": {"evals_per_level": [int(x) for x in st["evals"][:L]],
                      "survivors_per_level": [int(x) for x in st["survivors"][:L]],
                      "near": st["near"], "certified": st["certified"], "fallback": st["fallback"],
-                     "contacts": st["contacts"]}}
+                     "contacts": st["contacts"], "fine_records": st.get("fine_records", 0)}}
+    # distinct vertices the backward's gradient touches (last eager step's contacts)
+    touched = 0
+    if backward:
+        nc = eng.count()
+        tvd = ds.tri_verts
+        ti, tj = eng.contacts.ti[:nc].long(), eng.contacts.tj[:nc].long()
+        touched = int(torch.unique(torch.cat([tvd[:, ti].reshape(-1), tvd[:, tj].reshape(-1)])).numel())
+        out["stats"]["backward_vertices"] = touched
     if not args.no_flat:
         del eng, step
         torch.cuda.empty_cache()
@@ -758,6 +852,15 @@ def main():
         out["speedup_vs_flat"] = fms / ms
         log(f"[bench] flat: {fms:.2f} ms/step, {fevals:.4g} evals/step")
         del fe, fstep
+    # achievable peaks of this GPU (after the timed work), then every kernel
+    # of the step against its roof
+    peaks = measure_peaks(torch, log)
+    out["peaks"] = peaks
+    ap = peaks["fp64_fma_peak_tflops" if dtype == "f64" else "fp32_fma_peak_tflops"]
+    roof["achievable_peak"] = ap
+    roof["frac_of_achievable"] = achieved / ap
+    roof["step"] = step_roofline(ms, kernels, st, ds.n_pairs, n_iter, dtype == "f64", flat_bytes, touched, peaks)
+    log(f"[bench] step roofline: time-weighted fraction {roof['step']['weighted_frac']:.3f}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_pairs, backward)

@@ -359,6 +359,7 @@ typedef struct {
   unsigned long long frontier_leaves;    /* active pairs evaluated by dem_frontier_step */
   unsigned long long frontier_unfolded;  /* active pairs replaced by their child pairs (widening) */
   unsigned long long frontier_collapsed; /* child groups replaced by their parent pair (narrowing) */
+  unsigned long long fine_records;       /* triangle records the lazy flattening wrote */
 } dem_stats;
 
 /* Bytes of device workspace dem_find_contacts needs for this scene and

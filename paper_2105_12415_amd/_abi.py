@@ -98,7 +98,7 @@ class Stats(C.Structure):
                 ("near", C.c_uint64), ("certified", C.c_uint64), ("fallback", C.c_uint64),
                 ("contacts", C.c_uint64), ("items", C.c_uint64 * DEM_MAX_LEVELS),
                 ("frontier_leaves", C.c_uint64), ("frontier_unfolded", C.c_uint64),
-                ("frontier_collapsed", C.c_uint64)]
+                ("frontier_collapsed", C.c_uint64), ("fine_records", C.c_uint64)]
 
 
 class Merged(C.Structure):

@@ -460,7 +460,7 @@ def _stats_dict(stats: torch.Tensor) -> dict:
             "near": int(s[2 * L]), "certified": int(s[2 * L + 1]), "fallback": int(s[2 * L + 2]),
             "contacts": int(s[2 * L + 3]), "items": s[2 * L + 4:3 * L + 4].astype(np.int64),
             "frontier_leaves": int(s[3 * L + 4]), "frontier_unfolded": int(s[3 * L + 5]),
-            "frontier_collapsed": int(s[3 * L + 6])}
+            "frontier_collapsed": int(s[3 * L + 6]), "fine_records": int(s[3 * L + 7])}
 
 
 class FrontierEngine:

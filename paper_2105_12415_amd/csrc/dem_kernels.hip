@@ -56,6 +56,7 @@ constexpr int kCountMask = 0xFFFF;
 constexpr int kSeg = 8;
 // XCC (XCD) ids the hardware can report: the low 4 bits of HW_REG_XCC_ID.
 constexpr int kMaxXcc = 16;
+constexpr int kFinePart = 64;
 
 struct Counters {
   uint32_t tail[DEM_MAX_LEVELS + 1][kSeg];  // level queues
@@ -73,6 +74,9 @@ struct Counters {
   uint32_t bar_blocks[kMaxXcc][32];         // blocks resident on each XCC
   uint32_t bar_arrive[kMaxXcc][32];         // block arrivals per XCC, summed over the call's barriers
   uint32_t bar_release[kMaxXcc][32];        // barriers the XCC's last block has released
+  // statistics: records written by the lazy flattening, in kFinePart partial
+  // counts on lines of their own (folded into dem_stats by the exact pass)
+  uint32_t fine_part[kFinePart][32];
 };
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -222,6 +226,7 @@ struct FlatArgs {
   uint8_t* mark;  // lazy mode: per-surrogate "a pair with it survived" flags
   int lazy;
   uint32_t* status;
+  uint32_t* fine_part;  // statistics: Counters::fine_part (or null)
 };
 
 // Soup record of triangle t: world vertices (pose applied), edges, the
@@ -329,6 +334,7 @@ __device__ __forceinline__ void fine_range(const FlatArgs<T>& a, const int32_t* 
   // records leave together, as in k_flatten); further children of a parent
   // with more than kFineLanes are stored directly
   const int64_t total = (int64_t)n * kFineLanes;
+  uint32_t written = 0;  // records of the parents this thread found marked
   for (int64_t base = start * (int64_t)kFlatBlock; base < total; base += (int64_t)stride * kFlatBlock) {
     const int64_t i = base + threadIdx.x;
     int d = -1;
@@ -346,6 +352,7 @@ __device__ __forceinline__ void fine_range(const FlatArgs<T>& a, const int32_t* 
             d = cb + slot;
             sh.stage[threadIdx.x] = flatten_rec(a, d, a.cbeg[d], a.ccnt[d], a.tpart[d]);
           }
+          if (slot == 0) written += (uint32_t)cc;
           for (int c = cb + slot + kFineLanes; c < cb + cc; c += kFineLanes)
             flatten_one(a, c, a.cbeg[c], a.ccnt[c], a.tpart[c]);
         }
@@ -361,6 +368,12 @@ __device__ __forceinline__ void fine_range(const FlatArgs<T>& a, const int32_t* 
       if (dr >= 0) out[(size_t)dr * kChunks + c % kChunks] = src[c];
     }
     __syncthreads();
+  }
+  if (a.fine_part) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) written += __shfl_xor(written, o);
+    if (lane_id() == 0 && written)
+      atomicAdd(&a.fine_part[((blockIdx.x * (kFlatBlock / 64) + threadIdx.x / 64) % kFinePart) * 32], written);
   }
 }
 
@@ -1037,6 +1050,7 @@ struct NearArgs {
   const uint32_t* fr_state;
   uint8_t* fr_meta;
   void* adj;               // contacts' adjoint rows, or null
+  const uint32_t* fine_part;  // lazy flattening's partial counts to fold into stats (or null)
 };
 
 // A contact staged in LDS: its output fields and its adjoint rows.
@@ -1217,6 +1231,11 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_near(const Soup
       if (s0) atomicAdd(&a.stats->fallback, s0);
       if (s1) atomicAdd(&a.stats->contacts, s1);
       if (s2) atomicAdd(&a.stats->certified, s2);
+    }
+    // the lazy flattening's partial counts (its kernels ran before this one)
+    if (a.fine_part && blockIdx.x == 0 && threadIdx.x < kFinePart) {
+      const uint32_t v = a.fine_part[threadIdx.x * 32];
+      if (v) atomicAdd(&a.stats->fine_records, (unsigned long long)v);
     }
   }
 }
@@ -2814,7 +2833,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   mark();
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctr, stats, status, out->count, energy);
   mark();
-  FlatArgs<T> fa;
+  FlatArgs<T> fa{};
   fa.verts = static_cast<const T*>(s->verts);
   fa.n_verts = s->n_verts;
   fa.tv = s->tri_verts;
@@ -2833,6 +2852,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   fa.mark = reinterpret_cast<uint8_t*>(base + L.mark);
   fa.lazy = p.mode == DEM_MODE_HIER && s->fine_parents != nullptr;
   fa.status = status;
+  fa.fine_part = stats ? &ctr->fine_part[0][0] : nullptr;
   hipLaunchKernelGGL(k_flatten<T>, dim3((s->n_tris + kFlatBlock - 1) / kFlatBlock), dim3(kFlatBlock), 0, st, fa);
   mark();
   // per-segment capacities
@@ -2933,6 +2953,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
     na.near_ = na.fb;
     na.near_tail = na.fb_tail;
   }
+  na.fine_part = stats ? &ctr->fine_part[0][0] : nullptr;
   hipLaunchKernelGGL((k_near<T, 0, false, false>), dim3(grid), dim3(p.block), 0, st, soup, na);
   mark();
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
@@ -2994,7 +3015,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   mark();
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ctr, stats, status, out->count, energy);
   mark();
-  FlatArgs<T> fl;
+  FlatArgs<T> fl{};
   fl.verts = static_cast<const T*>(s->verts);
   fl.n_verts = s->n_verts;
   fl.tv = s->tri_verts;

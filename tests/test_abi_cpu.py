@@ -33,7 +33,7 @@ def test_header_symbols_exported():
 
 def test_struct_sizes_match_header_layout():
     # dem_stats: 3 arrays of 32 + 4 scalars + 3 frontier counters, 8 bytes each
-    assert C.sizeof(_abi.Stats) == 8 * (3 * 32 + 4 + 3)
+    assert C.sizeof(_abi.Stats) == 8 * (3 * 32 + 4 + 4)
     p = _abi.default_params()
     assert p.n_iter == 4 and p.mode == _abi.DEM_MODE_HIER and p.omega == 1.0
     assert list(p.level_grid) == [0] * _abi.DEM_MAX_LEVELS and list(p.level_batch) == [0] * _abi.DEM_MAX_LEVELS

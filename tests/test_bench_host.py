@@ -31,3 +31,27 @@ def test_flops_per_eval_counts():
     assert bench.flops_per_eval(4) == 356
     assert bench.flops_per_eval(0) == 84
     assert bench.flops_per_eval(1) == 134
+
+
+def test_exact_pair_flops_count():
+    # set-up 94, crossings 314, vertex-interior 178, edge lengths 42, nine
+    # segment pairs 765, winner 35, emission 24
+    assert bench.exact_pair_flops() == 1452
+
+
+def test_step_roofline_weights_each_kernel_by_time():
+    """Two kernels of a 2 ms step: a descent at half the FP32 VALU peak for
+    1 ms and a backward at a quarter of HBM for 0.5 ms give 0.3125."""
+    import numpy as np
+    peak = bench.PEAK_FP32_VALU_TFLOPS
+    evals = 0.5 * peak * 1e12 * 1e-3 / bench.flops_per_eval(4)
+    contacts = 1000.0
+    per_contact = 32 + 10 * 4
+    bwd_bytes = 0.25 * bench.PEAK_HBM_GBS * 1e9 * 0.5e-3
+    touched = (bwd_bytes - per_contact * contacts) / 24
+    st = {"evals": np.array([evals]), "items": np.array([0.0]), "fallback": 0.0, "contacts": contacts,
+          "fine_records": 0}
+    r = bench.step_roofline(2.0, {"levels_ms": 1.0, "backward_ms": 0.5}, st, 0, 4, False, 0.0, touched)
+    assert abs(r["kernels"]["k_level"]["frac"] - 0.5) < 1e-9
+    assert abs(r["kernels"]["k_backward"]["frac"] - 0.25) < 1e-9
+    assert abs(r["weighted_frac"] - (1.0 * 0.5 + 0.5 * 0.25) / 2.0) < 1e-9

@@ -59,6 +59,8 @@ def test_persistent_matches_per_depth_launches(name):
     n = _same(r0, r1)
     s0, s1 = e0.stats_dict(), e1.stats_dict()
     assert np.array_equal(s0["evals"], s1["evals"]) and s0["near"] == s1["near"]
+    # records the lazy flattening wrote: the same parents survive either way
+    assert s0["fine_records"] == s1["fine_records"] <= ds.n_tris
     assert abs(r0["energy"] - r1["energy"]) <= 1e-12 * abs(r0["energy"]) + 1e-300
     say(f"[gpu-test] {name}: {n} contacts, evals {s1['evals'][:ds.n_levels_max].tolist()}")
     assert n > 50
