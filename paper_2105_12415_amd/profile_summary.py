@@ -99,24 +99,38 @@ def header(title: str, commands):
     return lines
 
 
-def summary_trace(d: str, workload: str, commands):
+def summary_trace(d: str, workload: str, commands, per_depth=None):
+    """Per-kernel statistics; with per_depth = (kernel family, L) also the
+    average duration of that kernel's launches by launch index mod L (one
+    launch per tree depth, in depth order)."""
     stats = read_stats(d)
     lines = header(f"Kernel trace: {workload}", commands)
     lines += ["| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
     for name, calls, avg, mn, mx, pct in stats:
         lines.append(f"| `{name}` | {calls} | {avg:.1f} | {mn:.1f} | {mx:.1f} | {pct:.2f} |")
+    if per_depth:
+        fam, L = per_depth
+        rows = list(csv.DictReader(open(find_csv(d, "kernel_trace.csv"))))
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+                if family(r["Kernel_Name"]) == fam]
+        if durs and len(durs) % L == 0:
+            avg = [sum(durs[k::L]) / len(durs[k::L]) for k in range(L)]
+            lines += ["", f"Per-depth average of `{fam}` (launch d of every step):", "",
+                      "| depth | " + " | ".join(str(k) for k in range(L)) + " |", "|---|" + "---|" * L,
+                      "| avg us | " + " | ".join(f"{a:.1f}" for a in avg) + " |"]
     return "\n".join(lines) + "\n"
 
 
 def summary_sq(dirs, workload: str, commands, trace_dir: str = None, cycles_per_valu: float = None):
     """SQ counters per dispatch (several ``--pmc`` runs merged by kernel)
-    and, with the kernel trace's average durations, derived columns:
-    VALU busy from SQ_ACTIVE_INST_VALU (cycles in which the kernel's waves
-    issued VALU work, over 1024 SIMDs x 2.4 GHz x duration), VALU busy from
-    SQ_INSTS_VALU x the cycles one wave64 instruction occupies a SIMD (from
-    the FMA-loop microbenchmark), the active cycles per VALU instruction,
-    and the fraction of wave cycles spent waiting (SQ_WAIT_ANY /
-    SQ_WAVE_CYCLES)."""
+    and, with the kernel trace's average durations, derived columns: VALU
+    busy = SQ_INSTS_VALU x the cycles one wave64 FP32 instruction occupies a
+    SIMD (from the FMA-loop microbenchmark) / (1024 SIMDs x 2.4 GHz x
+    duration); SQ_ACTIVE_INST_VALU / SQ_INSTS_VALU (on MI355X the ratio is 1
+    for every microbenchmark kind, whatever cycles its instructions take, so
+    the counter counts instructions here, not cycles); the fraction of wave
+    cycles spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES)."""
     merged = OrderedDict()
     for d in dirs:
         cnt, _ = read_counters(d)
@@ -134,9 +148,9 @@ def summary_sq(dirs, workload: str, commands, trace_dir: str = None, cycles_per_
         cpi = f"{cycles_per_valu:.2f}" if cycles_per_valu else "n/a"
         lines += [f"Derived (average durations from the kernel trace; {cpi} cycles per wave64 FP32 VALU "
                   "instruction from the FMA-loop microbenchmark):", "",
-                  "| kernel | avg us | VALU instr / wave | VALU busy (SQ_ACTIVE_INST_VALU) | "
-                  "VALU busy (instr x cycles) | active cycles / VALU instr | waiting |",
-                  "|---|---|---|---|---|---|---|"]
+                  "| kernel | avg us | VALU instr / wave | VALU busy (instr x cycles) | "
+                  "SQ_ACTIVE_INST_VALU / SQ_INSTS_VALU | waiting |",
+                  "|---|---|---|---|---|---|"]
         for k, v in merged.items():
             us = avg_us(stats, k)
             if not us:
@@ -146,15 +160,14 @@ def summary_sq(dirs, workload: str, commands, trace_dir: str = None, cycles_per_
             w = v.get("SQ_WAVES")
             d = {"avg_us": us,
                  "valu_per_wave": iv / w if iv is not None and w else None,
-                 "valu_busy_active": av / den if av is not None else None,
                  "valu_busy_issue": iv * cycles_per_valu / den if iv is not None and cycles_per_valu else None,
-                 "active_cycles_per_valu": av / iv if av is not None and iv else None,
+                 "active_per_inst": av / iv if av is not None and iv else None,
                  "waiting": (v["SQ_WAIT_ANY"] / v["SQ_WAVE_CYCLES"]
                              if v.get("SQ_WAIT_ANY") is not None and v.get("SQ_WAVE_CYCLES") else None)}
             derived[k] = d
             lines.append(f"| `{k}` | {us:.1f} | " + " | ".join(
                 "n/a" if d[c] is None else f"{d[c]:.3g}" for c in
-                ("valu_per_wave", "valu_busy_active", "valu_busy_issue", "active_cycles_per_valu", "waiting")) + " |")
+                ("valu_per_wave", "valu_busy_issue", "active_per_inst", "waiting")) + " |")
         lines.append("")
     return "\n".join(lines) + "\n", merged, derived
 
@@ -216,9 +229,14 @@ def main(argv=None):
     ap.add_argument("--launch", default="{}")
     ap.add_argument("--calib-bytes", type=int, default=1 << 30)
     ap.add_argument("--cycles-per-valu", type=float, default=None)
+    ap.add_argument("--per-depth", default=None, help="KERNEL:L, e.g. k_level:6")
     a = ap.parse_args(argv)
     if a.kind == "trace":
-        sys.stdout.write(summary_trace(a.dirs[0], a.workload, a.command))
+        pd = None
+        if a.per_depth:
+            fam, L = a.per_depth.split(":")
+            pd = (fam, int(L))
+        sys.stdout.write(summary_trace(a.dirs[0], a.workload, a.command, pd))
     elif a.kind == "sq":
         sys.stdout.write(summary_sq(a.dirs, a.workload, a.command, a.trace_dir, a.cycles_per_valu)[0])
     else:
