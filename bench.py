@@ -356,10 +356,11 @@ def kernel_times(torch, step: Step, K: int):
     eng.p.n_events = n_ev
     # slots: reset, flatten, seed, (descent, lazy flatten) per depth or the
     # flat kernel, certify (if on), fallback
+    # (+1: the statistics fold after the exact pass)
     if eng.p.mode == _abi.DEM_MODE_HIER and eng.p.persistent:
-        n_launch = 3 + (2 if eng.p.certify else 1)  # reset, flatten, persistent descent, certify, fallback
+        n_launch = 3 + (2 if eng.p.certify else 1) + 1  # reset, flatten, persistent descent, certify, fallback
     else:
-        n_launch = 3 + (2 * eng.ds.n_levels_max if eng.p.mode == _abi.DEM_MODE_HIER else 1) + (2 if eng.p.certify else 1)
+        n_launch = 3 + (2 * eng.ds.n_levels_max if eng.p.mode == _abi.DEM_MODE_HIER else 1) + (2 if eng.p.certify else 1) + 1
     acc = np.zeros(n_launch)
     bwd = 0.0
     evals = np.zeros(_abi.DEM_MAX_LEVELS)
@@ -812,7 +813,7 @@ def main():
                "seed_ms": seed_ms, "levels_ms": level_ms,
                "levels_ms_each": [round(x, 4) for x in level_kt],
                "certify_ms": kt[nb] if cert else None, "fallback_ms": kt[nb + (1 if cert else 0)],
-               "near_ms": float(np.sum(kt[nb:])),
+               "near_ms": float(np.sum(kt[nb:nb + (2 if cert else 1)])), "fold_ms": kt[-1],
                "backward_ms": bwd_ms if backward else None,
                "flatten_records": n_written, "flatten_GBs": flat_bytes / (kt[1] * 1e-3) / 1e9}
     out = {"metric": METRIC, "value": evals / (ms * 1e-3), "unit": "tri-pair evals/s", "n_gpus": 1,
@@ -847,7 +848,7 @@ def main():
         fevals = float(np.sum(fst["evals"]))
         out["flat"] = {"autotuned": fe.tuned, "ms_per_step": fms, "ms_per_step_wall": fwall, "evals_per_step": fevals,
                        "evals_per_s": fevals / (fms * 1e-3), "contacts": fst["contacts"],
-                       "flat_kernel_ms": float(fkt[3]), "near_ms": float(np.sum(fkt[4:])),
+                       "flat_kernel_ms": float(fkt[3]), "near_ms": float(np.sum(fkt[4:-1])),
                        "flat_kernel_TFLOPs": flops_per_eval(n_iter) * fevals / (fkt[3] * 1e-3) / 1e12}
         out["speedup_vs_flat"] = fms / ms
         log(f"[bench] flat: {fms:.2f} ms/step, {fevals:.4g} evals/step")

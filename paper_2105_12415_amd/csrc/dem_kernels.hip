@@ -58,6 +58,20 @@ constexpr int kSeg = 8;
 constexpr int kMaxXcc = 16;
 constexpr int kFinePart = 64;
 
+// Statistics and energy of the forward pass in kStatPart partial sums: a
+// block adds its block-reduced counts to partial blockIdx % kStatPart, each
+// partial on lines of its own, and k_fold_stats sums the partials into
+// dem_stats and the energy after the call's last kernel.  (One atomic per
+// wave on one address serialises in L2 at the end of every launch: about
+// 10 % of the descent.)
+constexpr int kStatPart = 16;
+struct alignas(128) StatPart {
+  unsigned long long evals[DEM_MAX_LEVELS];
+  unsigned long long survivors[DEM_MAX_LEVELS];
+  unsigned long long near, fallback, contacts, certified;
+  double energy;
+};
+
 struct Counters {
   uint32_t tail[DEM_MAX_LEVELS + 1][kSeg];  // level queues
   uint32_t near_tail[kSeg];                 // fine pairs not pruned
@@ -77,6 +91,7 @@ struct Counters {
   // statistics: records written by the lazy flattening, in kFinePart partial
   // counts on lines of their own (folded into dem_stats by the exact pass)
   uint32_t fine_part[kFinePart][32];
+  StatPart stat_part[kStatPart];
 };
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -166,6 +181,43 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
+// Block sums of NV counts (every thread calls; valid in thread 0).
+template <int NV>
+__device__ __forceinline__ void block_sums(unsigned long long (&v)[NV]) {
+  __shared__ unsigned long long red[NV][16];
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    v[k] = wave_sum_u64(v[k]);
+    if (lane_id() == 0) red[k][w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      unsigned long long t = 0;
+      for (int q = 0; q < nw; ++q) t += red[k][q];
+      v[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double block_sum_f64(double v) {
+  __shared__ double redd[16];
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  if (lane_id() == 0) redd[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += redd[q];
+    v = t;
+  }
+  __syncthreads();
+  return v;
+}
+
 template <typename V>
 __device__ __forceinline__ V wave_min(V v) {
 #pragma unroll
@@ -198,6 +250,45 @@ __global__ void k_reset(Counters* ctr, dem_stats* stats, uint32_t* status, uint3
     *status = 0;
     *count = 0;
     if (energy) *energy = 0.0;
+  }
+}
+
+// Sums of the forward's partial statistics and energy (one wave, after the
+// call's last kernel).
+__global__ void k_fold_stats(const StatPart* part, const uint32_t* fine_part, int n_levels, dem_stats* stats,
+                             double* energy) {
+  const int t = threadIdx.x;
+  if (stats) {
+    for (int d = t; d < n_levels && d < DEM_MAX_LEVELS; d += blockDim.x) {
+      unsigned long long e = 0, v = 0;
+      for (int q = 0; q < kStatPart; ++q) {
+        e += part[q].evals[d];
+        v += part[q].survivors[d];
+      }
+      if (e) stats->evals[d] += e;
+      if (v) stats->survivors[d] += v;
+    }
+    if (t == 0) {
+      unsigned long long nr = 0, fb = 0, ct = 0, ce = 0;
+      for (int q = 0; q < kStatPart; ++q) {
+        nr += part[q].near;
+        fb += part[q].fallback;
+        ct += part[q].contacts;
+        ce += part[q].certified;
+      }
+      stats->near += nr;
+      stats->fallback += fb;
+      stats->contacts += ct;
+      stats->certified += ce;
+      unsigned long long fr = 0;
+      for (int q = 0; q < kFinePart; ++q) fr += fine_part[q * 32];
+      stats->fine_records += fr;
+    }
+  }
+  if (energy && t == 1) {
+    double e = 0.0;
+    for (int q = 0; q < kStatPart; ++q) e += part[q].energy;
+    *energy += e;
   }
 }
 
@@ -461,6 +552,7 @@ struct LevelArgs {
   uint32_t* near_tail;       // [kSeg]
   int64_t ncap;              // entries per segment
   dem_stats* stats;
+  StatPart* part;            // partial statistics (with stats; null: straight into stats)
   uint32_t* status;
   int depth;
   int dense;
@@ -685,13 +777,22 @@ __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup,
 }
 
 // End of a depth for this block: the staged survivors leave, and the counts
-// reach the statistics (one atomic per wave).
+// reach the statistics (block sums into a partial, or one atomic per wave).
 template <int BLOCK>
 __device__ __forceinline__ void level_finish(const LevelArgs& a, LevelShared<BLOCK>& sh, LevelCounts& c) {
   __syncthreads();
   lds_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
   lds_flush(sh.qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
-  if (a.stats) {
+  if (a.part) {
+    unsigned long long v[3] = {c.evals, c.surv, c.near};
+    block_sums(v);
+    if (threadIdx.x == 0) {
+      StatPart& q = a.part[blockIdx.x % kStatPart];
+      if (v[0]) atomicAdd(&q.evals[a.depth], v[0]);
+      if (v[1]) atomicAdd(&q.survivors[a.depth], v[1]);
+      if (v[2]) atomicAdd(&q.near, v[2]);
+    }
+  } else if (a.stats) {
     unsigned long long s0 = c.evals, s1 = c.surv, s2 = c.near;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1050,7 +1151,7 @@ struct NearArgs {
   const uint32_t* fr_state;
   uint8_t* fr_meta;
   void* adj;               // contacts' adjoint rows, or null
-  const uint32_t* fine_part;  // lazy flattening's partial counts to fold into stats (or null)
+  StatPart* part;          // partial statistics and energy (null: straight into stats / energy)
 };
 
 // A contact staged in LDS: its output fields and its adjoint rows.
@@ -1215,6 +1316,22 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_near(const Soup
   }
   write_contacts(qc, a);
   if constexpr (CERTIFY) lds_flush(qf, a.fb_tail, a.fb, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+  if (a.part) {
+    // block sums into this block's partial (k_fold_stats adds them up)
+    unsigned long long v[3] = {my_fb, my_c, my_cert};
+    block_sums(v);
+    const double esum = a.energy ? block_sum_f64(e_acc) : 0.0;
+    if (threadIdx.x == 0) {
+      StatPart& q = a.part[blockIdx.x % kStatPart];
+      if (a.stats) {
+        if (v[0]) atomicAdd(&q.fallback, v[0]);
+        if (v[1]) atomicAdd(&q.contacts, v[1]);
+        if (v[2]) atomicAdd(&q.certified, v[2]);
+      }
+      if (esum != 0.0) atomicAdd(&q.energy, esum);
+    }
+    return;
+  }
   if (a.energy) {
     double sum = wave_sum(e_acc);
     if (lane_id() == 0 && sum != 0.0) atomicAdd(a.energy, sum);
@@ -1231,11 +1348,6 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_near(const Soup
       if (s0) atomicAdd(&a.stats->fallback, s0);
       if (s1) atomicAdd(&a.stats->contacts, s1);
       if (s2) atomicAdd(&a.stats->certified, s2);
-    }
-    // the lazy flattening's partial counts (its kernels ran before this one)
-    if (a.fine_part && blockIdx.x == 0 && threadIdx.x < kFinePart) {
-      const uint32_t v = a.fine_part[threadIdx.x * 32];
-      if (v) atomicAdd(&a.stats->fine_records, (unsigned long long)v);
     }
   }
 }
@@ -2863,6 +2975,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   la.near_tail = ctr->near_tail;
   la.ncap = nseg;
   la.stats = stats;
+  la.part = stats ? ctr->stat_part : nullptr;
   la.status = status;
   la.dense = p.dense_distance;
   la.batch = p.batch_items;
@@ -2944,6 +3057,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
   na.k = p.energy_k;
   na.energy = energy;
   na.stats = stats;
+  na.part = (stats || energy) ? ctr->stat_part : nullptr;
   na.status = status;
   na.ip = make_iter(p);
   if (p.certify) {
@@ -2953,9 +3067,13 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
     na.near_ = na.fb;
     na.near_tail = na.fb_tail;
   }
-  na.fine_part = stats ? &ctr->fine_part[0][0] : nullptr;
   hipLaunchKernelGGL((k_near<T, 0, false, false>), dim3(grid), dim3(p.block), 0, st, soup, na);
   mark();
+  if (stats || energy) {
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(64), 0, st, ctr->stat_part, &ctr->fine_part[0][0],
+                       s->n_levels_max, stats, energy);
+    mark();
+  }
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
 
