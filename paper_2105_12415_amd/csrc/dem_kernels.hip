@@ -1428,6 +1428,43 @@ __device__ __forceinline__ void hash_add_tri(GradHash<T>& H, const int32_t* __re
   }
 }
 
+// Lanes of a quad exchange values with DPP quad permutations (VALU moves, no
+// LDS): QUAD_XOR1 swaps lanes 2k and 2k+1, QUAD_XOR2 lanes k and k^2.
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+
+template <int CTRL>
+__device__ __forceinline__ int quad_swap(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v) {
+  return __int_as_float(quad_swap<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = quad_swap<CTRL>((int)(b & 0xFFFFFFFFll)), hi = quad_swap<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One step of the quad merge: a lane whose partner holds the same key adds
+// the partner's contribution (the lower lane) or gives its own away (the
+// upper lane, whose key becomes unique and negative).  Every lane of the
+// wave must take part.
+template <int CTRL, int M, typename T>
+__device__ __forceinline__ void quad_merge_step(int& key, V3<T> (&g)[3]) {
+  const int pk = quad_swap<CTRL>(key);
+  V3<T> pg[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) pg[v] = V3<T>{quad_swap<CTRL>(g[v].x), quad_swap<CTRL>(g[v].y), quad_swap<CTRL>(g[v].z)};
+  const bool same = pk == key;
+  const bool lower = (lane_id() & M) == 0;
+#pragma unroll
+  for (int v = 0; v < 3; ++v) g[v] = (same && lower) ? g[v] + pg[v] : g[v];
+  key = (same && !lower) ? -2 - lane_id() : key;
+}
+
 // Four consecutive values with 16-byte loads (p 16-byte aligned).
 __device__ __forceinline__ void ld4(const int32_t* p, int32_t o[4]) {
   const int4 v = *reinterpret_cast<const int4*>(p);
@@ -1496,58 +1533,70 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_backward(const 
         }
       }
     }
+    // The contacts of a thread's step j and of the next lanes' step j are four
+    // apart in the list: in a surrogate pair's 4 x 4 children they share t_j.
+    // So at each step the four lanes of a quad merge equal t_j with DPP
+    // swaps, and one lane per distinct t_j enters the table.  (Flags instead
+    // of early exits keep every lane in step for the swaps.)
 #pragma unroll
     for (int j = 0; j < kBwdPerThread; ++j) {
       const uint32_t c = cb + j;
-      if (c >= cnt) continue;
-      const int ti = ADJ ? pti[j] : cti[c], tj = ADJ ? ptj[j] : ctj[c];
-      if ((uint32_t)ti >= (uint32_t)n_tris || (uint32_t)tj >= (uint32_t)n_tris) {
+      bool live = c < cnt;
+      const uint32_t cr = live ? c : cnt - 1;
+      const int ti = ADJ ? pti[j] : cti[cr], tj = ADJ ? ptj[j] : ctj[cr];
+      if (live && ((uint32_t)ti >= (uint32_t)n_tris || (uint32_t)tj >= (uint32_t)n_tris)) {
         atomicOr(status, DEM_DEV_BAD_TREE);  // not a triangle of this scene: skipped
-        continue;
+        live = false;
       }
-      T d, delta, wp[3], wq[3];
-      V3<T> u;
-      if constexpr (ADJ) {
-        d = pd[j];
-        delta = pa[0][j];
-        u = V3<T>{pa[1][j], pa[2][j], pa[3][j]};
-        const int code = (int)pa[4][j];
-        bary_weights(code & 7, pa[5][j], pa[6][j], wp);
-        bary_weights(code >> 3, pa[7][j], pa[8][j], wq);
-      } else {
-        int cbi, cci, pi_, cbj, ccj, pj_;
-        Tri<T> A = load_tri(soup, ti, cbi, cci, pi_);
-        Tri<T> B = load_tri(soup, tj, cbj, ccj, pj_);
-        V3<T> D0 = A.v0 - B.v0;
-        Closest<T> cl;
-        exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, cl);
-        d = sq_(cl.d2);
-        delta = A.eps + B.eps;
-        u = d > T(0) ? (T(1) / d) * (cl.q - cl.p) : V3<T>{T(0), T(0), T(0)};
+      T d = T(0), delta = T(-1), wp[3] = {T(0), T(0), T(0)}, wq[3] = {T(0), T(0), T(0)};
+      V3<T> u = {T(0), T(0), T(0)};
+      if (live) {
+        if constexpr (ADJ) {
+          d = pd[j];
+          delta = pa[0][j];
+          u = V3<T>{pa[1][j], pa[2][j], pa[3][j]};
+          const int code = (int)pa[4][j];
+          bary_weights(code & 7, pa[5][j], pa[6][j], wp);
+          bary_weights(code >> 3, pa[7][j], pa[8][j], wq);
+        } else {
+          int cbi, cci, pi_, cbj, ccj, pj_;
+          Tri<T> A = load_tri(soup, ti, cbi, cci, pi_);
+          Tri<T> B = load_tri(soup, tj, cbj, ccj, pj_);
+          V3<T> D0 = A.v0 - B.v0;
+          Closest<T> cl;
+          exact_tri_tri(V3<T>{0, 0, 0}, A.e1, A.e2, -D0, B.e1, B.e2, cl);
+          d = sq_(cl.d2);
+          delta = A.eps + B.eps;
+          u = d > T(0) ? (T(1) / d) * (cl.q - cl.p) : V3<T>{T(0), T(0), T(0)};
 #pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          wp[v] = cl.wp[v];
-          wq[v] = cl.wq[v];
+          for (int v = 0; v < 3; ++v) {
+            wp[v] = cl.wp[v];
+            wq[v] = cl.wq[v];
+          }
         }
       }
-      double pen = (double)delta - (double)d;
-      if (!(pen >= 0.0)) continue;
-      e_acc += k * pen * pen;
-      if (!(d > T(0)) || grad == nullptr) continue;
-      T g = T(2.0 * k * pen * gE);
-      if (ti != run) {
-        if (run >= 0) hash_add_tri(H, tv, n_tris, run, rg, grad, n_verts);
-        run = ti;
+      const double pen = (double)delta - (double)d;
+      live = live && pen >= 0.0;
+      if (live) e_acc += k * pen * pen;
+      const bool on = live && d > T(0) && grad != nullptr;
+      const T g = on ? T(2.0 * k * pen * gE) : T(0);
+      if (on) {
+        if (ti != run) {
+          if (run >= 0) hash_add_tri(H, tv, n_tris, run, rg, grad, n_verts);
+          run = ti;
 #pragma unroll
-        for (int v = 0; v < 3; ++v) rg[v] = V3<T>{0, 0, 0};
+          for (int v = 0; v < 3; ++v) rg[v] = V3<T>{0, 0, 0};
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) rg[v] = rg[v] + (g * wp[v]) * u;
       }
       V3<T> gq[3];
 #pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        rg[v] = rg[v] + (g * wp[v]) * u;
-        gq[v] = (-g * wq[v]) * u;
-      }
-      hash_add_tri(H, tv, n_tris, tj, gq, grad, n_verts);
+      for (int v = 0; v < 3; ++v) gq[v] = (-g * wq[v]) * u;
+      int key = on ? tj : -2 - lane_id();
+      quad_merge_step<kQuadXor1, 1>(key, gq);
+      quad_merge_step<kQuadXor2, 2>(key, gq);
+      if (key >= 0) hash_add_tri(H, tv, n_tris, key, gq, grad, n_verts);
     }
     if (run >= 0) hash_add_tri(H, tv, n_tris, run, rg, grad, n_verts);
     __syncthreads();
