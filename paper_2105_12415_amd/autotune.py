@@ -33,7 +33,7 @@ HIER_SPACE: Dict[str, Sequence] = {
 }
 
 LEVEL_GRIDS = (512, 1024, 1536, 2048, 3072)
-LEVEL_BATCHES = (32, 64, 128, 256)
+LEVEL_BATCHES = (8, 16, 32, 64, 128, 256)
 
 
 def hier_space(n_levels: int) -> Dict[str, Sequence]:
