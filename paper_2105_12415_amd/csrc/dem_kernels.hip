@@ -41,7 +41,8 @@ constexpr int kWave = 64;
 template <typename T>
 struct alignas(16) SoupRec {
   T g[12];         // v0.xyz eps | e1.xyz ia | e2.xyz ib
-  int32_t topo[4]; // child_begin, child_count, particle, size bound (float bits)
+  int32_t topo[4]; // child_begin, child_count, size bound (float bits), particle (last: the
+                   // descent does not read it, so the three words it reads are contiguous)
 };
 
 // Bit of topo[1] (above the child count) marking a surrogate whose children
@@ -139,9 +140,9 @@ __device__ __forceinline__ Tri<T> load_tri(const SoupRec<T>* __restrict__ s, int
     x.e1 = {b0.x, b0.y, b1.x}; x.ia = b1.y;
     x.e2 = {c0.x, c0.y, c1.x}; x.ib = c1.y;
   }
-  cb = d.x; cc = d.y & kCountMask; part = d.z;
+  cb = d.x; cc = d.y & kCountMask; part = d.w;
   kids_fine = (d.y & kKidsFine) != 0;
-  x.size = T(__int_as_float(d.w));
+  x.size = T(__int_as_float(d.z));
   return x;
 }
 
@@ -351,8 +352,8 @@ __device__ __forceinline__ SoupRec<T> flatten_rec(const FlatArgs<T>& a, int t, i
   const float sz = (float)(tri_size(e1, e2) * T(1.0 + 1.0 / 1048576.0));
   // children of the last surrogate level start at the particle's fine range
   const bool kids_fine = cc > 0 && cb >= a.fine_begin[part];
-  r.topo[0] = cb; r.topo[1] = cc | (kids_fine ? kKidsFine : 0); r.topo[2] = part;
-  r.topo[3] = __float_as_int(sz);
+  r.topo[0] = cb; r.topo[1] = cc | (kids_fine ? kKidsFine : 0); r.topo[2] = __float_as_int(sz);
+  r.topo[3] = part;
   T chk = v0.x + v0.y + v0.z + e1.x + e1.y + e1.z + e2.x + e2.y + e2.z;
   if (!isfinite(chk)) atomicOr(a.status, DEM_DEV_NONFINITE);
   return r;
@@ -580,7 +581,8 @@ __device__ __forceinline__ void lds_append(bool pred, R rec, R* buf, uint32_t* n
   int leader = __ffsll((long long)m) - 1;
   uint32_t base = 0;
   if (lane_id() == leader) base = atomicAdd(n, (uint32_t)__popcll(m));
-  base = __shfl(base, leader);
+  // the leader's slot to every lane with a lane read (no LDS permute)
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
   unsigned long long lt = (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
   if (pred) buf[base + (uint32_t)__popcll(m & lt)] = rec;
 }
@@ -652,7 +654,7 @@ struct LevelShared {
 };
 
 struct LevelCounts {
-  unsigned long long evals, surv, near;
+  uint32_t evals, surv, near;  // per lane and depth (summed in 64 bits at the depth's end)
 };
 
 // One batch of work items: items [first, first + n) of segment x of the
@@ -736,15 +738,19 @@ __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup,
       Tri<T> A = load_tri(soup, ci, cbi, cci, pi_, kfi);
       Tri<T> B = load_tri(soup, cj, cbj, ccj, pj_, kfj);
       V3<T> D0 = A.v0 - B.v0;
+      // what the test needs from the records, formed at once: otherwise the
+      // compiler reloads those words after the iteration (an extra L1
+      // request per record)
+      const T delta = A.eps + B.eps;
+      const T slack = bound_slack(A, B, D0, delta);
       T L;
       if constexpr (HALF && sizeof(T) == 4) {
         L = iterate_bound_mixed<N>(A, B, D0, a.ip);
       } else {
         L = iterate_bound<T, N>(A, B, D0, a.ip);
       }
-      T delta = A.eps + B.eps;
       bool fine = (cci == 0) && (ccj == 0);
-      bool keep = a.dense ? true : !(L > delta + bound_slack(A, B, D0, delta));
+      bool keep = a.dense ? true : !(L > delta + slack);
       ++c.evals;
       // surrogate survivors unfold into the next depth's item (only the
       // non-fine side unfolds); fine survivors go to the near list
