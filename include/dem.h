@@ -445,6 +445,13 @@ dem_status dem_find_contacts_noalloc(const dem_scene* scene, const int32_t* pair
  * grad_E     device double scalar multiplying the gradient, or NULL for 1.
  * grad_verts device [3][n_verts] with respect to world positions,
  *            ACCUMULATED into (caller zeroes it); NULL for energy only.
+ *            Contributions are first summed per vertex within a block in
+ *            64-bit fixed point scaled to the block's largest bound
+ *            2k |grad_E| delta (exact sums; each contribution rounded to
+ *            2^-29 of that bound in FP32, 2^-52 in FP64), then added to
+ *            grad_verts with one FP32/FP64 atomic per vertex and component
+ *            (order unspecified).  A contribution above 2^100 or not finite
+ *            is left out and sets DEM_DEV_NONFINITE.
  * energy_out device double or NULL: set to E.
  * workspace  without adjoint rows: the workspace of the dem_find_contacts
  *            call that produced `contacts`, unchanged since, with the

@@ -182,3 +182,37 @@ def test_frontier_contacts_carry_rows():
     assert gmax > 0
     assert np.abs(g_rows - g_solve).max() <= 1e-6 * gmax
     assert abs(e_rows - e_solve) <= 1e-6 * e_solve
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_backward_fixed_point_scale(prec):
+    """The per-vertex sums run in fixed point scaled to each chunk's bound
+    2k |grad_E| delta: a power-of-two grad_E moves that scale by the same
+    power, so the gradient for grad_E = 2^40 (or 2^-40) is that for 1 times
+    2^40 (2^-40) up to the order of the final atomic additions; grad_E = 0
+    gives a zero gradient; a non-finite grad_E leaves every contribution out
+    and sets DEM_DEV_NONFINITE, while the energy is still written."""
+    scene = _scene(prec)
+    ds = api.DeviceScene(scene, device="cuda:0")
+    eng = api.ContactEngine(ds, api.make_params("hier"), energy_k=1e4)
+    assert eng.run() == 0
+    g1, e1 = _grad(eng)
+    assert np.abs(g1).max() > 0
+    rtol = 1e-6 if prec == "f32" else 1e-12
+    for p2 in (40, -40):
+        ge = torch.tensor([2.0 ** p2], dtype=torch.float64, device="cuda:0")
+        g = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device="cuda:0")
+        eng.backward(g, grad_E=ge)
+        assert eng.check() == 0
+        gs = g.double().cpu().numpy() * 2.0 ** -p2
+        assert np.abs(gs - g1).max() <= rtol * np.abs(g1).max(), p2
+    g = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device="cuda:0")
+    eng.backward(g, grad_E=torch.zeros(1, dtype=torch.float64, device="cuda:0"))
+    assert eng.check() == 0 and float(g.abs().max()) == 0.0
+    g = torch.zeros(3, ds.n_verts, dtype=ds.dtype, device="cuda:0")
+    eng.backward(g, grad_E=torch.tensor([float("inf")], dtype=torch.float64, device="cuda:0"), energy=True)
+    st = eng.check()
+    assert st & _abi.DEM_DEV_NONFINITE
+    assert float(g.abs().max()) == 0.0
+    assert abs(float(eng.energy_bwd.item()) - e1) <= 1e-9 * e1
+    eng.status.zero_()
