@@ -1160,12 +1160,25 @@ struct NearArgs {
   StatPart* part;          // partial statistics and energy (null: straight into stats / energy)
 };
 
-// A contact staged in LDS: its output fields and its adjoint rows.
+// A contact on its way out: its output fields and its adjoint rows.
 template <typename T>
 struct ContactRec {
   int32_t pi, pj, ti, tj;
   T d, x[3], n[3];
   T adj[DEM_ADJOINT_ROWS];
+};
+
+// Contacts staged in LDS field by field (one array per field), so that the
+// lanes appending consecutive slots, and the threads copying them out, touch
+// consecutive words (an array of 80-byte records put consecutive lanes 20
+// words apart: conflicting banks on every access).
+constexpr int kContactFields = 7 + DEM_ADJOINT_ROWS;  // d, x[3], n[3], adjoint rows
+template <typename T, int CAP>
+struct ContactStage {
+  int32_t id[4][CAP];        // pi, pj, ti, tj
+  T f[kContactFields][CAP];
+  uint32_t n;
+  uint32_t gbase;
 };
 
 // 496 FP32 records (80 bytes) keep a block of the exact pass within 40 KB of
@@ -1184,9 +1197,32 @@ __device__ __forceinline__ void adjoint_rows(T adj[DEM_ADJOINT_ROWS], T delta, T
   adj[7] = kq.a; adj[8] = kq.b;
 }
 
+// Wave-aggregated append of rec (lanes with pred) to the stage.
+template <typename T, int CAP>
+__device__ __forceinline__ void stage_contact(bool pred, const ContactRec<T>& rec, ContactStage<T, CAP>& qc) {
+  unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(&qc.n, (uint32_t)__popcll(m));
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+  unsigned long long lt = (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
+  if (pred) {
+    const uint32_t k = base + (uint32_t)__popcll(m & lt);
+    qc.id[0][k] = rec.pi; qc.id[1][k] = rec.pj; qc.id[2][k] = rec.ti; qc.id[3][k] = rec.tj;
+    qc.f[0][k] = rec.d;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      qc.f[1 + q][k] = rec.x[q];
+      qc.f[4 + q][k] = rec.n[q];
+    }
+#pragma unroll
+    for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) qc.f[7 + q][k] = rec.adj[q];
+  }
+}
+
 template <typename T>
-__device__ __forceinline__ void write_contacts(LdsQueue<ContactRec<T>, kStageContacts>& qc,
-                                               const NearArgs& a) {
+__device__ __forceinline__ void write_contacts(ContactStage<T, kStageContacts>& qc, const NearArgs& a) {
   T* dd = static_cast<T*>(a.d);
   T* xx = static_cast<T*>(a.x);
   T* nn = static_cast<T*>(a.n);
@@ -1195,15 +1231,17 @@ __device__ __forceinline__ void write_contacts(LdsQueue<ContactRec<T>, kStageCon
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < qc.n; k += blockDim.x) {
     uint64_t slot = (uint64_t)qc.gbase + k;
-    const ContactRec<T>& r = qc.buf[k];
     if (slot < (uint64_t)a.ccap) {
-      a.pi[slot] = r.pi; a.pj[slot] = r.pj; a.ti[slot] = r.ti; a.tj[slot] = r.tj;
-      dd[slot] = r.d;
-      xx[slot] = r.x[0]; xx[a.ccap + slot] = r.x[1]; xx[2 * a.ccap + slot] = r.x[2];
-      nn[slot] = r.n[0]; nn[a.ccap + slot] = r.n[1]; nn[2 * a.ccap + slot] = r.n[2];
+      a.pi[slot] = qc.id[0][k]; a.pj[slot] = qc.id[1][k]; a.ti[slot] = qc.id[2][k]; a.tj[slot] = qc.id[3][k];
+      dd[slot] = qc.f[0][k];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        xx[q * a.ccap + slot] = qc.f[1 + q][k];
+        nn[q * a.ccap + slot] = qc.f[4 + q][k];
+      }
       if (aj) {
 #pragma unroll
-        for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) aj[q * a.ccap + slot] = r.adj[q];
+        for (int q = 0; q < DEM_ADJOINT_ROWS; ++q) aj[q * a.ccap + slot] = qc.f[7 + q][k];
       }
     } else {
       atomicOr(a.status, DEM_DEV_CONTACT_OVERFLOW);
@@ -1237,7 +1275,7 @@ struct CertTol<double> {
 // also allows)
 template <typename T, int N, bool CERTIFY, bool FR>
 __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_near(const SoupRec<T>* __restrict__ soup, NearArgs a) {
-  __shared__ LdsQueue<ContactRec<T>, kStageContacts> qc;
+  __shared__ ContactStage<T, kStageContacts> qc;
   __shared__ LdsQueue<int2, kStageNear> qf;
   __shared__ SegView view;
   seg_view(view, a.near_tail, a.ncap);
@@ -1311,7 +1349,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) k_near(const Soup
         my_c += emit;
       }
     }
-    lds_append(emit, rec, qc.buf, &qc.n);
+    stage_contact(emit, rec, qc);
     if constexpr (CERTIFY) lds_append(defer, pr, qf.buf, &qf.n);
     __syncthreads();
     if (qc.n + bdim > (uint32_t)kStageContacts) write_contacts(qc, a);
