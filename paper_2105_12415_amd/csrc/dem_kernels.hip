@@ -405,61 +405,97 @@ __global__ void __launch_bounds__(kFlatBlock) k_flatten(FlatArgs<T> a) {
     if (act[c / kChunks]) dst[c] = src[c];
 }
 
-// Lazy mode, after the descent at depth d: the children of every depth-d
-// surrogate (parents[0 .. n)) that survived in some pair are written.  Four
-// lanes share a parent and take its children in turn, so sibling records
-// (contiguous) are written together.
-constexpr int kFineLanes = 4;
+// Block-wide exclusive scan of v (blockDim <= 1024) into offs[0..n].
+__device__ __forceinline__ void block_scan(int v, int* offs, int* wsum, int n) {
+  int lane = lane_id();
+  int wid = threadIdx.x / kWave;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    int nw = (blockDim.x + kWave - 1) / kWave;
+    for (int w = 0; w < nw; ++w) {
+      int s = wsum[w];
+      wsum[w] = acc;
+      acc += s;
+    }
+    offs[n] = acc;  // total lives after the last item (read only after sync)
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < n) offs[threadIdx.x] = x - v + wsum[wid];
+  __syncthreads();
+}
 
+// Lazy mode, after the descent at depth d: the children of every depth-d
+// surrogate (parents[0 .. n)) that survived in some pair are written.  A
+// thread tests one parent's mark; a block-wide scan then packs the children
+// of the marked parents onto consecutive lanes (most parents are not
+// marked: testing four lanes per parent left most lanes of the flattening
+// idle), and the block's records go through LDS so that sibling records
+// leave as whole 16-byte chunks, as in k_flatten.
 template <typename T>
 struct FineShared {
   SoupRec<T> stage[kFlatBlock];
   int dest[kFlatBlock];
+  int offs[kFlatBlock + 1];                      // child slots of the block's parents
+  int wsum[16];
+  int cb[kFlatBlock];                            // child range begin of each parent
+  uint8_t owner[kFlatBlock * DEM_MAX_CHILDREN];  // child slot -> parent (thread)
 };
 
 // The children of parents[0 .. n) that survived (mark set), over blocks
-// start, start + stride, ... of kFlatBlock threads.
+// start, start + stride, ... of kFlatBlock parents.
 template <typename T>
 __device__ __forceinline__ void fine_range(const FlatArgs<T>& a, const int32_t* __restrict__ parents, int n,
                                            FineShared<T>& sh, uint32_t start, uint32_t stride) {
-  // a lane's first child goes through LDS (whole 16-byte chunks of sibling
-  // records leave together, as in k_flatten); further children of a parent
-  // with more than kFineLanes are stored directly
-  const int64_t total = (int64_t)n * kFineLanes;
   uint32_t written = 0;  // records of the parents this thread found marked
-  for (int64_t base = start * (int64_t)kFlatBlock; base < total; base += (int64_t)stride * kFlatBlock) {
+  for (int64_t base = start * (int64_t)kFlatBlock; base < n; base += (int64_t)stride * kFlatBlock) {
     const int64_t i = base + threadIdx.x;
-    int d = -1;
-    if (i < total) {
-      const int s = parents[i / kFineLanes];
-      const int slot = (int)(i % kFineLanes);
+    int cb = 0, cc = 0;
+    if (i < n) {
+      const int s = parents[i];
       if ((uint32_t)s >= (uint32_t)a.n_tris) {
-        if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
+        atomicOr(a.status, DEM_DEV_BAD_TREE);
       } else if (a.mark[s]) {
-        const int cb = a.cbeg[s], cc = a.ccnt[s];
+        cb = a.cbeg[s];
+        cc = a.ccnt[s];
         if (cc < 1 || cc > DEM_MAX_CHILDREN || cb < 0 || cb > a.n_tris - cc) {
-          if (slot == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
-        } else {
-          if (slot < cc) {
-            d = cb + slot;
-            sh.stage[threadIdx.x] = flatten_rec(a, d, a.cbeg[d], a.ccnt[d], a.tpart[d]);
-          }
-          if (slot == 0) written += (uint32_t)cc;
-          for (int c = cb + slot + kFineLanes; c < cb + cc; c += kFineLanes)
-            flatten_one(a, c, a.cbeg[c], a.ccnt[c], a.tpart[c]);
+          atomicOr(a.status, DEM_DEV_BAD_TREE);
+          cc = 0;
         }
       }
     }
-    sh.dest[threadIdx.x] = d;
+    written += (uint32_t)cc;
+    block_scan(cc, sh.offs, sh.wsum, kFlatBlock);
+    sh.cb[threadIdx.x] = cb;
+    for (int q = 0; q < cc; ++q) sh.owner[sh.offs[threadIdx.x] + q] = (uint8_t)threadIdx.x;
     __syncthreads();
-    constexpr int kChunks = (int)(sizeof(SoupRec<T>) / 16);
-    const uint4* src = reinterpret_cast<const uint4*>(sh.stage);
-    uint4* out = reinterpret_cast<uint4*>(a.soup);
-    for (int c = threadIdx.x; c < kFlatBlock * kChunks; c += kFlatBlock) {
-      const int dr = sh.dest[c / kChunks];
-      if (dr >= 0) out[(size_t)dr * kChunks + c % kChunks] = src[c];
+    const int total = sh.offs[kFlatBlock];
+    for (int k0 = 0; k0 < total; k0 += kFlatBlock) {
+      const int k = k0 + (int)threadIdx.x;
+      int d = -1;
+      if (k < total) {
+        const int pa = sh.owner[k];
+        d = sh.cb[pa] + (k - sh.offs[pa]);
+        sh.stage[threadIdx.x] = flatten_rec(a, d, a.cbeg[d], a.ccnt[d], a.tpart[d]);
+      }
+      sh.dest[threadIdx.x] = d;
+      __syncthreads();
+      constexpr int kChunks = (int)(sizeof(SoupRec<T>) / 16);
+      const uint4* src = reinterpret_cast<const uint4*>(sh.stage);
+      uint4* out = reinterpret_cast<uint4*>(a.soup);
+      for (int c = threadIdx.x; c < kFlatBlock * kChunks; c += kFlatBlock) {
+        const int dr = sh.dest[c / kChunks];
+        if (dr >= 0) out[(size_t)dr * kChunks + c % kChunks] = src[c];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (a.fine_part) {
 #pragma unroll
@@ -514,33 +550,6 @@ __global__ void k_seed(const int32_t* __restrict__ pairs, int n_pairs,
   __shared__ uint32_t base;
   if ((int)blockIdx.x < n_pairs)
     seed_pair(blockIdx.x, pairs, n_pairs, rbeg, rcnt, ci, cj, q, tails, seg_cap, status, base);
-}
-
-// Block-wide exclusive scan of v (blockDim <= 1024) into offs[0..n].
-__device__ __forceinline__ void block_scan(int v, int* offs, int* wsum, int n) {
-  int lane = lane_id();
-  int wid = threadIdx.x / kWave;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == kWave - 1) wsum[wid] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    int nw = (blockDim.x + kWave - 1) / kWave;
-    for (int w = 0; w < nw; ++w) {
-      int s = wsum[w];
-      wsum[w] = acc;
-      acc += s;
-    }
-    offs[n] = acc;  // total lives after the last item (read only after sync)
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < n) offs[threadIdx.x] = x - v + wsum[wid];
-  __syncthreads();
 }
 
 struct LevelArgs {
@@ -3211,7 +3220,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         const int f0 = fa.lazy ? s->fine_parent_begin[lev] : 0;
         const int nf = fa.lazy ? s->fine_parent_begin[lev + 1] - f0 : 0;
         if (nf > 0)
-          hipLaunchKernelGGL(k_fine<T>, dim3(std::min((nf * kFineLanes + kFlatBlock - 1) / kFlatBlock, 8192)), dim3(kFlatBlock), 0,
+          hipLaunchKernelGGL(k_fine<T>, dim3(std::min((nf + kFlatBlock - 1) / kFlatBlock, 1 << 20)), dim3(kFlatBlock), 0,
                              st, fa, s->fine_parents + f0, nf);
         mark();
       }
