@@ -265,7 +265,7 @@ class FrontierStep(Step):
             self.eng.backward(self.grad)
 
 
-FRONTIER_SLOTS = ("reset", "flatten", "eval", "near", "group", "scan", "emit", "finish")
+FRONTIER_SLOTS = ("reset", "flatten", "eval", "near", "group", "scan", "emit", "finish", "fold")
 
 
 def frontier_kernel_times(torch, step: FrontierStep, K: int):

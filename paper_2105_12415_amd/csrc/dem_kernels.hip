@@ -1807,6 +1807,7 @@ struct FrontierArgs {
   uint32_t* meta;               // [cap] per-leaf outcome word
   uint8_t* cm;                  // [cap] narrowing marks: 2 = group's first leaf, 1 = other member
   unsigned long long* part;     // [grid + 1] output leaves per block -> offsets
+  StatPart* spart;              // partial statistics (null: straight into stats)
   const int32_t* tri_parent;
   const uint8_t* tri_depth;
   const int32_t* cbeg;
@@ -1979,7 +1980,7 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
   }
   __syncthreads();
   lds_flush(qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
-  __shared__ unsigned long long osum[kFrBlock / kWave];
+  __shared__ unsigned long long osum[kFrBlock / kWave], nsum[kFrBlock / kWave];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     my_unf += __shfl_xor(my_unf, o);
@@ -1988,17 +1989,24 @@ __global__ void __launch_bounds__(kFrBlock) k_fr_eval(const SoupRec<T>* __restri
   }
   if (lane_id() == 0) {
     osum[threadIdx.x / kWave] = my_out;
-    if (my_unf) atomicAdd(&a.ctr->fr_unfold, my_unf);
-    if (a.stats && my_near) atomicAdd(&a.stats->near, (unsigned long long)my_near);
+    nsum[threadIdx.x / kWave] = my_near;
+    if (my_unf) atomicAdd(&a.ctr->fr_unfold, my_unf);  // (rare: the leaves that widen)
   }
   __syncthreads();
+  // counts into this block's partial (k_fold_stats adds them up): one atomic
+  // per wave on one address serialised across the whole grid
+  StatPart* sp = a.spart ? &a.spart[blockIdx.x % kStatPart] : nullptr;
   if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += osum[w];
+    unsigned long long t = 0, nr = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+      t += osum[w];
+      nr += nsum[w];
+    }
     a.part[blockIdx.x] = t;  // output leaves of this block's range, before narrowing
+    if (a.stats && nr) atomicAdd(sp ? &sp->near : &a.stats->near, nr);
   }
   if (a.stats && threadIdx.x < DEM_MAX_LEVELS && hist[threadIdx.x])
-    atomicAdd(&a.stats->evals[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
+    atomicAdd(sp ? &sp->evals[threadIdx.x] : &a.stats->evals[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
   if (a.stats && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.stats->frontier_leaves, (unsigned long long)n);
 }
 
@@ -3370,6 +3378,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   fa.near_tail = ctr->near_tail;
   fa.ncap = nseg;
   fa.stats = stats;
+  fa.spart = stats ? ctr->stat_part : nullptr;
   fa.status = status;
   fa.ip = make_iter(p);
   if (p.prune_exact) hipLaunchKernelGGL((k_fr_eval<T, 0, true>), dim3(grid), dim3(kFrBlock), 0, st, soup, fa);
@@ -3396,6 +3405,7 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   na.fr_buf1 = fa.buf1;
   na.fr_state = f->state;
   na.fr_meta = reinterpret_cast<uint8_t*>(fa.meta);
+  na.part = (stats || energy) ? ctr->stat_part : nullptr;  // summed by k_fold_stats at the end
   if (p.certify) {
     launch_near_certify<T, true>(p.n_iter, dim3(ngrid), dim3(p.block), st, soup, na);
     mark();
@@ -3412,6 +3422,10 @@ dem_status run_frontier_step(const dem_scene* s, const dem_params& p, const dem_
   mark();
   hipLaunchKernelGGL(k_fr_finish, dim3(1), dim3(64), 0, st, fa);
   mark();
+  if (na.part)
+    hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(64), 0, st, ctr->stat_part, &ctr->fine_part[0][0],
+                       DEM_MAX_LEVELS, stats, energy);
+  mark();  // (the fold's slot, empty without statistics and energy)
   return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
 }
 
