@@ -3691,34 +3691,78 @@ __global__ void k_cs_scatter(SortArgs a) {
 }
 
 // Every bucket by t_j (the last bucket, of invalid triangle numbers, by
-// input position).  A lane looks at one bucket; the wave then sorts its
-// lanes' buckets of two or more contacts one after the other, by ranks: every
-// contact's position is the number of smaller keys in its bucket (the keys of
-// a bucket are distinct).  A bucket of up to 64 contacts is ranked with one
-// contact per lane and placed directly; a longer one 64 contacts at a time
-// against its keys streamed through the wave's LDS slice in chunks, placed
-// through the staging area and copied back.
+// input position), by ranks: a contact's position is the number of smaller
+// keys in its bucket (the keys of a bucket are distinct).  Buckets inside
+// one window of 64 output positions (most) are ranked by k_cs_small; the
+// rest are listed and ranked one per wave by k_cs_bucket.
 constexpr uint32_t kBucketLds = 512;
 
 __device__ __forceinline__ long long cs_key(const SortArgs& a, bool by_input, int32_t c) {
   return by_input ? (long long)c : (long long)a.tj[c];
 }
 
-// The buckets to sort (two or more contacts), listed so that the sorting
-// waves share them evenly (contacts cluster in the triangle numbering).
+// A bucket of two or more contacts whose output range lies inside one
+// aligned window of 64 positions is ranked by k_cs_small.
+__device__ __forceinline__ bool cs_in_window(uint32_t lo, uint32_t m) {
+  return (lo / kWave) == ((lo + m - 1) / kWave);
+}
+
+// The other buckets to sort (two or more contacts, across a window boundary,
+// or of invalid triangle numbers), listed so that the sorting waves share
+// them evenly (contacts cluster in the triangle numbering).
 __global__ void k_cs_list(SortArgs a) {
   for (uint32_t base = blockIdx.x * blockDim.x; base < a.n_buckets; base += gridDim.x * blockDim.x) {
     const uint32_t b = base + threadIdx.x;
-    const bool need = b < a.n_buckets && a.fill[b] >= 2;
+    const uint32_t m = b < a.n_buckets ? a.fill[b] : 0u;
+    const bool need = m >= 2 && (b == a.n_buckets - 1 || !cs_in_window(a.hist[b], m));
     uint32_t ok;
     const uint32_t slot = wave_append(need, a.blist_n, ok);
     if (need && ok && slot < a.n_buckets) a.blist[slot] = b;
   }
 }
 
-// One wave per listed bucket.
+// The buckets inside one window (most: a triangle has a few contacts), by
+// the window's wave: lane p holds output position p's contact, reads its
+// bucket's range from the offsets, and counts the smaller keys among the
+// bucket's lanes (keys through the wave's LDS slice).  Every lane reads
+// before any lane writes, and a window's writes stay inside it.
+__global__ void __launch_bounds__(256) k_cs_small(SortArgs a) {
+  __shared__ long long skey[256 / kWave][kWave];
+  const uint32_t cnt = cs_count(a);
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+    const uint32_t p = base + threadIdx.x;
+    const uint32_t W = p - (uint32_t)lane;  // the window (base is a multiple of the block)
+    const bool act = p < cnt;
+    int32_t v = 0;
+    uint32_t b = 0, lo = 0, m = 0;
+    long long kk = LLONG_MAX;
+    if (act) {
+      v = a.idx[p];
+      b = cs_bucket(a, (uint32_t)v);
+      lo = a.hist[b];
+      m = a.fill[b];
+      kk = (long long)a.tj[v];
+    }
+    const bool mine = act && b != a.n_buckets - 1 && m >= 2 && cs_in_window(lo, m);
+    skey[w][lane] = kk;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t rank = 0;
+    if (mine)
+      for (uint32_t j = lo - W; j < lo - W + m; ++j) rank += skey[w][j] < kk ? 1u : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (mine) a.idx[lo + rank] = v;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// One wave per listed bucket.  Up to kBucketLds contacts: keys and contacts
+// into the wave's LDS slice first, so that every read of the bucket precedes
+// the writes and each contact is placed directly at its rank; longer
+// buckets 64 contacts at a time through the staging area.
 __global__ void __launch_bounds__(256) k_cs_bucket(SortArgs a) {
   __shared__ long long skey[256 / kWave][kBucketLds];
+  __shared__ int32_t sval[256 / kWave][kBucketLds];
   const uint32_t lane = (uint32_t)lane_id();
   const int w = threadIdx.x / kWave;
   int32_t* stage = reinterpret_cast<int32_t*>(a.tmp);  // free until the gather
@@ -3740,6 +3784,22 @@ __global__ void __launch_bounds__(256) k_cs_bucket(SortArgs a) {
       for (uint32_t j = 0; j < mw; ++j) rank += skey[w][j] < kk ? 1u : 0u;
       __builtin_amdgcn_wave_barrier();
       if (act) e[rank] = v;
+      continue;
+    }
+    if (mw <= kBucketLds) {
+      for (uint32_t r = lane; r < mw; r += kWave) {
+        const int32_t v = e[r];
+        sval[w][r] = v;
+        skey[w][r] = cs_key(a, by_input, v);
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t r = lane; r < mw; r += kWave) {
+        const long long kk = skey[w][r];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < mw; ++j) rank += skey[w][j] < kk ? 1u : 0u;
+        e[rank] = sval[w][r];
+      }
+      __builtin_amdgcn_wave_barrier();
       continue;
     }
     for (uint32_t k0 = 0; k0 < mw; k0 += kWave) {
@@ -3888,6 +3948,7 @@ dem_status run_sort(const dem_contacts* c, int32_t n_tris, void* ws, const SortL
   hipLaunchKernelGGL(k_cs_local, dim3(L.n_blocks), dim3(kSortThreads), 0, st, a);
   hipLaunchKernelGGL(k_cs_scatter, g, b, 0, st, a);
   hipLaunchKernelGGL(k_cs_list, dim3(4096), b, 0, st, a);
+  hipLaunchKernelGGL(k_cs_small, g, b, 0, st, a);
   hipLaunchKernelGGL(k_cs_bucket, dim3(4096), b, 0, st, a);
   hipLaunchKernelGGL(k_cs_gather<T>, g, b, 0, st, a);
   hipLaunchKernelGGL(k_cs_write<T>, g, b, 0, st, a);
