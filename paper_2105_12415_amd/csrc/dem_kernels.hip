@@ -25,6 +25,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "dem.h"
 #include "dem_geom.hpp"
@@ -583,17 +584,54 @@ struct LdsQueue {
   uint32_t gbase;
 };
 
-template <typename R>
-__device__ __forceinline__ void lds_append(bool pred, R rec, R* buf, uint32_t* n) {
+// Slot of this lane in a wave-aggregated LDS append (valid where pred holds);
+// false when no lane of the wave appends.
+__device__ __forceinline__ bool lds_reserve(bool pred, uint32_t* n, uint32_t& slot) {
   unsigned long long m = __ballot(pred);
-  if (m == 0ull) return;
+  if (m == 0ull) return false;
   int leader = __ffsll((long long)m) - 1;
   uint32_t base = 0;
   if (lane_id() == leader) base = atomicAdd(n, (uint32_t)__popcll(m));
   // the leader's slot to every lane with a lane read (no LDS permute)
   base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
   unsigned long long lt = (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
-  if (pred) buf[base + (uint32_t)__popcll(m & lt)] = rec;
+  slot = base + (uint32_t)__popcll(m & lt);
+  return true;
+}
+
+template <typename R>
+__device__ __forceinline__ void lds_append(bool pred, R rec, R* buf, uint32_t* n) {
+  uint32_t slot;
+  if (lds_reserve(pred, n, slot) && pred) buf[slot] = rec;
+}
+
+// Work items staged in LDS in compact form: the first child of each side,
+// and both child counts (1..DEM_MAX_CHILDREN) as count - 1 in one byte's two
+// halves; 9 bytes per item instead of 16.
+template <int CAP>
+struct ItemStage {
+  int2 first[CAP];
+  uint8_t cnt[CAP];
+  uint32_t n;
+  uint32_t gbase;
+};
+
+__device__ __forceinline__ bool item_counts_ok(const int4& it) {
+  return (uint32_t)(it.y - 1) < (uint32_t)DEM_MAX_CHILDREN && (uint32_t)(it.w - 1) < (uint32_t)DEM_MAX_CHILDREN;
+}
+
+// Requires item_counts_ok(it) where pred holds.
+template <int CAP>
+__device__ __forceinline__ void item_append(bool pred, const int4& it, ItemStage<CAP>& q) {
+  uint32_t slot;
+  if (lds_reserve(pred, &q.n, slot) && pred) {
+    q.first[slot] = make_int2(it.x, it.z);
+    q.cnt[slot] = (uint8_t)(((it.y - 1) << 4) | (it.w - 1));
+  }
+}
+template <int CAP>
+__device__ __forceinline__ void item_append(bool pred, const int4& it, LdsQueue<int4, CAP>& q) {
+  lds_append(pred, it, q.buf, &q.n);
 }
 
 // Copy an LDS queue to global memory (whole block): one atomic on the tail of
@@ -614,6 +652,32 @@ __device__ __forceinline__ void lds_flush(LdsQueue<R, CAP>& q, uint32_t* tails, 
   __syncthreads();
   if (threadIdx.x == 0) q.n = 0;
   __syncthreads();
+}
+
+// lds_flush for a compact item stage: the items leave in their full form.
+template <int CAP>
+__device__ __forceinline__ void item_flush(ItemStage<CAP>& q, uint32_t* tails, int4* out, int64_t seg_cap,
+                                           uint32_t* status) {
+  const uint32_t x = blockIdx.x % kSeg;
+  if (threadIdx.x == 0) q.gbase = q.n ? atomicAdd(&tails[x], q.n) : 0u;
+  __syncthreads();
+  const uint32_t n = q.n, g = q.gbase;
+  int4* seg = out + (size_t)x * (size_t)seg_cap;
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
+    uint64_t slot = (uint64_t)g + k;
+    const int2 f = q.first[k];
+    const int c = q.cnt[k];
+    if (slot < (uint64_t)seg_cap) seg[slot] = make_int4(f.x, (c >> 4) + 1, f.y, (c & 15) + 1);
+    else atomicOr(status, DEM_DEV_QUEUE_OVERFLOW);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) q.n = 0;
+  __syncthreads();
+}
+template <int CAP>
+__device__ __forceinline__ void item_flush(LdsQueue<int4, CAP>& q, uint32_t* tails, int4* out, int64_t seg_cap,
+                                           uint32_t* status) {
+  lds_flush(q, tails, out, seg_cap, status, DEM_DEV_QUEUE_OVERFLOW);
 }
 
 // Consumer side of a segmented list: prefix of the segment fills.
@@ -647,16 +711,28 @@ constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between
 // Outcome of a frontier leaf in a step (byte 0 of its outcome word).
 constexpr uint32_t kOutPrune = 0, kOutKeep = 1, kOutUnfold = 2, kOutNear = 3;
 
-// LDS of the descent over one depth: one item per thread, stages of two
-// rounds; under 20 KB at BLOCK = 256 so that eight blocks fit in a CU's 160 KB.
-template <int BLOCK>
+// LDS of the descent over one depth: one item per thread, survivor stages
+// of two rounds (26.4 KB at BLOCK = 256: six blocks per CU, as many waves as
+// the registers allow within one; more waves measured no faster).
+// The deepest depth (LEAF) stages near pairs only, over four rounds between
+// checks.
+#ifndef DEM_LEVEL_ROUNDS
+#define DEM_LEVEL_ROUNDS 4
+#endif
+#ifndef DEM_LEAF_ROUNDS
+#define DEM_LEAF_ROUNDS 8
+#endif
+template <int BLOCK, bool LEAF = false>
 struct LevelShared {
+  static constexpr int kRounds = LEAF ? DEM_LEAF_ROUNDS : DEM_LEVEL_ROUNDS;  // evaluation rounds between stage checks
+  static constexpr int kCap = (kRounds + 1) * BLOCK;
   int4 items[BLOCK];
   int offs[BLOCK + 1];
   int wsum[16];
   uint8_t owner[BLOCK * 8];
-  LdsQueue<int4, 3 * BLOCK> qi;
-  LdsQueue<int2, 3 * BLOCK> qn;
+  std::conditional_t<LEAF, LdsQueue<int4, 1>,
+                     std::conditional_t<(kRounds > 2), ItemStage<kCap>, LdsQueue<int4, kCap>>> qi;
+  LdsQueue<int2, kCap> qn;
   SegView view;
   uint32_t claim;      // persistent descent: the next batch claimed by thread 0
   uint32_t claim_seg;  // persistent descent: the segment of that batch
@@ -672,10 +748,16 @@ struct LevelCounts {
 // take one child pair each, located through a block-wide scan of the items'
 // pair counts.  Survivors are staged in LDS and flushed to the block's own
 // segment of the next queue / the near list.
-template <typename T, int N, int BLOCK, bool HALF>
+//
+// LEAF: the deepest tree depth, where every record is a fine triangle (a
+// surrogate that reaches depth d sits on tree level d, and the deepest level
+// holds leaves only), so survivors go to the near list alone; a surrogate
+// survivor there means a malformed tree and sets DEM_DEV_BAD_TREE.
+template <typename T, int N, int BLOCK, bool HALF, bool LEAF = false>
 __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup, const LevelArgs& a,
-                                            LevelShared<BLOCK>& sh, uint32_t x, uint32_t first, int n,
+                                            LevelShared<BLOCK, LEAF>& sh, uint32_t x, uint32_t first, int n,
                                             LevelCounts& c) {
+  constexpr int kR = LevelShared<BLOCK, LEAF>::kRounds;
   const uint32_t bdim = blockDim.x;
   const int4* seg_items = a.qin + (size_t)x * (size_t)a.qcap + first;
   int np = 0, quad_item = 1;
@@ -761,30 +843,40 @@ __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup,
       bool fine = (cci == 0) && (ccj == 0);
       bool keep = a.dense ? true : !(L > delta + slack);
       ++c.evals;
-      // surrogate survivors unfold into the next depth's item (only the
-      // non-fine side unfolds); fine survivors go to the near list
-      push_item = keep && !fine;
       push_near = keep && fine;
-      // lazy flattening: a surviving surrogate with fine children has them
-      // written before the next depth (plain byte stores of the same value)
-      if (a.mark && push_item) {
-        if (kfi) a.mark[ci] = 1;
-        if (kfj) a.mark[cj] = 1;
-      }
-      nx.x = cci ? cbi : ci; nx.y = cci ? cci : 1;
-      nx.z = ccj ? cbj : cj; nx.w = ccj ? ccj : 1;
-      c.surv += push_item;
       c.near += push_near;
+      if constexpr (LEAF) {
+        if (keep && !fine) atomicOr(a.status, DEM_DEV_BAD_TREE);
+      } else {
+        // surrogate survivors unfold into the next depth's item (only the
+        // non-fine side unfolds); fine survivors go to the near list
+        push_item = keep && !fine;
+        // lazy flattening: a surviving surrogate with fine children has them
+        // written before the next depth (plain byte stores of the same value)
+        if (a.mark && push_item) {
+          if (kfi) a.mark[ci] = 1;
+          if (kfj) a.mark[cj] = 1;
+        }
+        nx.x = cci ? cbi : ci; nx.y = cci ? cci : 1;
+        nx.z = ccj ? cbj : cj; nx.w = ccj ? ccj : 1;
+        if (push_item && !item_counts_ok(nx)) {
+          atomicOr(a.status, DEM_DEV_BAD_TREE);  // malformed tree: drop the item
+          push_item = false;
+        }
+        c.surv += push_item;
+      }
     }
-    lds_append(push_item, nx, sh.qi.buf, &sh.qi.n);
+    if constexpr (!LEAF) item_append(push_item, nx, sh.qi);
     lds_append(push_near, make_int2(ci, cj), sh.qn.buf, &sh.qn.n);
-    // check the stages every second round and at the batch's end: after a
-    // check at most BLOCK entries remain, two rounds add at most 2 * bdim
-    if ((round & 1) || base + (int)bdim >= total) {
+    // check the stages every kR-th round and at the batch's end: after a
+    // check at most BLOCK entries remain, kR rounds add at most kR * bdim
+    if ((round & (kR - 1)) == kR - 1 || base + (int)bdim >= total) {
       __syncthreads();
-      if (sh.qi.n + 2 * bdim > (uint32_t)(3 * BLOCK))
-        lds_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
-      if (sh.qn.n + 2 * bdim > (uint32_t)(3 * BLOCK))
+      if constexpr (!LEAF) {
+        if (sh.qi.n + kR * bdim > (uint32_t)((kR + 1) * BLOCK))
+          item_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status);
+      }
+      if (sh.qn.n + kR * bdim > (uint32_t)((kR + 1) * BLOCK))
         lds_flush(sh.qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
     }
   }
@@ -793,10 +885,10 @@ __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup,
 
 // End of a depth for this block: the staged survivors leave, and the counts
 // reach the statistics (block sums into a partial, or one atomic per wave).
-template <int BLOCK>
-__device__ __forceinline__ void level_finish(const LevelArgs& a, LevelShared<BLOCK>& sh, LevelCounts& c) {
+template <int BLOCK, bool LEAF>
+__device__ __forceinline__ void level_finish(const LevelArgs& a, LevelShared<BLOCK, LEAF>& sh, LevelCounts& c) {
   __syncthreads();
-  lds_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status, DEM_DEV_QUEUE_OVERFLOW);
+  if constexpr (!LEAF) item_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status);
   lds_flush(sh.qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
   if (a.part) {
     unsigned long long v[3] = {c.evals, c.surv, c.near};
@@ -829,9 +921,9 @@ __device__ __forceinline__ void level_finish(const LevelArgs& a, LevelShared<BLO
 // XCD produced at the previous depth (hardware dispatches workgroups
 // round-robin over the 8 XCDs, so block b runs on XCD b % 8): a subtree of
 // the descent stays on one XCD, whose L2 already holds its triangles.
-template <typename T, int N, int BLOCK, bool HALF>
+template <typename T, int N, int BLOCK, bool HALF, bool LEAF = false>
 __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ soup, LevelArgs a) {
-  __shared__ LevelShared<BLOCK> sh;
+  __shared__ LevelShared<BLOCK, LEAF> sh;
   seg_view(sh.view, a.tail_in, a.qcap);
   LevelCounts c{0, 0, 0};
   if (threadIdx.x == 0) { sh.qi.n = 0; sh.qn.n = 0; }
@@ -840,7 +932,7 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
   const uint32_t per = gridDim.x / kSeg + ((blockIdx.x % kSeg) < (gridDim.x % kSeg) ? 1u : 0u);
   const uint32_t fill = sh.view.pre[x + 1] - sh.view.pre[x];
   for (uint32_t first = (blockIdx.x / kSeg) * batch; first < fill; first += per * batch)
-    level_batch<T, N, BLOCK, HALF>(soup, a, sh, x, first, (int)min(batch, fill - first), c);
+    level_batch<T, N, BLOCK, HALF, LEAF>(soup, a, sh, x, first, (int)min(batch, fill - first), c);
   level_finish(a, sh, c);
 }
 
@@ -3062,9 +3154,22 @@ void launch_level_b(int n_iter, dim3 g, hipStream_t st, const SoupRec<T>* soup, 
   launch_level_h<T, BLOCK, false>(n_iter, g, st, soup, la);
 }
 
+// The deepest depth's kernel without the surrogate-survivor path (256-thread
+// blocks, full-precision iteration; other shapes take the general kernel).
 template <typename T>
-void launch_level(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
-  if (b.x == 64) launch_level_b<T, 64>(n_iter, g, st, soup, la);
+void launch_level_leaf(int n_iter, dim3 g, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la) {
+  switch (n_iter) {
+#define DEM_CASE(N) case N: hipLaunchKernelGGL((k_level<T, N, 256, false, true>), g, dim3(256), 0, st, soup, la); break;
+    DEM_CASE(0) DEM_CASE(1) DEM_CASE(2) DEM_CASE(3) DEM_CASE(4) DEM_CASE(5) DEM_CASE(6) DEM_CASE(7) DEM_CASE(8)
+#undef DEM_CASE
+  }
+}
+
+template <typename T>
+void launch_level(int n_iter, dim3 g, dim3 b, hipStream_t st, const SoupRec<T>* soup, const LevelArgs& la,
+                  bool deepest = false) {
+  if (deepest && b.x == 256 && !la.half) launch_level_leaf<T>(n_iter, g, st, soup, la);
+  else if (b.x == 64) launch_level_b<T, 64>(n_iter, g, st, soup, la);
   else if (b.x == 128) launch_level_b<T, 128>(n_iter, g, st, soup, la);
   else launch_level_b<T, 256>(n_iter, g, st, soup, la);
 }
@@ -3222,7 +3327,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         la.mark = fa.lazy ? fa.mark : nullptr;
         la.half = s->precision == DEM_F32 && lev < p.half_depths;
         const int g = p.level_grid[lev] > 0 ? p.level_grid[lev] : grid;
-        launch_level<T>(p.n_iter, dim3(g), dim3(p.block), st, soup, la);
+        launch_level<T>(p.n_iter, dim3(g), dim3(p.block), st, soup, la, lev == s->n_levels_max - 1);
         mark();
         // lazy flattening: children of this depth's surviving parents
         const int f0 = fa.lazy ? s->fine_parent_begin[lev] : 0;
