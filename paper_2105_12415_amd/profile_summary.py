@@ -195,7 +195,11 @@ def summary_traffic(fetch_dir, write_dir, calib_fetch_dir, calib_write_dir, cali
               f"{w_scale:.3f} (write).", "",
               "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled MB read | scaled MB written | avg us (trace) | GB/s |",
               "|---|---|---|---|---|---|---|---|"]
+    # per family (the instantiations of one kernel, e.g. the deepest depth's
+    # variant of k_level beside the others): bytes per dispatch averaged
+    # over all of the family's dispatches
     per = OrderedDict()
+    tot = OrderedDict()
     for k in fetch:
         fr = fetch[k].get("FETCH_SIZE", 0.0)
         wr = write.get(k, {}).get("WRITE_SIZE", 0.0)
@@ -204,7 +208,13 @@ def summary_traffic(fetch_dir, write_dir, calib_fetch_dir, calib_write_dir, cali
         gbs = (rb + wb) / (us * 1e-6) / 1e9 if us else float("nan")
         lines.append(f"| `{k}` | {fetch[k]['dispatches']} | {fr:.4g} | {wr:.4g} | {rb / 1e6:.2f} | {wb / 1e6:.2f} | "
                      f"{us if us else float('nan'):.1f} | {gbs:.0f} |")
-        per[family(k)] = {"read_bytes": rb, "write_bytes": wb}
+        n = fetch[k]["dispatches"]
+        t = tot.setdefault(family(k), [0.0, 0.0, 0])
+        t[0] += rb * n
+        t[1] += wb * n
+        t[2] += n
+    for fam, (rsum, wsum, n) in tot.items():
+        per[fam] = {"read_bytes": rsum / n, "write_bytes": wsum / n}
     rec = {"source_sha256": sources_sha256(sources), "workload": workload, "launch": launch, "per_dispatch": per}
     lines += ["", "Machine-readable line (bench.py reports `roofline.traffic` from it only while the sha256 of "
               "dem_kernels.hip + dem_geom.hpp matches the source it runs):", "",
