@@ -68,7 +68,9 @@ typedef enum { DEM_MODE_FLAT = 0, DEM_MODE_HIER = 1 } dem_mode;
 #define DEM_DEV_QUEUE_OVERFLOW 0x2u   /* a level work queue exceeded queue_capacity */
 #define DEM_DEV_NEAR_OVERFLOW 0x4u    /* near-pair list exceeded near_capacity */
 #define DEM_DEV_NONFINITE 0x8u        /* a non-finite coordinate or distance was met */
-#define DEM_DEV_BAD_TREE 0x10u        /* a child count outside 0..DEM_MAX_CHILDREN */
+#define DEM_DEV_BAD_TREE 0x10u        /* a child count outside 0..DEM_MAX_CHILDREN, or a surrogate pair
+                                         surviving at depth n_levels_max - 1 (a tree deeper than
+                                         dem_scene.n_levels_max states: its pairs below were not tested) */
 #define DEM_DEV_FRONTIER_OVERFLOW 0x20u /* active sets outgrew dem_frontier's capacity or memory set */
 #define DEM_DEV_STALLED 0x40u         /* persistent descent: a grid barrier gave up waiting (results invalid) */
 

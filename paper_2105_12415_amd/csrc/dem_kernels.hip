@@ -570,6 +570,7 @@ struct LevelArgs {
   int batch;
   uint8_t* mark;             // lazy flattening: survival flags of surrogates (else null)
   int half;                  // this depth runs the Newton iteration in half precision
+  int deepest;               // the tree's deepest depth: a surrogate survivor there means a malformed tree
   IterParams ip;
 };
 
@@ -873,6 +874,7 @@ __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup,
     if ((round & (kR - 1)) == kR - 1 || base + (int)bdim >= total) {
       __syncthreads();
       if constexpr (!LEAF) {
+        if (a.deepest && sh.qi.n != 0u && threadIdx.x == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
         if (sh.qi.n + kR * bdim > (uint32_t)((kR + 1) * BLOCK))
           item_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status);
       }
@@ -1154,6 +1156,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(T) == 4 ? DEM_DESCENT_WAVES : 1)
     a.qout = (lev & 1) ? d.q0 : d.q1;
     a.tail_out = d.ctr->tail[lev + 1];
     a.depth = lev;
+    a.deepest = lev == d.n_levels - 1;
     a.batch = d.batch[lev];
     if (threadIdx.x == 0) { sh.qi.n = 0; sh.qn.n = 0; }
     if (HALF && lev < d.half_depths)
@@ -3323,6 +3326,7 @@ dem_status run_find(const dem_scene* s, const int32_t* pairs, int n_pairs, const
         la.qout = q[(lev + 1) & 1];
         la.tail_out = ctr->tail[lev + 1];
         la.depth = lev;
+        la.deepest = lev == s->n_levels_max - 1;
         la.batch = p.level_batch[lev] > 0 ? p.level_batch[lev] : p.batch_items;
         la.mark = fa.lazy ? fa.mark : nullptr;
         la.half = s->precision == DEM_F32 && lev < p.half_depths;

@@ -777,3 +777,24 @@ def test_deterministic_order_in_a_graph():
         got = eng.result()
         for f in ("pi", "pj", "ti", "tj", "d", "x", "n"):
             assert np.array_equal(got[f], ref[f]), (rep, f)
+
+
+def test_understated_depth_flags_bad_tree():
+    """A scene whose n_levels_max is one below its trees' depth: surrogate
+    pairs survive the last depth launched and their pairs below are never
+    tested, which the call must report (DEM_DEV_BAD_TREE) rather than return
+    a short contact set.  Checked for the deepest depth's own kernel variant
+    (256-thread blocks) and the general kernel (128-thread blocks)."""
+    scene = sg.two_spheres(3, [1, 2, 3], "f32", sep=2.03, stream_id=47, name="depth")
+    for block in (256, 128):
+        ds = api.DeviceScene(scene, device="cuda:0")
+        ok = api.ContactEngine(ds, api.make_params("hier", block=block))
+        ok.forward()
+        assert ok.check() == 0
+        assert ds.n_levels_max >= 2
+        ds.n_levels_max -= 1
+        ds._refresh()
+        eng = api.ContactEngine(ds, api.make_params("hier", block=block))
+        eng.forward()
+        say(f"[gpu-test] understated depth, block {block}: status {eng.check():#x}")
+        assert eng.check() & _abi.DEM_DEV_BAD_TREE
