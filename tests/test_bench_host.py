@@ -55,3 +55,33 @@ def test_step_roofline_weights_each_kernel_by_time():
     assert abs(r["kernels"]["k_level"]["frac"] - 0.5) < 1e-9
     assert abs(r["kernels"]["k_backward"]["frac"] - 0.25) < 1e-9
     assert abs(r["weighted_frac"] - (1.0 * 0.5 + 0.5 * 0.25) / 2.0) < 1e-9
+
+
+def _counter_csv(path, rows):
+    """A rocprofv3 counter_collection.csv with (dispatch, kernel, counter, value) rows."""
+    path.mkdir(parents=True, exist_ok=True)
+    lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    lines += [f'{d},"{k}",{c},{v}' for d, k, c, v in rows]
+    (path / "p_counter_collection.csv").write_text("\n".join(lines) + "\n")
+
+
+def test_traffic_summary_averages_a_kernel_family(tmp_path):
+    """Two instantiations of one kernel (one launch per depth, the deepest
+    depth in its own variant) give one per-dispatch figure: the family's
+    bytes over all of its dispatches, each scaled by the copy calibration."""
+    from paper_2105_12415_amd import profile_summary as ps
+    a = "void k_level<float, 4, 256, false, false>(SoupRec<float> const*, LevelArgs)"
+    b = "void k_level<float, 4, 256, false, true>(SoupRec<float> const*, LevelArgs)"
+    # five dispatches of a reading 10 KiB each, one of b reading 70 KiB; writes 1 and 7 KiB
+    _counter_csv(tmp_path / "fetch", [(i, a, "FETCH_SIZE", 10.0) for i in range(5)] + [(5, b, "FETCH_SIZE", 70.0)])
+    _counter_csv(tmp_path / "write", [(i, a, "WRITE_SIZE", 1.0) for i in range(5)] + [(5, b, "WRITE_SIZE", 7.0)])
+    # calibration: a 1 MiB copy reads 512 KiB by the counter (scale 2) and writes 1024 KiB (scale 1)
+    _counter_csv(tmp_path / "cf", [(0, "k_copy", "FETCH_SIZE", 512.0)])
+    _counter_csv(tmp_path / "cw", [(0, "k_copy", "WRITE_SIZE", 1024.0)])
+    text = ps.summary_traffic(str(tmp_path / "fetch"), str(tmp_path / "write"), str(tmp_path / "cf"),
+                              str(tmp_path / "cw"), 1 << 20, "w", ["cmd"], {"grid": 1})
+    rec = json.loads(text.split("traffic-json: ")[1])
+    fam = rec["per_dispatch"]["k_level"]
+    assert abs(fam["read_bytes"] - 2 * 1024 * (5 * 10.0 + 70.0) / 6) < 1e-6
+    assert abs(fam["write_bytes"] - 1024 * (5 * 1.0 + 7.0) / 6) < 1e-6
+    assert set(rec["per_dispatch"]) == {"k_level"}
