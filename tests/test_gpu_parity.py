@@ -798,3 +798,26 @@ def test_understated_depth_flags_bad_tree():
         eng.forward()
         say(f"[gpu-test] understated depth, block {block}: status {eng.check():#x}")
         assert eng.check() & _abi.DEM_DEV_BAD_TREE
+
+
+def test_deepest_depth_variant_matches_general_kernel():
+    """The deepest depth runs its own kernel variant (near pairs only, checks
+    every eighth round) with 256-thread blocks and the general kernel with
+    128-thread blocks: the same contacts with bit-identical distances and the
+    same evaluation and survivor counts at every depth."""
+    scene = sg.two_spheres(4, [1, 2, 3, 4], "f32", sep=2.03, stream_id=48, name="leaf")
+    out = {}
+    for block in (256, 128):
+        ds = api.DeviceScene(scene, device="cuda:0")
+        eng = api.ContactEngine(ds, api.make_params("hier", block=block))
+        assert eng.run() == 0
+        r = eng.result()
+        st = eng.stats_dict()
+        L = ds.n_levels_max
+        out[block] = ({(int(a), int(b)): float(d) for a, b, d in zip(r["ti"], r["tj"], r["d"])},
+                      np.asarray(st["evals"])[:L].tolist(), np.asarray(st["survivors"])[:L].tolist())
+        say(f"[gpu-test] deepest-depth variant, block {block}: {len(out[block][0])} contacts, "
+            f"evals {out[block][1]}")
+    assert len(out[256][0]) > 100
+    assert out[256][0] == out[128][0]
+    assert out[256][1] == out[128][1] and out[256][2] == out[128][2]
