@@ -606,34 +606,26 @@ __device__ __forceinline__ void lds_append(bool pred, R rec, R* buf, uint32_t* n
   if (lds_reserve(pred, n, slot) && pred) buf[slot] = rec;
 }
 
-// Work items staged in LDS in compact form: the first child of each side,
-// and both child counts (1..DEM_MAX_CHILDREN) as count - 1 in one byte's two
-// halves; 9 bytes per item instead of 16.
-template <int CAP>
-struct ItemStage {
-  int2 first[CAP];
-  uint8_t cnt[CAP];
-  uint32_t n;
-  uint32_t gbase;
-};
-
 __device__ __forceinline__ bool item_counts_ok(const int4& it) {
   return (uint32_t)(it.y - 1) < (uint32_t)DEM_MAX_CHILDREN && (uint32_t)(it.w - 1) < (uint32_t)DEM_MAX_CHILDREN;
 }
 
-// Requires item_counts_ok(it) where pred holds.
+// Survivor stage of the depths above the deepest.  In a round a lane
+// appends at most one entry, a surrogate item or a near pair, never both, so
+// the two lists share one pool: items from its front (first children as
+// int2, both child counts - 1 in one byte), near pairs from its back.
 template <int CAP>
-__device__ __forceinline__ void item_append(bool pred, const int4& it, ItemStage<CAP>& q) {
-  uint32_t slot;
-  if (lds_reserve(pred, &q.n, slot) && pred) {
-    q.first[slot] = make_int2(it.x, it.z);
-    q.cnt[slot] = (uint8_t)(((it.y - 1) << 4) | (it.w - 1));
-  }
-}
+struct SharedStage {
+  int2 pool[CAP];
+  uint8_t cnt[CAP];
+  uint32_t ni, nn;  // items, near pairs
+  uint32_t gi, gn;  // global bases of a flush
+};
+
 template <int CAP>
-__device__ __forceinline__ void item_append(bool pred, const int4& it, LdsQueue<int4, CAP>& q) {
-  lds_append(pred, it, q.buf, &q.n);
-}
+__device__ __forceinline__ void stage_reset(SharedStage<CAP>& q) { q.ni = 0; q.nn = 0; }
+template <typename R, int CAP>
+__device__ __forceinline__ void stage_reset(LdsQueue<R, CAP>& q) { q.n = 0; }
 
 // Copy an LDS queue to global memory (whole block): one atomic on the tail of
 // this block's segment reserves the range.  seg_cap = entries per segment.
@@ -655,30 +647,35 @@ __device__ __forceinline__ void lds_flush(LdsQueue<R, CAP>& q, uint32_t* tails, 
   __syncthreads();
 }
 
-// lds_flush for a compact item stage: the items leave in their full form.
+// Both lists of a shared stage to their segments of the next queue and of
+// the near list (one atomic on each tail), then empty.
 template <int CAP>
-__device__ __forceinline__ void item_flush(ItemStage<CAP>& q, uint32_t* tails, int4* out, int64_t seg_cap,
-                                           uint32_t* status) {
+__device__ __forceinline__ void shared_flush(SharedStage<CAP>& q, uint32_t* qtails, int4* qout, int64_t qcap,
+                                             uint32_t* ntails, int2* nout, int64_t ncap, uint32_t* status) {
   const uint32_t x = blockIdx.x % kSeg;
-  if (threadIdx.x == 0) q.gbase = q.n ? atomicAdd(&tails[x], q.n) : 0u;
-  __syncthreads();
-  const uint32_t n = q.n, g = q.gbase;
-  int4* seg = out + (size_t)x * (size_t)seg_cap;
-  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) {
-    uint64_t slot = (uint64_t)g + k;
-    const int2 f = q.first[k];
-    const int c = q.cnt[k];
-    if (slot < (uint64_t)seg_cap) seg[slot] = make_int4(f.x, (c >> 4) + 1, f.y, (c & 15) + 1);
-    else atomicOr(status, DEM_DEV_QUEUE_OVERFLOW);
+  if (threadIdx.x == 0) {
+    q.gi = q.ni ? atomicAdd(&qtails[x], q.ni) : 0u;
+    q.gn = q.nn ? atomicAdd(&ntails[x], q.nn) : 0u;
   }
   __syncthreads();
-  if (threadIdx.x == 0) q.n = 0;
+  const uint32_t ni = q.ni, nn = q.nn, gi = q.gi, gn = q.gn;
+  int4* qseg = qout + (size_t)x * (size_t)qcap;
+  int2* nseg = nout + (size_t)x * (size_t)ncap;
+  for (uint32_t k = threadIdx.x; k < ni; k += blockDim.x) {
+    const uint64_t slot = (uint64_t)gi + k;
+    const int2 f = q.pool[k];
+    const int c = q.cnt[k];
+    if (slot < (uint64_t)qcap) qseg[slot] = make_int4(f.x, (c >> 4) + 1, f.y, (c & 15) + 1);
+    else atomicOr(status, DEM_DEV_QUEUE_OVERFLOW);
+  }
+  for (uint32_t k = threadIdx.x; k < nn; k += blockDim.x) {
+    const uint64_t slot = (uint64_t)gn + k;
+    if (slot < (uint64_t)ncap) nseg[slot] = q.pool[CAP - 1 - k];
+    else atomicOr(status, DEM_DEV_NEAR_OVERFLOW);
+  }
   __syncthreads();
-}
-template <int CAP>
-__device__ __forceinline__ void item_flush(LdsQueue<int4, CAP>& q, uint32_t* tails, int4* out, int64_t seg_cap,
-                                           uint32_t* status) {
-  lds_flush(q, tails, out, seg_cap, status, DEM_DEV_QUEUE_OVERFLOW);
+  if (threadIdx.x == 0) { q.ni = 0; q.nn = 0; }
+  __syncthreads();
 }
 
 // Consumer side of a segmented list: prefix of the segment fills.
@@ -712,13 +709,13 @@ constexpr int kStageFlat = 2048;  // >= 4 evaluation rounds of 256 lanes between
 // Outcome of a frontier leaf in a step (byte 0 of its outcome word).
 constexpr uint32_t kOutPrune = 0, kOutKeep = 1, kOutUnfold = 2, kOutNear = 3;
 
-// LDS of the descent over one depth: one item per thread, survivor stages
-// of two rounds (26.4 KB at BLOCK = 256: six blocks per CU, as many waves as
-// the registers allow within one; more waves measured no faster).
-// The deepest depth (LEAF) stages near pairs only, over four rounds between
-// checks.
+// LDS of the descent over one depth: one item per thread, and a survivor
+// stage for kRounds evaluation rounds between stage checks (each check is a
+// block barrier; fewer checks measured faster than more waves per SIMD).
+// At BLOCK = 256: 28.7 KB above the deepest depth (the shared stage, five
+// blocks per CU), 26.4 KB at the deepest (near pairs only, six blocks).
 #ifndef DEM_LEVEL_ROUNDS
-#define DEM_LEVEL_ROUNDS 4
+#define DEM_LEVEL_ROUNDS 8
 #endif
 #ifndef DEM_LEAF_ROUNDS
 #define DEM_LEAF_ROUNDS 8
@@ -731,9 +728,8 @@ struct LevelShared {
   int offs[BLOCK + 1];
   int wsum[16];
   uint8_t owner[BLOCK * 8];
-  std::conditional_t<LEAF, LdsQueue<int4, 1>,
-                     std::conditional_t<(kRounds > 2), ItemStage<kCap>, LdsQueue<int4, kCap>>> qi;
-  LdsQueue<int2, kCap> qn;
+  // the deepest depth stages near pairs only
+  std::conditional_t<LEAF, LdsQueue<int2, kCap>, SharedStage<kCap>> st;
   SegView view;
   uint32_t claim;      // persistent descent: the next batch claimed by thread 0
   uint32_t claim_seg;  // persistent descent: the segment of that batch
@@ -867,19 +863,29 @@ __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup,
         c.surv += push_item;
       }
     }
-    if constexpr (!LEAF) item_append(push_item, nx, sh.qi);
-    lds_append(push_near, make_int2(ci, cj), sh.qn.buf, &sh.qn.n);
+    if constexpr (LEAF) {
+      lds_append(push_near, make_int2(ci, cj), sh.st.buf, &sh.st.n);
+    } else {
+      uint32_t slot;
+      if (lds_reserve(push_item, &sh.st.ni, slot) && push_item) {
+        sh.st.pool[slot] = make_int2(nx.x, nx.z);
+        sh.st.cnt[slot] = (uint8_t)(((nx.y - 1) << 4) | (nx.w - 1));
+      }
+      if (lds_reserve(push_near, &sh.st.nn, slot) && push_near) sh.st.pool[sh.kCap - 1 - slot] = make_int2(ci, cj);
+    }
     // check the stages every kR-th round and at the batch's end: after a
     // check at most BLOCK entries remain, kR rounds add at most kR * bdim
     if ((round & (kR - 1)) == kR - 1 || base + (int)bdim >= total) {
       __syncthreads();
-      if constexpr (!LEAF) {
-        if (a.deepest && sh.qi.n != 0u && threadIdx.x == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
-        if (sh.qi.n + kR * bdim > (uint32_t)((kR + 1) * BLOCK))
-          item_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status);
+      if constexpr (LEAF) {
+        if (sh.st.n + kR * bdim > (uint32_t)sh.kCap)
+          lds_flush(sh.st, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+      } else {
+        // (both lists together: after a check at most BLOCK entries remain)
+        if (a.deepest && sh.st.ni != 0u && threadIdx.x == 0) atomicOr(a.status, DEM_DEV_BAD_TREE);
+        if (sh.st.ni + sh.st.nn + kR * bdim > (uint32_t)sh.kCap)
+          shared_flush(sh.st, a.tail_out, a.qout, a.qcap, a.near_tail, a.near_, a.ncap, a.status);
       }
-      if (sh.qn.n + kR * bdim > (uint32_t)((kR + 1) * BLOCK))
-        lds_flush(sh.qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
     }
   }
   __syncthreads();
@@ -890,8 +896,8 @@ __device__ __forceinline__ void level_batch(const SoupRec<T>* __restrict__ soup,
 template <int BLOCK, bool LEAF>
 __device__ __forceinline__ void level_finish(const LevelArgs& a, LevelShared<BLOCK, LEAF>& sh, LevelCounts& c) {
   __syncthreads();
-  if constexpr (!LEAF) item_flush(sh.qi, a.tail_out, a.qout, a.qcap, a.status);
-  lds_flush(sh.qn, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+  if constexpr (LEAF) lds_flush(sh.st, a.near_tail, a.near_, a.ncap, a.status, DEM_DEV_NEAR_OVERFLOW);
+  else shared_flush(sh.st, a.tail_out, a.qout, a.qcap, a.near_tail, a.near_, a.ncap, a.status);
   if (a.part) {
     unsigned long long v[3] = {c.evals, c.surv, c.near};
     block_sums(v);
@@ -928,7 +934,7 @@ __global__ void __launch_bounds__(BLOCK) k_level(const SoupRec<T>* __restrict__ 
   __shared__ LevelShared<BLOCK, LEAF> sh;
   seg_view(sh.view, a.tail_in, a.qcap);
   LevelCounts c{0, 0, 0};
-  if (threadIdx.x == 0) { sh.qi.n = 0; sh.qn.n = 0; }
+  if (threadIdx.x == 0) stage_reset(sh.st);
   const uint32_t batch = (uint32_t)a.batch;
   const uint32_t x = blockIdx.x % kSeg;
   const uint32_t per = gridDim.x / kSeg + ((blockIdx.x % kSeg) < (gridDim.x % kSeg) ? 1u : 0u);
@@ -1158,7 +1164,7 @@ __global__ void __launch_bounds__(BLOCK, sizeof(T) == 4 ? DEM_DESCENT_WAVES : 1)
     a.depth = lev;
     a.deepest = lev == d.n_levels - 1;
     a.batch = d.batch[lev];
-    if (threadIdx.x == 0) { sh.qi.n = 0; sh.qn.n = 0; }
+    if (threadIdx.x == 0) stage_reset(sh.st);
     if (HALF && lev < d.half_depths)
       level_dynamic<T, N, BLOCK, HALF>(soup, a, sh, d.ctr->claim[lev], c);
     else
